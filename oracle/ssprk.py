@@ -1,0 +1,22 @@
+"""Three-stage, third-order strong-stability-preserving Runge-Kutta (oracle).
+
+The paper integrates with SSPRK43 and other explicit schemes (Sec. Results);
+the workloads fix the Shu-Osher SSPRK3 at a constant time step:
+
+  u1 = u + dt L(u, t)
+  u2 = 3/4 u + 1/4 (u1 + dt L(u1, t + dt))
+  u  = 1/3 u + 2/3 (u2 + dt L(u2, t + dt/2))
+"""
+
+
+def step(L, u, t, dt):
+    u1 = u + dt * L(u, t)
+    u2 = 0.75 * u + 0.25 * (u1 + dt * L(u1, t + dt))
+    return u / 3.0 + 2.0 / 3.0 * (u2 + dt * L(u2, t + 0.5 * dt))
+
+
+def run(L, u, t, dt, nsteps):
+    for _ in range(nsteps):
+        u = step(L, u, t, dt)
+        t += dt
+    return u, t

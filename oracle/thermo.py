@@ -1,0 +1,116 @@
+"""RRHO mixture thermodynamics and the T(e) Newton solve (oracle).
+
+Paper: Appendix, Thermodynamics, Eqs. Internal_energy, trans_energ,
+rot_energ, vib_energ, elec_energ; Governing Equations, Eqs.
+internal_energies and eos (Dalton's law p = sum rho_s R_s T).
+
+e_s(T) = 3/2 R_s T  (+ L_s/2 R_s T + R_s theta_v/(exp(theta_v/T) - 1) for
+molecules) + e_s^0, with L_s = 2 for the linear diatomics.
+
+Readings:
+* the electronic mode has no level data in the paper; it is dropped
+  (e_e = 0, ground-state degeneracy only);
+* the paper asks for iterative T(e) at least cost but does not give the
+  iteration: Newton on f(T) = sum rho_s e_s(T) - rho e with
+  f' = sum rho_s cv_s(T) > 0, stopped when |dT| <= tol * T.
+* the frozen sound speed a_f = sqrt(gamma_f p / rho),
+  gamma_f = 1 + sum rho_s R_s / sum rho_s cv_s, is used in the Lax-Friedrichs
+  dissipation.
+"""
+import numpy as np
+
+
+class Mixture:
+    def __init__(self, sp):
+        self.sp = sp
+        self.Rs = sp.Ru / sp.W
+        self.mol = sp.molecule.astype(bool)
+        self.th = sp.theta_v
+        self.e0 = sp.e0
+        self.ns = len(sp.W)
+
+    def _col(self, a, nd):
+        return a.reshape((-1,) + (1,) * nd)
+
+    def e_species(self, T):
+        """Specific energies e_s(T), shape (ns,) + T.shape."""
+        nd = np.ndim(T)
+        R = self._col(self.Rs, nd)
+        e = 1.5 * R * T + self._col(self.e0, nd)
+        out = np.array(np.broadcast_to(e, (self.ns,) + np.shape(T)))
+        for s in range(self.ns):
+            if self.mol[s]:
+                x = self.th[s] / T
+                out[s] = out[s] + self.Rs[s] * T + self.Rs[s] * self.th[s] / np.expm1(x)
+        return out
+
+    def cv_species(self, T):
+        nd = np.ndim(T)
+        out = np.array(np.broadcast_to(1.5 * self._col(self.Rs, nd), (self.ns,) + np.shape(T)))
+        for s in range(self.ns):
+            if self.mol[s]:
+                x = self.th[s] / T
+                ex = np.exp(x)
+                out[s] = out[s] + self.Rs[s] + self.Rs[s] * x * x * ex / (ex - 1.0) ** 2
+        return out
+
+    def rho_e(self, rs, T):
+        """sum_s rho_s e_s(T)."""
+        return np.sum(rs * self.e_species(T), axis=0)
+
+    def rho_cv(self, rs, T):
+        return np.sum(rs * self.cv_species(T), axis=0)
+
+    def solve_T(self, rs, rhoe, T0, tol=1e-10, maxit=50):
+        """Per-node Newton iteration; every node stops on its own test.
+
+        Returns T and the iteration count per node; raises if any node
+        fails to converge within maxit.
+        """
+        T = np.array(np.broadcast_to(T0, np.shape(rhoe)), float)
+        it = np.zeros(np.shape(rhoe), np.int64)
+        active = np.ones(np.shape(rhoe), bool)
+        for _ in range(maxit):
+            if not active.any():
+                break
+            Ta = T[active]
+            rsa = rs[:, active]
+            f = self.rho_e(rsa, Ta) - rhoe[active]
+            fp = self.rho_cv(rsa, Ta)
+            dT = f / fp
+            Tn = Ta - dT
+            T[active] = Tn
+            it[active] += 1
+            done = np.abs(dT) <= tol * np.abs(Tn)
+            idx = np.flatnonzero(active)
+            active[idx[done]] = False
+        if active.any():
+            raise RuntimeError("Newton for T(e) did not converge")
+        return T, it
+
+    def pressure(self, rs, T):
+        return np.sum(rs * self.Rs.reshape((-1,) + (1,) * np.ndim(T)), axis=0) * T
+
+    def sound_speed(self, rs, T):
+        nd = np.ndim(T)
+        rho = rs.sum(0)
+        rR = np.sum(rs * self._col(self.Rs, nd), axis=0)
+        gam = 1.0 + rR / self.rho_cv(rs, T)
+        return np.sqrt(gam * rR * T / rho)
+
+    def state(self, u, dim, T):
+        """Mixture flux state from conserved u and a converged T."""
+        rs = u[:self.ns]
+        rho = rs.sum(0)
+        v = u[self.ns:self.ns + dim] / rho
+        rhoE = u[self.ns + dim]
+        p = self.pressure(rs, T)
+        c = self.sound_speed(rs, T)
+        return dict(rho=rho, rs=rs, v=v, p=p, rhoE=rhoE, c=c, T=T, mix=True)
+
+    def temperature(self, u, dim, T0, tol=1e-10, maxit=50):
+        rs = u[:self.ns]
+        rho = rs.sum(0)
+        m = u[self.ns:self.ns + dim]
+        rhoe = u[self.ns + dim] - 0.5 * np.sum(m * m, axis=0) / rho
+        return self.solve_T(rs, rhoe, T0, tol, maxit)

@@ -1,0 +1,158 @@
+"""Pins of the oracle's semi-discrete operator: free-stream, conservation,
+entropy conservation, metric identities, convergence, viscous dissipation."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2511_17551_amd import workloads as W
+from oracle import gas, ssprk
+from oracle.dgsem import Operator
+from oracle.geometry import tensor, flat, ref_deriv
+
+
+def quad_weights(op):
+    w = op.b.w
+    if op.dim == 2:
+        return np.outer(w, w).reshape(-1)
+    return np.einsum("i,j,k->kji", w, w, w).reshape(-1)
+
+
+def test_metric_identities_curved():
+    c = W.curved_periodic_case(n=2, N=4)
+    op = Operator(c.cfg, c.mesh)
+    n1 = op.b.n1
+    for comp in range(3):
+        s = sum(ref_deriv(tensor(op.Ja[d, comp], 3, n1), op.b.D, d, 3) for d in range(3))
+        assert np.abs(s).max() < 1e-13 * np.abs(op.Ja).max()
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.5, 1.0])
+@pytest.mark.parametrize("N", [3, 4])
+def test_freestream_curved(alpha, N):
+    c = W.curved_periodic_case(n=2, N=N, shock=True, force_alpha=alpha)
+    op = Operator(c.cfg, c.mesh)
+    u = np.empty_like(c.u0)
+    rho, v, p = 1.3, np.array([0.4, -0.7, 0.2]), 2.1
+    u[0] = rho
+    u[1:4] = (rho * v)[:, None, None]
+    u[4] = p / 0.4 + 0.5 * rho * (v @ v)
+    du = op.rhs(u)
+    # per-variable scale S_v = max_n sum_d |f_v(u0)| |Ja^d_n| / J_n
+    f = np.array([rho, rho * v[0] + p, rho * v[1] + p, rho * v[2] + p,
+                  (u[4, 0, 0] + p)]) * np.abs(v).max()
+    f[1:4] += p
+    S = f * (sum(np.sqrt((op.Ja[d] ** 2).sum(0)) for d in range(3)) / op.J).max()
+    assert np.all(np.abs(du).max(axis=(1, 2)) < 1e-12 * S)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.3, 1.0])
+def test_conservation_curved(alpha):
+    c = W.curved_periodic_case(n=2, N=3, shock=True, force_alpha=alpha)
+    op = Operator(c.cfg, c.mesh)
+    du = op.rhs(c.u0)
+    wq = quad_weights(op)
+    tot = (du * op.J[None] * wq).sum(axis=(1, 2))
+    scale = np.abs(du * op.J[None] * wq).sum(axis=(1, 2))
+    assert np.all(np.abs(tot) < 1e-13 * scale)
+
+
+def test_entropy_conservation_ec_surface():
+    for c in (W.case_c1(n=6, surface_flux=W.SF_RANOCHA),
+              W.curved_periodic_case(n=2, N=3, surface_flux=W.SF_RANOCHA)):
+        op = Operator(c.cfg, c.mesh)
+        du = op.rhs(c.u0)
+        s = gas.pg_state(c.u0, op.dim, 1.4)
+        w = gas.entropy_variables(s)
+        prod = w * du * op.J[None] * quad_weights(op)
+        assert abs(prod.sum()) < 1e-13 * np.abs(prod).sum()
+
+
+def test_entropy_dissipation_rusanov_and_fv():
+    """Rusanov faces and the FV subcells only remove entropy (jumps make it strict)."""
+    for alpha in (0.0, 1.0):
+        c = W.curved_periodic_case(n=2, N=3, shock=True, force_alpha=alpha)
+        op = Operator(c.cfg, c.mesh)
+        rng = np.random.default_rng(5)
+        u = c.u0 * (1.0 + 0.02 * rng.uniform(-1, 1, (1, c.u0.shape[1], 1)))
+        du = op.rhs(u)
+        w = gas.entropy_variables(gas.pg_state(u, 3, 1.4))
+        prod = (w * du * op.J[None] * quad_weights(op)).sum()
+        assert prod < -1e-6
+
+
+def test_telescoped_equals_diagonal_free_split_form():
+    """(Fbar_{n+1} - Fbar_n)/w_n == sum_{j != n} 2 D_nj F#(u_n, u_j)."""
+    c = W.curved_periodic_case(n=2, N=4)
+    op = Operator(c.cfg, c.mesh)
+    s = gas.pg_state(c.u0, 3, 1.4)
+    G = op.volume_terms(s, np.zeros(op.mesh.nelem))
+    from oracle.geometry import line_view, line_unview
+    n1 = op.b.n1
+    ref = np.zeros_like(G)
+    for d in range(3):
+        sl = {k: (line_view(v, d, 3, n1) if isinstance(v, np.ndarray) else v) for k, v in s.items()}
+        Jl = line_view(op.Ja[d], d, 3, n1)
+        acc = np.zeros((5,) + Jl.shape[1:])
+        for nn in range(n1):
+            for j in range(n1):
+                if j != nn:
+                    f = gas.ranocha(gas.take(sl, nn), gas.take(sl, j), 0.5 * (Jl[..., nn] + Jl[..., j]))
+                    acc[..., nn] += 2 * op.b.D[nn, j] * f
+        ref += line_unview(acc, d, 3, n1)
+    assert np.abs(G - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_vortex_convergence():
+    """Advected isentropic vortex: max error of rho falls faster than h^3 (N = 3)."""
+    errs = []
+    T = 0.2
+    for n in (24, 48):
+        c = W.case_c1(n=n, N=3, length=14.0)
+        op = Operator(c.cfg, c.mesh)
+        h = 14.0 / n
+        steps = int(math.ceil(T / (0.01 * h)))
+        dt = T / steps
+        u, _ = ssprk.run(lambda v, t: op.rhs(v, t), c.u0, 0.0, dt, steps)
+        rho, vel, p = W.isentropic_vortex(c.mesh.x[0] - T, c.mesh.x[1] - T, xc=7.0, yc=7.0)
+        errs.append(np.abs(u[0] - rho).max())
+    eoc = math.log(errs[0] / errs[1], 2)
+    assert eoc > 3.0, (errs, eoc)
+
+
+def test_tgv_initial_dissipation():
+    """-dKE/dt(0) = mu <|omega|^2> = 3 mu / 4 for the TGV (closed form)."""
+    c = W.case_c2(n=8)
+    op = Operator(c.cfg, c.mesh)
+    du = op.rhs(c.u0)
+    u = c.u0
+    v = u[1:4] / u[0]
+    dke = (v * du[1:4]).sum(0) - 0.5 * (v * v).sum(0) * du[0]
+    wq = quad_weights(op)
+    rate = (dke * op.J * wq).sum() / (op.J * wq).sum()
+    mu = c.cfg["mu"]
+    assert abs(rate + 0.75 * mu) < 1e-5 * 0.75 * mu
+
+
+def test_br1_uniform_flow_and_linear_gradient():
+    c = W.case_c2(n=3)
+    op = Operator(c.cfg, c.mesh)
+    u = np.empty_like(c.u0)
+    u[0] = 1.0
+    u[1:4] = np.array([0.3, -0.2, 0.1])[:, None, None]
+    u[4] = 50.0 + 0.5 * 0.14
+    from oracle.br1 import viscous_rhs, gradients, primitives
+    s = gas.pg_state(u, 3, 1.4)
+    assert np.abs(viscous_rhs(op, u, s)).max() < 1e-12
+    # gradient of a field that is periodic and degree <= N per element is exact:
+    # a single Fourier mode is not, but its error must be small and shrink.
+    x = c.mesh.x
+    W_ = np.stack([np.sin(x[0]), np.cos(x[1]), np.sin(x[2]), np.cos(x[0] + x[1])])
+    q = gradients(op, W_)
+    exact = np.zeros_like(q)
+    exact[0, 0] = np.cos(x[0])
+    exact[1, 1] = -np.sin(x[1])
+    exact[2, 2] = np.cos(x[2])
+    exact[0, 3] = -np.sin(x[0] + x[1])
+    exact[1, 3] = -np.sin(x[0] + x[1])
+    assert np.abs(q - exact).max() < 0.1
