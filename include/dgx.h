@@ -1,0 +1,235 @@
+/*
+ * dgx — semi-discrete entropy-stable DGSEM right-hand side on one AMD MI355X.
+ *
+ * C ABI of libdgx.so.  Every call takes plain pointers and sizes; no C++ or
+ * PyTorch type crosses this boundary.  The operation computed is the
+ * semi-discrete operator of arXiv 2511.17551 (H3PC), Sec. Methodology:
+ *
+ *   du/dt = -(1/J) sum_d { (1/w) Delta[(1-alpha) Fbar^d + alpha F^{FV,d}]
+ *                          + surface Riemann fluxes }  + viscous terms + S
+ *
+ * (Eqs. strong_form, fluxes_discrete_fluxdifferencing, DGvec,
+ * fluxes_discrete_with_fv, finitevolumeflux, riemann_problem1-3, auxil,
+ * auxstrongf; thermochemistry from the Appendix, Eqs. Internal_energy ..
+ * calc_prod).
+ *
+ * Conventions shared by every entry point
+ *   Layout   state arrays u, du are device FP64 structure-of-arrays
+ *            [nvar][nelem][(N+1)^dim], node n = i + (N+1)(j + (N+1)k), i along
+ *            the first reference direction.  Variables: perfect gas
+ *            (rho, rho v_1..rho v_dim, rho E); mixture (rho_N2, rho_O2,
+ *            rho_NO, rho_N, rho_O, rho v_1..rho v_dim, rho E).
+ *   Memory   the caller owns u, du, T, p (device memory, 8-byte aligned,
+ *            contiguous).  The library owns everything it allocates (geometry,
+ *            connectivity, stage buffers, graphs, surrogate weights) and frees
+ *            it in dgx_destroy.
+ *   Streams  calls enqueue on the caller's hipStream_t (NULL = legacy default
+ *            stream).  Only calls documented as synchronising wait.
+ *   Errors   0 on success or a negative DGX_E_* code.  DGX_E_INVAL is returned
+ *            before anything is enqueued.  Device-side errors (non-physical
+ *            states, Newton non-convergence) are sticky flags reported by the
+ *            next synchronising call.  dgx_last_error() gives the text.  No
+ *            call aborts the process and no C++ exception leaves the library.
+ *   Threads  one context per host thread; contexts are independent.
+ */
+#ifndef DGX_H
+#define DGX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define DGX_OK 0
+#define DGX_E_INVAL (-1)        /* bad argument, checked before any launch   */
+#define DGX_E_NOMEM (-2)        /* device or host allocation failed           */
+#define DGX_E_DEVICE (-3)       /* a HIP runtime call failed                   */
+#define DGX_E_NONPHYSICAL (-4)  /* non-finite value, rho_s < 0 or p <= 0       */
+#define DGX_E_NOCONV (-5)       /* T(e) Newton exceeded its iteration limit    */
+#define DGX_E_STATE (-6)        /* call out of order (e.g. rhs before mesh)    */
+
+/* equation systems (Sec. Governing Equations) */
+#define DGX_EQ_EULER 0      /* calorically perfect gas, inviscid               */
+#define DGX_EQ_NS 1         /* perfect gas, BR1 viscous terms, const. mu       */
+#define DGX_EQ_EULER_MIX 2  /* 5-species air, RRHO energies, frozen chemistry  */
+#define DGX_EQ_REACT_MIX 3  /* 5-species air, RRHO energies, Arrhenius sources */
+
+/* two-point volume fluxes (Eq. fluxdiffcons) */
+#define DGX_VF_RANOCHA 0    /* entropy-conservative (perfect gas only) */
+#define DGX_VF_DUCROS 1     /* Ducros split form                       */
+/* surface fluxes (Eqs. riemann_problem1-3) */
+#define DGX_SF_RUSANOV 0    /* local Lax-Friedrichs                     */
+#define DGX_SF_RANOCHA 1    /* EC flux at faces (entropy checks)        */
+/* boundary kinds (weak, through the surface flux with an external state) */
+#define DGX_BC_DIRICHLET 0
+#define DGX_BC_OUTFLOW 1
+#define DGX_BC_SLIPWALL 2
+/* shock-indicator quantity */
+#define DGX_IND_RHO_P 0
+#define DGX_IND_P 1
+/* initial guess of the T(e) Newton solve */
+#define DGX_GUESS_FREESTREAM 0
+#define DGX_GUESS_SURROGATE 1
+
+/* Species data of the 5-species mixture (Appendix, Thermodynamics and
+ * Chemical Kinetics).  Order N2, O2, NO, N, O.  SI units; e0 in J/kg. */
+typedef struct dgx_species {
+    int nspecies;          /* must be 5 */
+    int molecule[5];       /* 1 = linear diatomic (rotation + vibration)   */
+    double W[5];           /* molar mass, kg/mol                            */
+    double theta_v[5];     /* vibrational temperature, K                    */
+    double theta_r[5];     /* rotational temperature, K                     */
+    double sigma[5];       /* symmetry (steric) factor                      */
+    double Qe[5];          /* electronic partition function (constant)      */
+    double e0[5];          /* formation energy, J/kg                        */
+    double Ru, NA, hP;     /* gas constant, Avogadro, Planck                */
+    double p_ref;          /* reference pressure of K_eq, Pa                */
+} dgx_species;
+
+/* Reaction table (Eq. chemreact, forward_rate): host arrays, copied. */
+typedef struct dgx_reactions {
+    int nreactions;        /* 1..32 */
+    const double *A;       /* [nr] m^3 mol^-1 s^-1 (bimolecular forward)    */
+    const double *b;       /* [nr] temperature exponent                     */
+    const double *theta_a; /* [nr] activation temperature E/R_u, K          */
+    const int32_t *nu;     /* [nr][5] reactant stoichiometry                */
+    const int32_t *nup;    /* [nr][5] product stoichiometry                 */
+} dgx_reactions;
+
+typedef struct dgx_config {
+    int dim;               /* 2 or 3 */
+    int N;                 /* polynomial degree: 3 or 4 */
+    int equation;          /* DGX_EQ_* */
+    int volume_flux;       /* DGX_VF_* */
+    int surface_flux;      /* DGX_SF_* */
+    double gamma, R;       /* perfect gas */
+    double mu, Pr;         /* DGX_EQ_NS */
+    int shock;             /* 1 = modal indicator + subcell FV blending */
+    double alpha_max, alpha_min;
+    int ind_var;           /* DGX_IND_* */
+    int alpha_smooth;      /* 1 = alpha <- max(alpha, alpha_nbr / 2) */
+    double force_alpha;    /* >= 0: use this alpha everywhere (testing) */
+    double newton_tol;     /* relative step tolerance of T(e) */
+    int newton_maxit;
+    double T_guess;        /* freestream guess of T(e) */
+    const dgx_species *species;      /* mixture equations, else NULL */
+    const dgx_reactions *reactions;  /* DGX_EQ_REACT_MIX, else NULL  */
+} dgx_config;
+
+/* Mesh (host arrays, copied by dgx_set_mesh).  Conforming face row
+ * (eL, fL, eR, fR): the +d face of eL (fL = 2d+1) meets the -d face of eR
+ * (fR = 2d) with aligned tangential node order.  Boundary row (e, f, bc).
+ * Mortar row (eL, fL, eS[0..m-1], fS) with m = 2^(dim-1): the large face fL
+ * of eL meets the faces fS of the small elements; sub-face s = a + 2b covers
+ * the lower/upper half of each tangential direction.  One mesh may hold
+ * several independent cases (batched execution): cases never share faces. */
+typedef struct dgx_mesh {
+    int nelem;
+    const double *x;          /* [dim][nelem][(N+1)^dim] nodal coordinates   */
+    int nface;
+    const int32_t *faces;     /* [nface][4]   */
+    int nbface;
+    const int32_t *bfaces;    /* [nbface][3]  */
+    int nmortar;
+    const int32_t *mortars;   /* [nmortar][3 + 2^(dim-1)] */
+    int nbc;
+    const int32_t *bc_kind;   /* [nbc] DGX_BC_*           */
+    const double *bc_state;   /* [nbc][nvar] conserved external states */
+} dgx_mesh;
+
+typedef struct dgx_newton_stats {
+    int64_t nodes;            /* nodes solved                              */
+    int64_t iters_total;      /* sum of per-node iterations                */
+    int32_t iters_max;        /* max per-node iterations                   */
+    double iters_wave_max_mean; /* mean over wavefronts of the per-wave max */
+    int64_t nonconverged;     /* nodes that hit newton_maxit              */
+    int64_t first_bad;        /* first non-converged node, or -1           */
+} dgx_newton_stats;
+
+typedef struct dgx_ctx dgx_ctx;  /* opaque */
+
+/* Create a context for one discretisation (Sec. Methodology; equation type
+ * of Sec. Hypersonic Equations Type).  cfg and the tables it points to are
+ * copied.  Returns DGX_E_INVAL for unsupported combinations
+ * (dim not 2/3, N not 3/4, EC flux with a mixture, NS with a mixture). */
+int dgx_create(const dgx_config *cfg, dgx_ctx **out);
+
+/* Upload a mesh: the library computes its own LGL operators, metric terms
+ * (2D cross form, 3D conservative curl form), Jacobians, face normals and
+ * subcell normals (Eqs. mapp, mapped_equation, jacobian).  May be called
+ * again to replace the mesh.  Synchronous. */
+int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *mesh);
+
+/* du = L(u, t): the DGSEM right-hand side (Eq. strong_form with the
+ * flux-differencing volume term of Eq. DGvec, the FV blend of
+ * Eq. fluxes_discrete_with_fv, Riemann fluxes of Eqs. riemann_problem1-3,
+ * the BR1 viscous terms of Eqs. auxil/auxstrongf and species sources of
+ * Eq. calc_prod).  u and du: device [nvar][nelem][nn], must not alias.
+ * Enqueued on stream; t is accepted for time-dependent data (none yet). */
+int dgx_rhs(dgx_ctx *ctx, const double *u, double t, double *du, void *stream);
+
+/* nsteps steps of SSPRK3 (Shu-Osher form) at constant dt, updating u in place.
+ * The three stages are captured once into a HIP graph per u pointer and
+ * replayed.  Enqueued on stream. */
+int dgx_ssprk3_step(dgx_ctx *ctx, double *u, double t, double dt, int nsteps, void *stream);
+
+/* Largest stable dt estimate: cfl * 2/(N+1) / max_n sum_d (|v.Ja^d| + c|Ja^d|)/J.
+ * Synchronises; result written to *dt_host. */
+int dgx_max_dt(dgx_ctx *ctx, const double *u, double cfl, double *dt_host, void *stream);
+
+/* Per-node temperature from energy (Appendix Eqs. Internal_energy and
+ * eos): Newton on sum rho_s e_s(T) = rho e to |dT| <= newton_tol*T, started
+ * from T_guess (DGX_GUESS_FREESTREAM) or the trained surrogate
+ * (DGX_GUESS_SURROGATE).  u: device [nvar][nelem][nn] of a mixture context,
+ * or nstates = count of a packed [nvar][count] state set when the mesh is not
+ * used (pass nstates > 0).  T, p: device [count].  stats (host, may be NULL)
+ * receive iteration counts.  Synchronises. */
+int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double *p,
+               int guess_mode, dgx_newton_stats *stats, void *stream);
+
+/* Shock-indicator blending factor of the last dgx_rhs call (device pointer
+ * to [nelem] doubles owned by the library; NULL if shock capturing is off). */
+const double *dgx_last_alpha(const dgx_ctx *ctx);
+
+/* Surrogate T-guess network 6 -> 64 -> 64 -> 64 -> 1 (tanh), BF16 operands,
+ * FP32 accumulation, FP32 master weights.  Parameter vector layout (8833
+ * floats): W1[64][6], b1[64], W2[64][64], b2[64], W3[64][64], b3[64],
+ * W4[1][64], b4[1]; then 14 normalisation floats: mean[6], std[6],
+ * T_mean, T_std.  dgx_surrogate_set copies host params (n = 8847). */
+int dgx_surrogate_set(dgx_ctx *ctx, const float *params_host, size_t n);
+int dgx_surrogate_get(dgx_ctx *ctx, float *params_host, size_t n);
+
+/* Train the surrogate on device states (packed [nvar][count], count >= 256)
+ * with labels T (device [count]): epochs of Adam (lr, beta1 0.9, beta2 0.999,
+ * eps 1e-8) over minibatches of `batch` in a seeded order.  The loss of each
+ * epoch is written to loss_host[epoch] if not NULL.  Synchronises. */
+int dgx_surrogate_train(dgx_ctx *ctx, const double *states, const double *T, int64_t count,
+                        int epochs, int batch, float lr, uint64_t seed, float *loss_host,
+                        void *stream);
+
+/* Surrogate prediction T_guess for packed states (device [nvar][count]) into
+ * Tg (device [count], FP64).  Enqueued on stream. */
+int dgx_surrogate_predict(dgx_ctx *ctx, const double *states, int64_t count, double *Tg,
+                          void *stream);
+
+/* Read and clear the sticky device error flags.  Synchronises. */
+int dgx_check(dgx_ctx *ctx, void *stream);
+
+/* Per-species specific energy e_s(T) and heat capacity cv_s(T) of the
+ * context's mixture at one temperature (host computation, for building
+ * states).  e, cv: host [5]. */
+int dgx_species_energy(const dgx_ctx *ctx, double T, double *e, double *cv);
+
+/* Text of the last error on this context (never NULL). */
+const char *dgx_last_error(const dgx_ctx *ctx);
+
+/* Release every resource of the context.  NULL is ignored. */
+void dgx_destroy(dgx_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGX_H */

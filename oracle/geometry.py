@@ -8,7 +8,10 @@ Reading (the paper is silent on how metric terms are discretised): 2D uses
 Ja^1 = (y_eta, -x_eta), Ja^2 = (-y_xi, x_xi); 3D uses the conservative curl
 form Ja^i_n = -e_i . curl_X( I^N( x_l grad_X x_m ) ), (n, m, l) cyclic, with
 every derivative taken by the nodal derivative matrix.  |J| is the
-determinant of the nodal Jacobian matrix.  Face normals are +-Ja^d at the
+determinant of the nodal Jacobian matrix.  Both are evaluated on coordinates
+relative to the element's first node: the discrete curl form is invariant
+under a translation (D_p and D_q act on different tensor indices and
+commute), and the smaller magnitudes reduce roundoff.  Face normals are +-Ja^d at the
 face nodes; subcell normals of the finite-volume blend are the telescoped
 sums n_m = Ja^d_0 + sum_{l<m} w_l (D Ja^d)_l along each line.
 """
@@ -39,7 +42,7 @@ def metrics(x, basis, dim):
     """
     n1 = basis.n1
     D = basis.D
-    X = tensor(x, dim, n1)
+    X = tensor(x - x[:, :, :1], dim, n1)
     # dx_c / dX_d
     dx = np.stack([np.stack([ref_deriv(X[c], D, d, dim) for d in range(dim)], 0)
                    for c in range(dim)], 0)  # dx[c][d]

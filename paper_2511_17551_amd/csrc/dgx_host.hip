@@ -1,0 +1,789 @@
+// libdgx host runtime: contexts, geometry upload, kernel dispatch and the
+// C-ABI entry points declared in include/dgx.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dgx.h"
+#include "host_geometry.h"
+#include "k_aux.h"
+#include "surrogate.h"
+
+using namespace dgx;
+
+namespace {
+
+#define HIPCHK(call)                                                              \
+    do {                                                                          \
+        hipError_t _e = (call);                                                   \
+        if (_e != hipSuccess) {                                                   \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(_e);         \
+            return DGX_E_DEVICE;                                                  \
+        }                                                                         \
+    } while (0)
+
+// ------------------------------------------------------------------ dispatch
+using RhsLaunch = void (*)(const RhsParams &, int, int, int, size_t, hipStream_t);
+using GradLaunch = void (*)(const RhsParams &, int, int, size_t, hipStream_t);
+using IndLaunch = void (*)(const RhsParams &, int, double, double, double *, double *, int, int, size_t,
+                           hipStream_t);
+
+template <int DIM, int N, int EQ, int VF, int SF, bool CURV>
+void rhs_launch(const RhsParams &P, int mode, int blocks, int threads, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_rhs<DIM, N, EQ, VF, SF, CURV>), dim3(blocks), dim3(threads), lds, s, P, mode);
+}
+template <int DIM, int N>
+void grad_launch(const RhsParams &P, int blocks, int threads, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_grad<DIM, N>), dim3(blocks), dim3(threads), lds, s, P);
+}
+template <int DIM, int N, bool MIX>
+void ind_launch(const RhsParams &P, int iv, double amax, double amin, double *a, double *araw, int blocks,
+                int threads, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_indicator<DIM, N, MIX>), dim3(blocks), dim3(threads), lds, s, P, iv, amax, amin, a,
+                       araw);
+}
+
+struct RhsEntry {
+    int dim, N, eq, vf, sf, curv;
+    RhsLaunch fn;
+    int slot;  // doubles of LDS per element
+};
+
+#define RHS_ENTRY(D, N, EQ, VF, SF, CV) \
+    {D, N, EQ, VF, SF, CV, &rhs_launch<D, N, EQ, VF, SF, (bool)CV>, RhsShape<D, N, EQ, VF, (bool)CV>::SLOT}
+
+const RhsEntry kRhs[] = {
+    // 2D perfect gas (isentropic vortex, O-grid checks)
+    RHS_ENTRY(2, 3, 0, 0, 0, 0), RHS_ENTRY(2, 3, 0, 0, 1, 0), RHS_ENTRY(2, 3, 0, 0, 0, 1),
+    RHS_ENTRY(2, 3, 0, 1, 0, 1), RHS_ENTRY(2, 4, 0, 0, 0, 0),
+    // 3D perfect gas Euler / NS
+    RHS_ENTRY(3, 3, 0, 0, 0, 0), RHS_ENTRY(3, 3, 0, 0, 1, 0), RHS_ENTRY(3, 3, 1, 0, 0, 0),
+    RHS_ENTRY(3, 3, 0, 0, 0, 1), RHS_ENTRY(3, 3, 0, 0, 1, 1), RHS_ENTRY(3, 4, 0, 0, 0, 1),
+    RHS_ENTRY(3, 4, 0, 0, 1, 1), RHS_ENTRY(3, 3, 0, 1, 0, 1), RHS_ENTRY(3, 4, 0, 1, 0, 1),
+    // mixtures
+    RHS_ENTRY(3, 4, 2, 1, 0, 1), RHS_ENTRY(3, 3, 2, 1, 0, 1), RHS_ENTRY(2, 3, 2, 1, 0, 1),
+    RHS_ENTRY(2, 3, 3, 1, 0, 1), RHS_ENTRY(2, 3, 3, 1, 0, 0),
+};
+
+struct IndEntry {
+    int dim, N, mix;
+    IndLaunch fn;
+};
+const IndEntry kInd[] = {
+    {2, 3, 0, &ind_launch<2, 3, false>}, {2, 3, 1, &ind_launch<2, 3, true>},
+    {3, 3, 0, &ind_launch<3, 3, false>}, {3, 3, 1, &ind_launch<3, 3, true>},
+    {3, 4, 0, &ind_launch<3, 4, false>}, {3, 4, 1, &ind_launch<3, 4, true>},
+    {2, 4, 0, &ind_launch<2, 4, false>}, {2, 4, 1, &ind_launch<2, 4, true>},
+};
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+}  // namespace
+
+struct dgx_ctx {
+    dgx_config cfg{};
+    dgx_species sp{};
+    bool has_sp = false;
+    std::vector<double> rA, rb, rth;
+    std::vector<int> rnu, rnup;
+    int nvar = 0, N1 = 0, nn = 0, nf = 0;
+    HostBasis basis;
+    BasisC bc{};
+    MixC mix{};
+    KinC kin{};
+    std::string err;
+    // mesh
+    int nelem = 0;
+    bool curved = false;
+    bool mesh_ok = false;
+    int nbc = 0;
+    DevBuf<double> geo, Jn, nsub, bc_state, bc_T, T, alpha, alpha_tmp, alpha_raw, grad, u1, u2, dtbuf;
+    DevBuf<int> nbr, bc_kind;
+    DevBuf<KinC> kin_d;
+    DevBuf<unsigned> flags;
+    DevBuf<unsigned long long> rate;
+    // launch configuration (autotuned elements per block)
+    int epb = 1;
+    const RhsEntry *rhs = nullptr;
+    // graph cache for ssprk3
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;
+    const double *g_u = nullptr;
+    double g_dt = 0.0;
+    // surrogate
+    Surrogate sur;
+};
+
+namespace {
+
+int set_err(dgx_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+template <typename T>
+int dalloc(dgx_ctx *ctx, DevBuf<T> &b, size_t n) {
+    if (b.n == n && b.p) return DGX_OK;
+    b.release();
+    if (n == 0) return DGX_OK;
+    if (hipMalloc(&b.p, n * sizeof(T)) != hipSuccess) {
+        b.p = nullptr;
+        return set_err(ctx, DGX_E_NOMEM, "hipMalloc failed");
+    }
+    b.n = n;
+    return DGX_OK;
+}
+
+int threads_for(int nn, int epb) { return ((nn * epb + 63) / 64) * 64; }
+
+void clear_graph(dgx_ctx *ctx) {
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->gexec = nullptr;
+    ctx->graph = nullptr;
+    ctx->g_u = nullptr;
+}
+
+bool is_mix(const dgx_ctx *ctx) { return ctx->cfg.equation >= DGX_EQ_EULER_MIX; }
+
+// Host T(e) for a single mixture state (Dirichlet boundary states).
+double host_T(const dgx_ctx *ctx, const double *u) {
+    const MixC &M = ctx->mix;
+    const int dim = ctx->cfg.dim;
+    double rho = 0.0, m2 = 0.0;
+    for (int s = 0; s < kNS; ++s) rho += u[s];
+    for (int c = 0; c < dim; ++c) m2 += u[kNS + c] * u[kNS + c];
+    const double target = u[kNS + dim] - 0.5 * m2 / rho;
+    double T = ctx->cfg.T_guess;
+    for (int it = 0; it < 200; ++it) {
+        double e = 0.0, cv = 0.0;
+        for (int s = 0; s < kNS; ++s) {
+            double es = 1.5 * M.Rs[s] * T + M.e0[s], cs = 1.5 * M.Rs[s];
+            if (M.mol[s]) {
+                const double x = M.thv[s] / T, em1 = std::expm1(x);
+                es += M.Rs[s] * T + M.Rs[s] * M.thv[s] / em1;
+                cs += M.Rs[s] + M.Rs[s] * x * x * (em1 + 1.0) / (em1 * em1);
+            }
+            e += u[s] * es;
+            cv += u[s] * cs;
+        }
+        const double dT = (e - target) / cv;
+        T -= dT;
+        if (std::fabs(dT) <= 1e-14 * T) break;
+    }
+    return T;
+}
+
+RhsParams base_params(dgx_ctx *ctx) {
+    RhsParams P{};
+    P.nelem = ctx->nelem;
+    P.nbr = ctx->nbr.p;
+    P.geo = ctx->geo.p;
+    P.Jn = ctx->Jn.p;
+    P.nsub = ctx->nsub.p;
+    P.T = ctx->T.p;
+    P.grad = ctx->grad.p;
+    P.bc_kind = ctx->bc_kind.p;
+    P.bc_state = ctx->bc_state.p;
+    P.bc_T = ctx->bc_T.p;
+    P.kin = ctx->kin_d.p;
+    P.gamma = ctx->cfg.gamma;
+    P.R = ctx->cfg.R;
+    P.mu = ctx->cfg.mu;
+    P.kappa = ctx->cfg.mu * ctx->cfg.gamma * ctx->cfg.R / ((ctx->cfg.gamma - 1.0) * ctx->cfg.Pr);
+    P.epb = ctx->epb;
+    P.flags = ctx->flags.p;
+    P.B = ctx->bc;
+    P.M = ctx->mix;
+    return P;
+}
+
+const IndEntry *find_ind(const dgx_ctx *ctx) {
+    for (const auto &e : kInd)
+        if (e.dim == ctx->cfg.dim && e.N == ctx->cfg.N && e.mix == (is_mix(ctx) ? 1 : 0)) return &e;
+    return nullptr;
+}
+
+// thermo for the mesh state (mixtures), T stored in ctx->T
+int enqueue_thermo_mesh(dgx_ctx *ctx, const double *u, hipStream_t s) {
+    const int64_t count = (int64_t)ctx->nelem * ctx->nn;
+    const int th = 256;
+    const int blocks = (int)((count + th - 1) / th);
+    if (ctx->cfg.dim == 2)
+        hipLaunchKernelGGL(k_thermo<2>, dim3(blocks), dim3(th), 0, s, u, count, (const double *)nullptr,
+                           ctx->cfg.T_guess, ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, ctx->T.p,
+                           (double *)nullptr, (int *)nullptr, ctx->flags.p);
+    else
+        hipLaunchKernelGGL(k_thermo<3>, dim3(blocks), dim3(th), 0, s, u, count, (const double *)nullptr,
+                           ctx->cfg.T_guess, ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, ctx->T.p,
+                           (double *)nullptr, (int *)nullptr, ctx->flags.p);
+    return hipGetLastError() == hipSuccess ? DGX_OK : DGX_E_DEVICE;
+}
+
+// Everything of one right-hand-side evaluation.  mode 0: out = du;
+// mode 1: out = sa*u0 + sb*(u + dt*du).
+int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const double *u0, double sa, double sb,
+                double dt, hipStream_t s) {
+    const dgx_config &c = ctx->cfg;
+    if (is_mix(ctx)) {
+        int rc = enqueue_thermo_mesh(ctx, u, s);
+        if (rc) return set_err(ctx, rc, "thermo launch failed");
+    }
+    RhsParams P = base_params(ctx);
+    P.u = u;
+    const int epb = ctx->epb;
+    const int th = threads_for(ctx->nn, epb);
+    const int blocks = (ctx->nelem + epb - 1) / epb;
+    // shock indicator / forced blending
+    if (c.force_alpha >= 0.0) {
+        P.alpha = ctx->alpha.p;
+    } else if (c.shock) {
+        const IndEntry *ie = find_ind(ctx);
+        if (!ie) return set_err(ctx, DGX_E_INVAL, "no indicator kernel for this configuration");
+        ie->fn(P, c.ind_var, c.alpha_max, c.alpha_min, ctx->alpha.p, ctx->alpha_raw.p, blocks, th,
+               (size_t)epb * 2 * ctx->nn * sizeof(double), s);
+        if (c.alpha_smooth) {
+            const int tb = 256;
+            if (c.dim == 2)
+                hipLaunchKernelGGL(k_alpha_smooth<2>, dim3((ctx->nelem + tb - 1) / tb), dim3(tb), 0, s,
+                                   ctx->nbr.p, ctx->nelem, ctx->alpha.p, ctx->alpha_tmp.p);
+            else
+                hipLaunchKernelGGL(k_alpha_smooth<3>, dim3((ctx->nelem + tb - 1) / tb), dim3(tb), 0, s,
+                                   ctx->nbr.p, ctx->nelem, ctx->alpha.p, ctx->alpha_tmp.p);
+            (void)hipMemcpyAsync(ctx->alpha.p, ctx->alpha_tmp.p, ctx->nelem * sizeof(double), hipMemcpyDeviceToDevice,
+                           s);
+        }
+        P.alpha = ctx->alpha.p;
+    }
+    if (c.equation == DGX_EQ_NS) {
+        RhsParams G = P;
+        G.out = ctx->grad.p;
+        const size_t lds = (size_t)epb * (c.dim + 1) * ctx->nn * sizeof(double);
+        if (c.dim == 3 && c.N == 3) grad_launch<3, 3>(G, blocks, th, lds, s);
+        else if (c.dim == 3 && c.N == 4) grad_launch<3, 4>(G, blocks, th, lds, s);
+        else if (c.dim == 2 && c.N == 3) grad_launch<2, 3>(G, blocks, th, lds, s);
+        else return set_err(ctx, DGX_E_INVAL, "NS gradients not built for this dim/N");
+    }
+    P.out = out;
+    P.u0 = u0;
+    P.sa = sa;
+    P.sb = sb;
+    P.dt = dt;
+    ctx->rhs->fn(P, mode, blocks, th, (size_t)epb * ctx->rhs->slot * sizeof(double), s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_err(ctx, DGX_E_DEVICE, std::string("rhs launch: ") + hipGetErrorString(e));
+    return DGX_OK;
+}
+
+int check_ctx(dgx_ctx *ctx) {
+    if (!ctx) return DGX_E_INVAL;
+    if (!ctx->mesh_ok) return set_err(ctx, DGX_E_STATE, "no mesh set");
+    return DGX_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
+    if (!cfg || !out) return DGX_E_INVAL;
+    *out = nullptr;
+    if ((cfg->dim != 2 && cfg->dim != 3) || (cfg->N != 3 && cfg->N != 4)) return DGX_E_INVAL;
+    if (cfg->equation < 0 || cfg->equation > 3) return DGX_E_INVAL;
+    const bool mix = cfg->equation >= DGX_EQ_EULER_MIX;
+    if (mix && (!cfg->species || cfg->species->nspecies != 5)) return DGX_E_INVAL;
+    if (mix && cfg->volume_flux == DGX_VF_RANOCHA) return DGX_E_INVAL;
+    if (mix && cfg->surface_flux != DGX_SF_RUSANOV) return DGX_E_INVAL;
+    if (cfg->equation == DGX_EQ_REACT_MIX &&
+        (!cfg->reactions || cfg->reactions->nreactions < 1 || cfg->reactions->nreactions > kMaxR))
+        return DGX_E_INVAL;
+    if (cfg->equation == DGX_EQ_NS && (cfg->mu < 0.0 || cfg->Pr <= 0.0)) return DGX_E_INVAL;
+    if (!mix && !(cfg->gamma > 1.0)) return DGX_E_INVAL;
+    dgx_ctx *ctx = new (std::nothrow) dgx_ctx();
+    if (!ctx) return DGX_E_NOMEM;
+    ctx->cfg = *cfg;
+    ctx->cfg.species = nullptr;
+    ctx->cfg.reactions = nullptr;
+    ctx->N1 = cfg->N + 1;
+    ctx->nn = cfg->dim == 2 ? ctx->N1 * ctx->N1 : ctx->N1 * ctx->N1 * ctx->N1;
+    ctx->nf = ctx->nn / ctx->N1;
+    ctx->nvar = (mix ? 5 : 1) + cfg->dim + 1;
+    ctx->basis = make_basis(cfg->N);
+    for (int i = 0; i < ctx->N1 * ctx->N1; ++i) {
+        ctx->bc.D[i] = ctx->basis.D[i];
+        ctx->bc.Vinv[i] = ctx->basis.Vinv[i];
+    }
+    for (int i = 0; i < ctx->N1; ++i) ctx->bc.w[i] = ctx->basis.w[i];
+    if (mix) {
+        ctx->sp = *cfg->species;
+        ctx->has_sp = true;
+        for (int s = 0; s < 5; ++s) {
+            ctx->mix.Rs[s] = ctx->sp.Ru / ctx->sp.W[s];
+            ctx->mix.thv[s] = ctx->sp.molecule[s] ? ctx->sp.theta_v[s] : 0.0;
+            ctx->mix.e0[s] = ctx->sp.e0[s];
+            ctx->mix.mol[s] = ctx->sp.molecule[s] ? 1 : 0;
+        }
+    }
+    if (cfg->equation == DGX_EQ_REACT_MIX) {
+        const dgx_reactions *r = cfg->reactions;
+        KinC &K = ctx->kin;
+        K.nr = r->nreactions;
+        const dgx_species &sp = ctx->sp;
+        for (int i = 0; i < K.nr; ++i) {
+            K.A[i] = r->A[i];
+            K.b[i] = r->b[i];
+            K.tha[i] = r->theta_a[i];
+            double sum = 0.0;
+            for (int s = 0; s < 5; ++s) {
+                K.nu[i][s] = r->nu[i * 5 + s];
+                K.nup[i][s] = r->nup[i * 5 + s];
+                sum += K.nup[i][s] - K.nu[i][s];
+            }
+            K.dnu_sum[i] = sum;
+        }
+        for (int s = 0; s < 5; ++s) {
+            K.W[s] = sp.W[s];
+            // -g_s/(R_s T) = ln c_s + (5/2 + mol) ln T - mol [ln theta_r + ln sigma]
+            //                - mol ln(1 - e^{-theta_v/T}) + ln Qe - e0/(R_s T);
+            // gconst = -ln c_s + mol (ln theta_r + ln sigma) - ln Qe  (see k_rhs)
+            const double ct = std::log(sp.Ru / (sp.NA * sp.p_ref)) +
+                              1.5 * std::log(2.0 * M_PI * sp.W[s] * sp.Ru / (sp.NA * sp.NA * sp.hP * sp.hP));
+            double g = -ct - std::log(sp.Qe[s]);
+            if (sp.molecule[s]) g += std::log(sp.theta_r[s]) + std::log(sp.sigma[s]);
+            K.gconst[s] = g;
+        }
+        K.lnpref_Ru = std::log(sp.p_ref / sp.Ru);
+    }
+    for (const auto &e : kRhs) {
+        if (e.dim == cfg->dim && e.N == cfg->N && e.eq == cfg->equation && e.vf == cfg->volume_flux &&
+            e.sf == cfg->surface_flux) {
+            ctx->rhs = &e;  // curved flag fixed at set_mesh
+            break;
+        }
+    }
+    if (!ctx->rhs) {
+        delete ctx;
+        return DGX_E_INVAL;
+    }
+    if (hipMalloc(&ctx->flags.p, sizeof(unsigned)) != hipSuccess) {
+        delete ctx;
+        return DGX_E_DEVICE;
+    }
+    ctx->flags.n = 1;
+    (void)hipMemset(ctx->flags.p, 0, sizeof(unsigned));
+    if (hipMalloc(&ctx->rate.p, sizeof(unsigned long long)) != hipSuccess) {
+        ctx->flags.release();
+        delete ctx;
+        return DGX_E_DEVICE;
+    }
+    ctx->rate.n = 1;
+    *out = ctx;
+    return DGX_OK;
+}
+
+int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
+    if (!ctx || !m || !m->x || m->nelem <= 0) return set_err(ctx, DGX_E_INVAL, "bad mesh");
+    const int dim = ctx->cfg.dim, N = ctx->cfg.N, n1 = ctx->N1, nn = ctx->nn, E = m->nelem;
+    const int nv = ctx->nvar;
+    if (m->nface < 0 || (m->nface && !m->faces) || m->nbface < 0 || (m->nbface && !m->bfaces) ||
+        m->nbc < 0 || (m->nbc && (!m->bc_kind || !m->bc_state)))
+        return set_err(ctx, DGX_E_INVAL, "bad mesh tables");
+    if (m->nmortar != 0) return set_err(ctx, DGX_E_INVAL, "mortar meshes need the AMR path");
+    clear_graph(ctx);
+    ctx->mesh_ok = false;
+    // connectivity
+    std::vector<int> nbr((size_t)E * 2 * dim, INT_MIN);
+    for (int i = 0; i < m->nface; ++i) {
+        const int eL = m->faces[4 * i], fL = m->faces[4 * i + 1], eR = m->faces[4 * i + 2], fR = m->faces[4 * i + 3];
+        if (eL < 0 || eL >= E || eR < 0 || eR >= E || fL < 0 || fL >= 2 * dim || fL % 2 != 1 || fR != fL - 1)
+            return set_err(ctx, DGX_E_INVAL, "face row " + std::to_string(i) + " is not a (+d, -d) pair");
+        nbr[(size_t)eL * 2 * dim + fL] = eR;
+        nbr[(size_t)eR * 2 * dim + fR] = eL;
+    }
+    for (int i = 0; i < m->nbface; ++i) {
+        const int e = m->bfaces[3 * i], f = m->bfaces[3 * i + 1], b = m->bfaces[3 * i + 2];
+        if (e < 0 || e >= E || f < 0 || f >= 2 * dim || b < 0 || b >= m->nbc)
+            return set_err(ctx, DGX_E_INVAL, "bad boundary face " + std::to_string(i));
+        nbr[(size_t)e * 2 * dim + f] = -1 - b;
+    }
+    for (size_t i = 0; i < nbr.size(); ++i)
+        if (nbr[i] == INT_MIN) return set_err(ctx, DGX_E_INVAL, "element face without neighbour or boundary");
+    if (ctx->cfg.equation == DGX_EQ_NS && m->nbface) return set_err(ctx, DGX_E_INVAL, "NS supports periodic meshes only");
+    for (int b = 0; b < m->nbc; ++b)
+        if (m->bc_kind[b] < 0 || m->bc_kind[b] > 2) return set_err(ctx, DGX_E_INVAL, "bad boundary kind");
+    // geometry
+    std::vector<double> Ja((size_t)dim * dim * E * nn), Jv((size_t)E * nn);
+    std::vector<double> jae(dim * dim * nn), je(nn);
+    std::vector<const double *> xe(dim);
+    bool affine = true;
+    for (int e = 0; e < E; ++e) {
+        for (int c = 0; c < dim; ++c) xe[c] = m->x + ((size_t)c * E + e) * nn;
+        element_metrics(ctx->basis, dim, xe.data(), jae.data(), je.data());
+        double mx = 0.0, dev = 0.0;
+        for (int k = 0; k < dim * dim; ++k)
+            for (int n = 0; n < nn; ++n) {
+                mx = std::max(mx, std::fabs(jae[k * nn + n]));
+                dev = std::max(dev, std::fabs(jae[k * nn + n] - jae[k * nn]));
+                Ja[((size_t)k * E + e) * nn + n] = jae[k * nn + n];
+            }
+        for (int n = 0; n < nn; ++n) {
+            if (!(je[n] > 0.0)) return set_err(ctx, DGX_E_INVAL, "non-positive Jacobian in element " + std::to_string(e));
+            dev = std::max(dev, std::fabs(je[n] - je[0]) * mx / std::fabs(je[0]));
+            Jv[(size_t)e * nn + n] = je[n];
+        }
+        if (dev > 1e-12 * mx) affine = false;
+    }
+    if (ctx->cfg.equation == DGX_EQ_NS && !affine) return set_err(ctx, DGX_E_INVAL, "NS needs affine elements");
+    // pick the kernel variant for this geometry
+    const RhsEntry *sel = nullptr;
+    for (const auto &e : kRhs)
+        if (e.dim == dim && e.N == N && e.eq == ctx->cfg.equation && e.vf == ctx->cfg.volume_flux &&
+            e.sf == ctx->cfg.surface_flux && e.curv == (affine ? 0 : 1))
+            sel = &e;
+    if (!sel && affine)  // fall back to the curved variant (valid for any mesh)
+        for (const auto &e : kRhs)
+            if (e.dim == dim && e.N == N && e.eq == ctx->cfg.equation && e.vf == ctx->cfg.volume_flux &&
+                e.sf == ctx->cfg.surface_flux && e.curv == 1)
+                sel = &e, affine = false;
+    if (!sel) return set_err(ctx, DGX_E_INVAL, "no kernel variant for this configuration and mesh");
+    ctx->rhs = sel;
+    ctx->curved = !affine;
+    ctx->nelem = E;
+    ctx->nbc = m->nbc;
+    int rc;
+    if ((rc = dalloc(ctx, ctx->nbr, nbr.size()))) return rc;
+    HIPCHK(hipMemcpy(ctx->nbr.p, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (affine) {
+        const int GA = dim * dim + 1;
+        std::vector<double> g((size_t)E * GA);
+        for (int e = 0; e < E; ++e) {
+            for (int k = 0; k < dim * dim; ++k) g[(size_t)e * GA + k] = Ja[((size_t)k * E + e) * nn];
+            g[(size_t)e * GA + dim * dim] = Jv[(size_t)e * nn];
+        }
+        if ((rc = dalloc(ctx, ctx->geo, g.size()))) return rc;
+        HIPCHK(hipMemcpy(ctx->geo.p, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice));
+        ctx->Jn.release();
+        ctx->nsub.release();
+    } else {
+        if ((rc = dalloc(ctx, ctx->geo, Ja.size()))) return rc;
+        HIPCHK(hipMemcpy(ctx->geo.p, Ja.data(), Ja.size() * sizeof(double), hipMemcpyHostToDevice));
+        if ((rc = dalloc(ctx, ctx->Jn, Jv.size()))) return rc;
+        HIPCHK(hipMemcpy(ctx->Jn.p, Jv.data(), Jv.size() * sizeof(double), hipMemcpyHostToDevice));
+        if (ctx->cfg.shock || ctx->cfg.force_alpha > 0.0) {
+            // telescoped subcell normals n_m = Ja^d_0 + sum_{l<m} w_l (D_d Ja^d)_l, m = 1..N
+            const int nf = ctx->nf;
+            std::vector<double> ns((size_t)E * dim * nf * N * dim);
+            std::vector<double> f(nn), df(nn);
+            for (int e = 0; e < E; ++e)
+                for (int d = 0; d < dim; ++d) {
+                    const int st = d == 0 ? 1 : (d == 1 ? n1 : n1 * n1);
+                    for (int c = 0; c < dim; ++c) {
+                        for (int n = 0; n < nn; ++n) f[n] = Ja[((size_t)(d * dim + c) * E + e) * nn + n];
+                        ref_derivative(ctx->basis, dim, d, f.data(), df.data());
+                        for (int l = 0; l < nf; ++l) {
+                            // node of line l at position a along d
+                            int base;
+                            if (d == 0) base = n1 * l;
+                            else if (d == 1) base = (l % n1) + (dim == 3 ? n1 * n1 * (l / n1) : 0);
+                            else base = l;
+                            double acc = f[base];
+                            for (int mm = 1; mm <= N; ++mm) {
+                                acc += ctx->basis.w[mm - 1] * df[base + (mm - 1) * st];
+                                ns[((((size_t)e * dim + d) * nf + l) * N + (mm - 1)) * dim + c] = acc;
+                            }
+                        }
+                    }
+                }
+            if ((rc = dalloc(ctx, ctx->nsub, ns.size()))) return rc;
+            HIPCHK(hipMemcpy(ctx->nsub.p, ns.data(), ns.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
+    }
+    // boundary states
+    if (m->nbc) {
+        if ((rc = dalloc(ctx, ctx->bc_kind, m->nbc))) return rc;
+        HIPCHK(hipMemcpy(ctx->bc_kind.p, m->bc_kind, m->nbc * sizeof(int), hipMemcpyHostToDevice));
+        if ((rc = dalloc(ctx, ctx->bc_state, (size_t)m->nbc * nv))) return rc;
+        HIPCHK(hipMemcpy(ctx->bc_state.p, m->bc_state, (size_t)m->nbc * nv * sizeof(double), hipMemcpyHostToDevice));
+        std::vector<double> bT(m->nbc, 0.0);
+        if (is_mix(ctx))
+            for (int b = 0; b < m->nbc; ++b)
+                if (m->bc_kind[b] == DGX_BC_DIRICHLET) bT[b] = host_T(ctx, m->bc_state + (size_t)b * nv);
+        if ((rc = dalloc(ctx, ctx->bc_T, m->nbc))) return rc;
+        HIPCHK(hipMemcpy(ctx->bc_T.p, bT.data(), m->nbc * sizeof(double), hipMemcpyHostToDevice));
+    }
+    // scratch
+    if (is_mix(ctx) && (rc = dalloc(ctx, ctx->T, (size_t)E * nn))) return rc;
+    if ((rc = dalloc(ctx, ctx->alpha, E))) return rc;
+    if ((rc = dalloc(ctx, ctx->alpha_tmp, E))) return rc;
+    if ((rc = dalloc(ctx, ctx->alpha_raw, E))) return rc;
+    {
+        std::vector<double> a(E, ctx->cfg.force_alpha >= 0.0 ? ctx->cfg.force_alpha : 0.0);
+        HIPCHK(hipMemcpy(ctx->alpha.p, a.data(), E * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(ctx->alpha_raw.p, a.data(), E * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (ctx->cfg.equation == DGX_EQ_NS && (rc = dalloc(ctx, ctx->grad, (size_t)dim * (dim + 1) * E * nn))) return rc;
+    if (ctx->cfg.equation == DGX_EQ_REACT_MIX) {
+        if ((rc = dalloc(ctx, ctx->kin_d, 1))) return rc;
+        HIPCHK(hipMemcpy(ctx->kin_d.p, &ctx->kin, sizeof(KinC), hipMemcpyHostToDevice));
+    }
+    // default elements per block: about 256 threads, LDS <= 64 KB
+    int epb = std::max(1, 256 / nn);
+    while (epb > 1 && (size_t)epb * sel->slot * sizeof(double) > 64 * 1024) --epb;
+    ctx->epb = epb;
+    ctx->mesh_ok = true;
+    return DGX_OK;
+}
+
+int dgx_rhs(dgx_ctx *ctx, const double *u, double t, double *du, void *stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    (void)t;
+    if (!u || !du || u == du) return set_err(ctx, DGX_E_INVAL, "u/du must be distinct device pointers");
+    return enqueue_rhs(ctx, u, du, 0, nullptr, 0.0, 1.0, 0.0, (hipStream_t)stream);
+}
+
+int dgx_ssprk3_step(dgx_ctx *ctx, double *u, double t, double dt, int nsteps, void *stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    (void)t;
+    if (!u || nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return set_err(ctx, DGX_E_INVAL, "bad ssprk3 arguments");
+    if (nsteps == 0) return DGX_OK;
+    const size_t n = (size_t)ctx->nvar * ctx->nelem * ctx->nn;
+    if ((rc = dalloc(ctx, ctx->u1, n))) return rc;
+    if ((rc = dalloc(ctx, ctx->u2, n))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (!ctx->gexec || ctx->g_u != u || ctx->g_dt != dt) {
+        clear_graph(ctx);
+        if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        int r1 = enqueue_rhs(ctx, u, ctx->u1.p, 1, nullptr, 0.0, 1.0, dt, ctx->cap_stream);
+        int r2 = r1 ? r1 : enqueue_rhs(ctx, ctx->u1.p, ctx->u2.p, 1, u, 0.75, 0.25, dt, ctx->cap_stream);
+        int r3 = r2 ? r2 : enqueue_rhs(ctx, ctx->u2.p, u, 1, u, 1.0 / 3.0, 2.0 / 3.0, dt, ctx->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (r3) {
+            if (g) (void)hipGraphDestroy(g);
+            return r3;
+        }
+        if (ee != hipSuccess) return set_err(ctx, DGX_E_DEVICE, std::string("capture: ") + hipGetErrorString(ee));
+        ctx->graph = g;
+        HIPCHK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+        ctx->g_u = u;
+        ctx->g_dt = dt;
+    }
+    for (int i = 0; i < nsteps; ++i) HIPCHK(hipGraphLaunch(ctx->gexec, s));
+    return DGX_OK;
+}
+
+int dgx_max_dt(dgx_ctx *ctx, const double *u, double cfl, double *dt_host, void *stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!u || !dt_host || !(cfl > 0.0)) return set_err(ctx, DGX_E_INVAL, "bad max_dt arguments");
+    hipStream_t s = (hipStream_t)stream;
+    if (is_mix(ctx) && (rc = enqueue_thermo_mesh(ctx, u, s))) return rc;
+    HIPCHK(hipMemsetAsync(ctx->rate.p, 0, sizeof(unsigned long long), s));
+    RhsParams P = base_params(ctx);
+    P.u = u;
+    P.epb = ctx->nn;
+    const int64_t total = (int64_t)ctx->nelem * ctx->nn;
+    const int tb = 256;
+    const int blocks = (int)((total + tb - 1) / tb);
+    const int key = ctx->cfg.dim * 100 + (is_mix(ctx) ? 10 : 0) + (ctx->curved ? 1 : 0);
+    switch (key) {
+        case 200: hipLaunchKernelGGL((k_maxrate<2, false, false>), dim3(blocks), dim3(tb), 0, s, P, ctx->rate.p); break;
+        case 201: hipLaunchKernelGGL((k_maxrate<2, false, true>), dim3(blocks), dim3(tb), 0, s, P, ctx->rate.p); break;
+        case 210: hipLaunchKernelGGL((k_maxrate<2, true, false>), dim3(blocks), dim3(tb), 0, s, P, ctx->rate.p); break;
+        case 211: hipLaunchKernelGGL((k_maxrate<2, true, true>), dim3(blocks), dim3(tb), 0, s, P, ctx->rate.p); break;
+        case 300: hipLaunchKernelGGL((k_maxrate<3, false, false>), dim3(blocks), dim3(tb), 0, s, P, ctx->rate.p); break;
+        case 301: hipLaunchKernelGGL((k_maxrate<3, false, true>), dim3(blocks), dim3(tb), 0, s, P, ctx->rate.p); break;
+        case 310: hipLaunchKernelGGL((k_maxrate<3, true, false>), dim3(blocks), dim3(tb), 0, s, P, ctx->rate.p); break;
+        default: hipLaunchKernelGGL((k_maxrate<3, true, true>), dim3(blocks), dim3(tb), 0, s, P, ctx->rate.p); break;
+    }
+    unsigned long long bits = 0;
+    HIPCHK(hipMemcpyAsync(&bits, ctx->rate.p, sizeof(bits), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double rate;
+    std::memcpy(&rate, &bits, sizeof(rate));
+    if (!(rate > 0.0) || !std::isfinite(rate)) return set_err(ctx, DGX_E_NONPHYSICAL, "non-finite wave speed");
+    *dt_host = cfl * 2.0 / (ctx->N1 * rate);
+    return DGX_OK;
+}
+
+int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double *p, int guess_mode,
+               dgx_newton_stats *stats, void *stream) {
+    if (!ctx) return DGX_E_INVAL;
+    if (!is_mix(ctx)) return set_err(ctx, DGX_E_INVAL, "thermo needs a mixture context");
+    if (!u || !T) return set_err(ctx, DGX_E_INVAL, "null pointer");
+    if (guess_mode != DGX_GUESS_FREESTREAM && guess_mode != DGX_GUESS_SURROGATE)
+        return set_err(ctx, DGX_E_INVAL, "bad guess mode");
+    int64_t count = nstates;
+    if (count <= 0) {
+        if (!ctx->mesh_ok) return set_err(ctx, DGX_E_STATE, "no mesh and no state count");
+        count = (int64_t)ctx->nelem * ctx->nn;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int *iters = nullptr;
+    double *tg = nullptr;
+    HIPCHK(hipMalloc((void **)&iters, count * sizeof(int)));
+    if (guess_mode == DGX_GUESS_SURROGATE) {
+        if (!ctx->sur.ready) {
+            (void)hipFree(iters);
+            return set_err(ctx, DGX_E_STATE, "surrogate has no weights");
+        }
+        HIPCHK(hipMalloc((void **)&tg, count * sizeof(double)));
+        int rc = surrogate_predict(ctx->sur, ctx->cfg.dim, u, count, tg, s);
+        if (rc) {
+            (void)hipFree(iters);
+            (void)hipFree(tg);
+            return set_err(ctx, rc, "surrogate launch failed");
+        }
+    }
+    const int tb = 256;
+    const int blocks = (int)((count + tb - 1) / tb);
+    if (ctx->cfg.dim == 2)
+        hipLaunchKernelGGL(k_thermo<2>, dim3(blocks), dim3(tb), 0, s, u, count, (const double *)tg, ctx->cfg.T_guess,
+                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, iters, ctx->flags.p);
+    else
+        hipLaunchKernelGGL(k_thermo<3>, dim3(blocks), dim3(tb), 0, s, u, count, (const double *)tg, ctx->cfg.T_guess,
+                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, iters, ctx->flags.p);
+    std::vector<int> h(count);
+    HIPCHK(hipMemcpyAsync(h.data(), iters, count * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    (void)hipFree(iters);
+    if (tg) (void)hipFree(tg);
+    int64_t tot = 0, bad = 0, first = -1;
+    int mx = 0;
+    double wsum = 0.0;
+    int64_t nw = 0;
+    for (int64_t i = 0; i < count; i += 64) {
+        int wm = 0;
+        for (int64_t j = i; j < std::min(count, i + 64); ++j) {
+            int it = h[j];
+            if (it < 0) {
+                ++bad;
+                if (first < 0) first = j;
+                it = ctx->cfg.newton_maxit;
+            }
+            tot += it;
+            mx = std::max(mx, it);
+            wm = std::max(wm, it);
+        }
+        wsum += wm;
+        ++nw;
+    }
+    if (stats) {
+        stats->nodes = count;
+        stats->iters_total = tot;
+        stats->iters_max = mx;
+        stats->iters_wave_max_mean = nw ? wsum / nw : 0.0;
+        stats->nonconverged = bad;
+        stats->first_bad = first;
+    }
+    if (bad) return set_err(ctx, DGX_E_NOCONV, std::to_string(bad) + " nodes did not converge");
+    return DGX_OK;
+}
+
+const double *dgx_last_alpha(const dgx_ctx *ctx) {
+    if (!ctx || !ctx->mesh_ok) return nullptr;
+    if (!ctx->cfg.shock && ctx->cfg.force_alpha < 0.0) return nullptr;
+    return ctx->alpha.p;
+}
+
+int dgx_check(dgx_ctx *ctx, void *stream) {
+    if (!ctx) return DGX_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned f = 0;
+    HIPCHK(hipMemcpyAsync(&f, ctx->flags.p, sizeof(f), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemset(ctx->flags.p, 0, sizeof(unsigned)));
+    if (f & FLAG_NOCONV) return set_err(ctx, DGX_E_NOCONV, "Newton for T(e) did not converge");
+    if (f & FLAG_NONPHYS) return set_err(ctx, DGX_E_NONPHYSICAL, "non-physical state (rho_s < 0, p <= 0 or non-finite)");
+    return DGX_OK;
+}
+
+int dgx_species_energy(const dgx_ctx *ctx, double T, double *e, double *cv) {
+    if (!ctx || !ctx->has_sp || !e || !cv || !(T > 0.0)) return DGX_E_INVAL;
+    const MixC &M = ctx->mix;
+    for (int s = 0; s < kNS; ++s) {
+        double es = 1.5 * M.Rs[s] * T + M.e0[s], cs = 1.5 * M.Rs[s];
+        if (M.mol[s]) {
+            const double x = M.thv[s] / T, em1 = std::expm1(x);
+            es += M.Rs[s] * T + M.Rs[s] * M.thv[s] / em1;
+            cs += M.Rs[s] + M.Rs[s] * x * x * (em1 + 1.0) / (em1 * em1);
+        }
+        e[s] = es;
+        cv[s] = cs;
+    }
+    return DGX_OK;
+}
+
+int dgx_surrogate_set(dgx_ctx *ctx, const float *params, size_t n) {
+    if (!ctx || !params || n != (size_t)kSurParams + kSurNorm) return set_err(ctx, DGX_E_INVAL, "bad surrogate params");
+    return surrogate_set(ctx->sur, params) ? set_err(ctx, DGX_E_DEVICE, "surrogate upload failed") : DGX_OK;
+}
+
+int dgx_surrogate_get(dgx_ctx *ctx, float *params, size_t n) {
+    if (!ctx || !params || n != (size_t)kSurParams + kSurNorm) return set_err(ctx, DGX_E_INVAL, "bad surrogate params");
+    if (!ctx->sur.ready) return set_err(ctx, DGX_E_STATE, "surrogate has no weights");
+    return surrogate_get(ctx->sur, params) ? set_err(ctx, DGX_E_DEVICE, "surrogate download failed") : DGX_OK;
+}
+
+int dgx_surrogate_train(dgx_ctx *ctx, const double *states, const double *T, int64_t count, int epochs, int batch,
+                        float lr, uint64_t seed, float *loss_host, void *stream) {
+    if (!ctx || !is_mix(ctx)) return set_err(ctx, DGX_E_INVAL, "surrogate needs a mixture context");
+    if (!states || !T || count < 256 || epochs < 1 || batch < 64 || batch % 64 || !(lr > 0.0f))
+        return set_err(ctx, DGX_E_INVAL, "bad training arguments");
+    int rc = surrogate_train(ctx->sur, ctx->cfg.dim, states, T, count, epochs, batch, lr, seed, loss_host,
+                             (hipStream_t)stream);
+    if (rc) return set_err(ctx, rc, "surrogate training failed: " + ctx->sur.err);
+    return DGX_OK;
+}
+
+int dgx_surrogate_predict(dgx_ctx *ctx, const double *states, int64_t count, double *Tg, void *stream) {
+    if (!ctx || !is_mix(ctx) || !states || !Tg || count <= 0) return set_err(ctx, DGX_E_INVAL, "bad predict arguments");
+    if (!ctx->sur.ready) return set_err(ctx, DGX_E_STATE, "surrogate has no weights");
+    int rc = surrogate_predict(ctx->sur, ctx->cfg.dim, states, count, Tg, (hipStream_t)stream);
+    return rc ? set_err(ctx, rc, "surrogate launch failed") : DGX_OK;
+}
+
+const char *dgx_last_error(const dgx_ctx *ctx) {
+    if (!ctx) return "null context";
+    return ctx->err.c_str();
+}
+
+void dgx_destroy(dgx_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    clear_graph(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    DevBuf<double> *bufs[] = {&ctx->geo,   &ctx->Jn,        &ctx->nsub,      &ctx->bc_state, &ctx->bc_T, &ctx->T,
+                              &ctx->alpha, &ctx->alpha_tmp, &ctx->alpha_raw, &ctx->grad,     &ctx->u1,   &ctx->u2,
+                              &ctx->dtbuf};
+    for (auto *b : bufs) b->release();
+    ctx->nbr.release();
+    ctx->bc_kind.release();
+    ctx->kin_d.release();
+    ctx->flags.release();
+    ctx->rate.release();
+    surrogate_free(ctx->sur);
+    delete ctx;
+}
+
+}  // extern "C"

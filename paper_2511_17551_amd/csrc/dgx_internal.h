@@ -1,0 +1,68 @@
+// Internal definitions shared by the host runtime and the HIP kernels of
+// libdgx.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dgx {
+
+constexpr int kNS = 5;        // species of the air mixture
+constexpr int kMaxR = 32;     // reactions
+
+// Reference-element operators of one polynomial degree, passed by value
+// (kernel arguments live in scalar registers / the constant cache).
+struct BasisC {
+    double D[25];      // D[a*(N+1)+b] = l_b'(xi_a)
+    double w[5];       // LGL weights
+    double Vinv[25];   // nodal -> orthonormal Legendre modes
+};
+
+// Thermodynamic data of the 5 species (RRHO, Appendix Thermodynamics).
+struct MixC {
+    double Rs[kNS];    // R_u / W_s
+    double thv[kNS];   // vibrational temperature (0 for atoms)
+    double e0[kNS];    // formation energy J/kg
+    int mol[kNS];      // linear diatomic?
+};
+
+// Reaction data (device memory, read with uniform addresses).
+struct KinC {
+    int nr;
+    double A[kMaxR], b[kMaxR], tha[kMaxR];
+    double dnu_sum[kMaxR];          // sum_s (nu' - nu)
+    int nu[kMaxR][kNS], nup[kMaxR][kNS];
+    double W[kNS];
+    double gconst[kNS];             // T-independent part of -g_s/(R_s T)
+    double lnpref_Ru;               // ln(p_ref / R_u)
+};
+
+// Device error flags (bit mask), sticky until dgx_check.
+enum : unsigned { FLAG_NONPHYS = 1u, FLAG_NOCONV = 2u };
+
+struct RhsParams {
+    int nelem;
+    const double *u;        // stage input state
+    double *out;            // du (mode 0) or next stage (mode 1)
+    const double *u0;       // stage base (mode 1)
+    double sa, sb, dt;      // out = sa*u0 + sb*(u + dt*du)
+    const int *nbr;         // [E][2*dim]: >= 0 neighbour, < 0: -1-bc index
+    const double *geo;      // affine: [E][dim*dim+1] (Ja rows, J); curved: Ja [dim*dim][E][nn]
+    const double *Jn;       // curved: J [E][nn]
+    const double *nsub;     // curved + shock: [E][dim][nf][N][dim] subcell normals
+    const double *alpha;    // [E] or null
+    const double *T;        // mixture temperature [E][nn]
+    const double *grad;     // NS gradients [dim][dim+1][E][nn]
+    const int *bc_kind;     // [nbc]
+    const double *bc_state; // [nbc][nvar]
+    const double *bc_T;     // [nbc] temperatures of Dirichlet states (mixture)
+    const KinC *kin;        // reacting mixture
+    const int *mort;        // element -> mortar slot table (unused when null)
+    double gamma, R, mu, kappa;
+    int epb;                // elements per block
+    unsigned *flags;
+    BasisC B;
+    MixC M;
+};
+
+}  // namespace dgx

@@ -1,0 +1,250 @@
+// Auxiliary kernels of the right-hand side: BR1 gradients, mixture
+// temperature, shock indicator, time-step bound.
+#pragma once
+
+#include "k_rhs.h"
+
+namespace dgx {
+
+// BR1 gradients of W = (v, T), T = p/(rho R)  (Sec. Methodology, Viscous
+// Fluxes, Eqs. auxil and auxstrongf with the interface value
+// W* = (W_own + W_nbr)/2; affine elements, strong form
+// q = (1/J) sum_d Ja^d [D_d W + lift(W* - W)]).
+template <int DIM, int N>
+__global__ void __launch_bounds__(256) k_grad(RhsParams P) {
+    constexpr int N1 = N + 1;
+    constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+    constexpr int NV = DIM + 2;
+    constexpr int NW = DIM + 1;
+    constexpr int GA = DIM * DIM + 1;
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
+    int el = tid / NN;
+    const int node = tid - el * NN;
+    const int e = blockIdx.x * P.epb + el;
+    const bool valid = (el < P.epb) && (e < P.nelem);
+    if (el >= P.epb) el = 0;
+    double *sw = smem + el * NW * NN;
+    const size_t stride = (size_t)P.nelem * NN;
+    const size_t gi = (size_t)(valid ? e : 0) * NN + node;
+    const double Rinv = 1.0 / P.R;
+
+    auto prim = [&](const double *u, double *W) {
+        const double ir = 1.0 / u[0];
+        double v2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            W[c] = u[1 + c] * ir;
+            v2 = fma(W[c], W[c], v2);
+        }
+        const double p = (P.gamma - 1.0) * (u[1 + DIM] - 0.5 * u[0] * v2);
+        W[DIM] = p / (u[0] * P.R);
+    };
+    double Wo[NW];
+    if (valid) {
+        double uo[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uo[v] = P.u[v * stride + gi];
+        prim(uo, Wo);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sw[w * NN + node] = Wo[w];
+    }
+    __syncthreads();
+    if (!valid) return;
+    (void)Rinv;
+    const double *g = P.geo + (size_t)e * GA;
+    double q[DIM][NW];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) q[c][w] = 0.0;
+#pragma unroll 1
+    for (int d = 0; d < DIM; ++d) {
+        const int a = node_pos<N1>(node, d);
+        const int l = node_line<N1, DIM>(node, d);
+        double dW[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) dW[w] = 0.0;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) {
+            const double Dj = P.B.D[a * N1 + j];
+            const int nj = line_node<N1, DIM>(d, j, l);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) dW[w] = fma(Dj, sw[w * NN + nj], dW[w]);
+        }
+        if (a == 0 || a == N) {
+            const int side = (a == N) ? 1 : 0;
+            const int nb = P.nbr[(size_t)e * 2 * DIM + 2 * d + side];
+            const int nbn = line_node<N1, DIM>(d, side ? 0 : N, l);
+            const size_t gj = (size_t)nb * NN + nbn;
+            double un[NV], Wn[NW];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) un[v] = P.u[v * stride + gj];
+            prim(un, Wn);
+            const double sc = side ? 1.0 / P.B.w[N] : -1.0 / P.B.w[0];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const double ws = 0.5 * (Wo[w] + Wn[w]);
+                dW[w] = fma(sc, ws - Wo[w], dW[w]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int w = 0; w < NW; ++w) q[c][w] = fma(g[d * DIM + c], dW[w], q[c][w]);
+    }
+    const double iJ = 1.0 / g[DIM * DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) P.out[(size_t)(c * NW + w) * stride + gi] = q[c][w] * iJ;
+}
+
+// Per-node T(e) Newton (Appendix, Thermodynamics).  Tguess may be null
+// (use T0).  Writes T, optionally p, and the iteration count.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_thermo(const double *__restrict__ u, int64_t count,
+                                                const double *__restrict__ Tguess, double T0,
+                                                double tol, int maxit, MixC M, double *__restrict__ T,
+                                                double *__restrict__ pout, int *__restrict__ iters,
+                                                unsigned *flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double rs[kNS];
+    double rho = 0.0;
+#pragma unroll
+    for (int s = 0; s < kNS; ++s) {
+        rs[s] = u[s * count + i];
+        rho += rs[s];
+    }
+    double m2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const double m = u[(kNS + c) * count + i];
+        m2 = fma(m, m, m2);
+    }
+    const double rhoe = u[(kNS + DIM) * count + i] - 0.5 * m2 / rho;
+    double t = Tguess ? Tguess[i] : T0;
+    if (!(t > 0.0) || !isfinite(t)) t = T0;
+    const int it = mix_newton(M, rs, rhoe, t, tol, maxit);
+    T[i] = t;
+    if (pout) pout[i] = mix_rR(M, rs) * t;
+    if (iters) iters[i] = it;
+    if (it < 0 || !isfinite(t) || !(t > 0.0)) atomicOr(flags, FLAG_NOCONV);
+}
+
+// Modal shock indicator (Hennemann et al. type, as referenced in
+// Sec. Methodology): eps = rho*p or p, orthonormal Legendre modes by V^-1
+// along each direction, energy ratio of the top modes, logistic map to alpha.
+template <int DIM, int N, bool MIX>
+__global__ void __launch_bounds__(256) k_indicator(RhsParams P, int ind_var, double alpha_max,
+                                                   double alpha_min, double *__restrict__ alpha,
+                                                   double *__restrict__ alpha_raw) {
+    constexpr int N1 = N + 1;
+    constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+    constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
+    int el = tid / NN;
+    const int node = tid - el * NN;
+    const int e = blockIdx.x * P.epb + el;
+    const bool valid = (el < P.epb) && (e < P.nelem);
+    if (el >= P.epb) el = 0;
+    double *x = smem + el * 2 * NN;
+    double *y = x + NN;
+    const size_t stride = (size_t)P.nelem * NN;
+    const size_t gi = (size_t)(valid ? e : 0) * NN + node;
+    if (valid) {
+        double uo[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uo[v] = P.u[v * stride + gi];
+        St<DIM, MIX> s;
+        make_state<DIM, MIX>(uo, MIX ? P.T[gi] : 0.0, P.gamma, P.M, s);
+        x[node] = ind_var == 1 ? s.p : s.rho * s.p;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int d = 0; d < DIM; ++d) {
+        double m = 0.0;
+        if (valid) {
+            const int a = node_pos<N1>(node, d);
+            const int l = node_line<N1, DIM>(node, d);
+#pragma unroll
+            for (int j = 0; j < N1; ++j) m = fma(P.B.Vinv[a * N1 + j], x[line_node<N1, DIM>(d, j, l)], m);
+        }
+        __syncthreads();
+        if (valid) x[node] = m;
+        __syncthreads();
+    }
+    if (valid) {
+        // largest mode index of this coefficient
+        int mx = 0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) mx = max(mx, node_pos<N1>(node, d));
+        y[node] = (double)mx;
+    }
+    __syncthreads();
+    if (valid && node == 0) {
+        double eall = 0.0, e1 = 0.0, e2 = 0.0;
+        for (int n = 0; n < NN; ++n) {
+            const double m2 = x[n] * x[n];
+            const int mx = (int)y[n];
+            eall += m2;
+            if (mx <= N - 1) e1 += m2;
+            if (mx <= N - 2) e2 += m2;
+        }
+        const double E = fmax((eall - e1) / eall, (e1 - e2) / e1);
+        const double thr = 0.5 * pow(10.0, -1.8 * pow((double)N1, 0.25));
+        const double s = log((1.0 - 1e-4) / 1e-4);
+        const double a = 1.0 / (1.0 + exp(-(s / thr) * (E - thr)));
+        alpha_raw[e] = a;
+        alpha[e] = a < alpha_min ? 0.0 : fmin(a, alpha_max);
+    }
+}
+
+// alpha_k <- max(alpha_k, alpha_nbr / 2) over conforming neighbours.
+template <int DIM>
+__global__ void k_alpha_smooth(const int *__restrict__ nbr, int nelem, const double *__restrict__ ain,
+                               double *__restrict__ aout) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nelem) return;
+    double a = ain[e];
+#pragma unroll
+    for (int f = 0; f < 2 * DIM; ++f) {
+        const int nb = nbr[(size_t)e * 2 * DIM + f];
+        if (nb >= 0) a = fmax(a, 0.5 * ain[nb]);
+    }
+    aout[e] = a;
+}
+
+// max_n sum_d (|v.Ja^d| + c |Ja^d|)/J, as an ordered uint64 of a positive double.
+template <int DIM, bool MIX, bool CURV>
+__global__ void k_maxrate(RhsParams P, unsigned long long *out) {
+    constexpr int GA = DIM * DIM + 1;
+    const int NN = P.epb;  // nodes per element passed in epb
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)P.nelem * NN;
+    double rate = 0.0;
+    if (i < total) {
+        const int e = (int)(i / NN);
+        const size_t stride = (size_t)total;
+        constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
+        double uo[NV];
+        for (int v = 0; v < NV; ++v) uo[v] = P.u[v * stride + i];
+        St<DIM, MIX> s;
+        make_state<DIM, MIX>(uo, MIX ? P.T[i] : 0.0, P.gamma, P.M, s);
+        const double J = CURV ? P.Jn[i] : P.geo[(size_t)e * GA + DIM * DIM];
+        for (int d = 0; d < DIM; ++d) {
+            double n[DIM];
+            for (int c = 0; c < DIM; ++c)
+                n[c] = CURV ? P.geo[(d * DIM + c) * stride + i] : P.geo[(size_t)e * GA + d * DIM + c];
+            rate += fabs(dotn<DIM>(s.v, n)) + s.c * sqrt(dotn<DIM>(n, n));
+        }
+        rate /= fabs(J);
+    }
+    // wave reduction then one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) rate = fmax(rate, __shfl_xor(rate, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(rate));
+}
+
+}  // namespace dgx

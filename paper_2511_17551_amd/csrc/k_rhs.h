@@ -1,0 +1,532 @@
+// The fused DGSEM right-hand-side kernel (one or more elements per workgroup).
+//
+// Per element k and node n (Sec. Methodology, Eqs. strong_form,
+// fluxes_discrete_fluxdifferencing, DGvec, fluxes_discrete_with_fv):
+//
+//   du_n = -(1/J_n) { sum_d [ (1-alpha_k) sum_{j != n_d} 2 D_{n_d j} F#(u_n, u_j; nbar)
+//                            + alpha_k (F^FV_{n_d+1} - F^FV_{n_d}) / w_{n_d} ]
+//                    + F*_N / w_N (face xi_d = +1) - F*_0 / w_0 (face xi_d = -1) }
+//          + viscous divergence (BR1) + species sources.
+//
+// The diagonal-free sum is the telescoped subcell flux difference of
+// Eq. DGvec with zero end values (the end values cancel against the strong-
+// form surface terms because 2 D_00 + 1/w_0 = 0).  Each symmetric pair
+// (a < b) of a line is evaluated once and feeds both nodes.
+//
+// Work layout: thread <-> node, EPB elements per workgroup, the element's
+// conserved state, primitives and (curved meshes) metric terms staged in
+// LDS.  Interface fluxes are computed element-centrically by the face nodes
+// of each element, with one normal per face (taken from the element whose
+// xi_d = +1 face it is), so both neighbours obtain bitwise identical fluxes
+// without atomics.
+#pragma once
+
+#include "physics.h"
+
+namespace dgx {
+
+template <int N1, int DIM>
+__device__ __forceinline__ int line_node(int d, int a, int l) {
+    if (d == 0) return a + N1 * l;
+    if (d == 1) return (l % N1) + N1 * a + (DIM == 3 ? N1 * N1 * (l / N1) : 0);
+    return l + N1 * N1 * a;
+}
+template <int N1>
+__device__ __forceinline__ int node_pos(int n, int d) {
+    if (d == 0) return n % N1;
+    if (d == 1) return (n / N1) % N1;
+    return n / (N1 * N1);
+}
+template <int N1, int DIM>
+__device__ __forceinline__ int node_line(int n, int d) {
+    if (d == 0) return n / N1;
+    if (d == 1) return (n % N1) + N1 * (n / (N1 * N1));
+    return n % (N1 * N1);
+}
+// index of pair (a < b) among the N1(N1-1)/2 pairs of a line
+template <int N1>
+__device__ __forceinline__ int pair_index(int a, int b) {
+    return a * N1 - (a * (a + 1)) / 2 + (b - a - 1);
+}
+template <int N1>
+__device__ __forceinline__ void pair_of(int k, int &a, int &b) {
+    a = 0;
+#pragma unroll
+    for (int i = 0; i < N1 - 1; ++i) {
+        const int cnt = N1 - 1 - i;
+        if (k >= cnt && a == i) {
+            k -= cnt;
+            a = i + 1;
+        }
+    }
+    b = a + 1 + k;
+}
+
+template <int DIM, int N, int EQ, int VF, bool CURV>
+struct RhsShape {
+    static constexpr int N1 = N + 1;
+    static constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+    static constexpr int NF = NN / N1;
+    static constexpr bool MIX = EQ >= 2;
+    static constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
+    static constexpr bool EC = VF == 0;
+    static constexpr int NQ = DIM + 3 + (EC ? 3 : 0);  // rho, v, p, c [, beta, ln rho, ln beta]
+    static constexpr int NPL = N1 * N / 2;
+    static constexpr int PD = NF * NPL;
+    static constexpr int NFV = NF * N;
+    static constexpr int B1 = PD * NV;
+    static constexpr int B2 = NFV * NV;
+    static constexpr int B3 = EQ == 1 ? DIM * (DIM + 1) * NN : 0;
+    static constexpr int BUF = B1 > B2 ? (B1 > B3 ? B1 : B3) : (B2 > B3 ? B2 : B3);
+    static constexpr int GEO = CURV ? (DIM * DIM + 1) * NN : 0;
+    static constexpr int SLOT = NV * NN + NQ * NN + GEO + BUF;
+};
+
+template <int DIM, bool MIX, int NQ>
+__device__ __forceinline__ void lds_state(const double *su, const double *sq, int NN, int n,
+                                          St<DIM, MIX> &s) {
+    s.rho = sq[n];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) s.v[c] = sq[(1 + c) * NN + n];
+    s.p = sq[(1 + DIM) * NN + n];
+    s.c = sq[(2 + DIM) * NN + n];
+    if constexpr (MIX) {
+#pragma unroll
+        for (int k = 0; k < kNS; ++k) s.rs[k] = su[k * NN + n];
+        s.rhoE = su[(kNS + DIM) * NN + n];
+    } else {
+        s.rs[0] = 0.0;
+        s.rhoE = su[(1 + DIM) * NN + n];
+    }
+}
+
+template <int DIM, int N, int EQ, int VF, int SF, bool CURV>
+__global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
+    using S = RhsShape<DIM, N, EQ, VF, CURV>;
+    constexpr int N1 = S::N1, NN = S::NN, NF = S::NF, NV = S::NV, NQ = S::NQ;
+    constexpr int NPL = S::NPL, PD = S::PD, NFV = S::NFV;
+    constexpr bool MIX = S::MIX;
+    constexpr int GA = DIM * DIM + 1;
+    extern __shared__ double smem[];
+
+    const int tid = threadIdx.x;
+    int el = tid / NN;
+    const int node = tid - el * NN;
+    const int e = blockIdx.x * P.epb + el;
+    const bool valid = (el < P.epb) && (e < P.nelem);
+    if (el >= P.epb) el = 0;
+    double *su = smem + el * S::SLOT;
+    double *sq = su + NV * NN;
+    double *sJa = sq + NQ * NN;
+    double *sJ = sJa + DIM * DIM * NN;
+    double *buf = sq + NQ * NN + S::GEO;
+    const size_t stride = (size_t)P.nelem * NN;
+    const size_t gi = (size_t)(valid ? e : 0) * NN + node;
+
+    // ---- stage the element: conserved state, geometry, primitives
+    double uo[NV];
+    double Tn = 0.0;
+    if (valid) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            uo[v] = P.u[v * stride + gi];
+            su[v * NN + node] = uo[v];
+        }
+        if constexpr (CURV) {
+#pragma unroll
+            for (int k = 0; k < DIM * DIM; ++k) sJa[k * NN + node] = P.geo[k * stride + gi];
+            sJ[node] = P.Jn[gi];
+        }
+        if constexpr (MIX) Tn = P.T[gi];
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uo[v] = 1.0;
+        if constexpr (MIX) Tn = 1.0;
+    }
+    St<DIM, MIX> own;
+    make_state<DIM, MIX>(uo, Tn, P.gamma, P.M, own);
+    if (valid) {
+        sq[node] = own.rho;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) sq[(1 + c) * NN + node] = own.v[c];
+        sq[(1 + DIM) * NN + node] = own.p;
+        sq[(2 + DIM) * NN + node] = own.c;
+        if constexpr (S::EC) {
+            const double beta = own.rho / own.p;
+            sq[(3 + DIM) * NN + node] = beta;
+            sq[(4 + DIM) * NN + node] = log(own.rho);
+            sq[(5 + DIM) * NN + node] = log(beta);
+        }
+        bool ok = own.rho > 0.0 && own.p > 0.0 && isfinite(own.rhoE) && isfinite(own.p);
+        if constexpr (MIX) {
+#pragma unroll
+            for (int k = 0; k < kNS; ++k) ok = ok && own.rs[k] >= 0.0;
+        }
+        if (!ok) atomicOr(P.flags, FLAG_NONPHYS);
+    }
+    // affine element geometry
+    double Jaf[DIM * DIM];
+    double Jel = 1.0;
+    if constexpr (!CURV) {
+        const double *g = P.geo + (size_t)(valid ? e : 0) * GA;
+#pragma unroll
+        for (int k = 0; k < DIM * DIM; ++k) Jaf[k] = g[k];
+        Jel = g[DIM * DIM];
+    }
+    __syncthreads();
+
+    // ---- high-order volume term: symmetric two-point fluxes along lines
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    const double gm1_inv = 1.0 / (P.gamma - 1.0);
+#pragma unroll 1
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+        for (int r = 0; r < (PD + NN - 1) / NN; ++r) {
+            const int p = r * NN + node;
+            if (valid && p < PD) {
+                const int l = p / NPL;
+                int a, b;
+                pair_of<N1>(p - l * NPL, a, b);
+                const int na = line_node<N1, DIM>(d, a, l);
+                const int nb = line_node<N1, DIM>(d, b, l);
+                double nbar[DIM];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c)
+                    nbar[c] = CURV ? 0.5 * (sJa[(d * DIM + c) * NN + na] + sJa[(d * DIM + c) * NN + nb])
+                                   : Jaf[d * DIM + c];
+                double F[NV];
+                if constexpr (S::EC) {
+                    double vA[DIM], vB[DIM];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        vA[c] = sq[(1 + c) * NN + na];
+                        vB[c] = sq[(1 + c) * NN + nb];
+                    }
+                    ranocha_prims<DIM>(sq[na], vA, sq[(1 + DIM) * NN + na], sq[(3 + DIM) * NN + na],
+                                       sq[(4 + DIM) * NN + na], sq[(5 + DIM) * NN + na], sq[nb], vB,
+                                       sq[(1 + DIM) * NN + nb], sq[(3 + DIM) * NN + nb],
+                                       sq[(4 + DIM) * NN + nb], sq[(5 + DIM) * NN + nb], nbar, gm1_inv, F);
+                } else {
+                    St<DIM, MIX> A, B;
+                    lds_state<DIM, MIX, NQ>(su, sq, NN, na, A);
+                    lds_state<DIM, MIX, NQ>(su, sq, NN, nb, B);
+                    ducros_state<DIM, MIX>(A, B, nbar, F);
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) buf[v * PD + p] = F[v];
+            }
+        }
+        __syncthreads();
+        if (valid) {
+            const int a = node_pos<N1>(node, d);
+            const int l = node_line<N1, DIM>(node, d);
+#pragma unroll
+            for (int b = 0; b < N1; ++b) {
+                if (b == a) continue;
+                const int k = l * NPL + (a < b ? pair_index<N1>(a, b) : pair_index<N1>(b, a));
+                const double coef = 2.0 * P.B.D[a * N1 + b];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[v] = fma(coef, buf[v * PD + k], acc[v]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- first-order subcell finite volumes (elements with alpha > 0)
+    const double alpha = (P.alpha != nullptr && valid) ? P.alpha[e] : 0.0;
+    double accfv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) accfv[v] = 0.0;
+    if (__syncthreads_or(alpha > 0.0)) {
+#pragma unroll 1
+        for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+            for (int r = 0; r < (NFV + NN - 1) / NN; ++r) {
+                const int p = r * NN + node;
+                if (valid && alpha > 0.0 && p < NFV) {
+                    const int l = p / N;
+                    const int m = p - l * N + 1;
+                    const int nL = line_node<N1, DIM>(d, m - 1, l);
+                    const int nR = line_node<N1, DIM>(d, m, l);
+                    double nrm[DIM];
+                    if constexpr (CURV) {
+                        const double *ns = P.nsub + ((((size_t)e * DIM + d) * NF + l) * N + (m - 1)) * DIM;
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) nrm[c] = ns[c];
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) nrm[c] = Jaf[d * DIM + c];
+                    }
+                    St<DIM, MIX> A, B;
+                    lds_state<DIM, MIX, NQ>(su, sq, NN, nL, A);
+                    lds_state<DIM, MIX, NQ>(su, sq, NN, nR, B);
+                    double F[NV];
+                    rusanov<DIM, MIX>(A, B, nrm, F);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) buf[v * NFV + p] = F[v];
+                }
+            }
+            __syncthreads();
+            if (valid && alpha > 0.0) {
+                const int a = node_pos<N1>(node, d);
+                const int l = node_line<N1, DIM>(node, d);
+                const double iw = 1.0 / P.B.w[a];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double hi = a < N ? buf[v * NFV + l * N + a] : 0.0;
+                    const double lo = a > 0 ? buf[v * NFV + l * N + a - 1] : 0.0;
+                    accfv[v] += (hi - lo) * iw;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- interface / boundary Riemann fluxes, element-centric
+    double accs[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) accs[v] = 0.0;
+    if (valid) {
+#pragma unroll 1
+        for (int d = 0; d < DIM; ++d) {
+            const int a = node_pos<N1>(node, d);
+            if (a != 0 && a != N) continue;
+            const int side = (a == N) ? 1 : 0;
+            const int l = node_line<N1, DIM>(node, d);
+            const int nb = P.nbr[(size_t)e * 2 * DIM + 2 * d + side];
+            double nrm[DIM];
+            if constexpr (CURV) {
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) nrm[c] = sJa[(d * DIM + c) * NN + node];
+            } else {
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) nrm[c] = Jaf[d * DIM + c];
+            }
+            St<DIM, MIX> ext;
+            if (nb >= 0) {
+                const int nbn = line_node<N1, DIM>(d, side ? 0 : N, l);
+                const size_t gj = (size_t)nb * NN + nbn;
+                double ue[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) ue[v] = P.u[v * stride + gj];
+                const double Te = MIX ? P.T[gj] : 0.0;
+                make_state<DIM, MIX>(ue, Te, P.gamma, P.M, ext);
+                if (side == 0) {
+                    if constexpr (CURV) {
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(d * DIM + c) * stride + gj];
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(size_t)nb * GA + d * DIM + c];
+                    }
+                }
+            } else {
+                const int bc = -1 - nb;
+                const int kind = P.bc_kind[bc];
+                if (kind == 0) {
+                    double ue[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) ue[v] = P.bc_state[bc * NV + v];
+                    make_state<DIM, MIX>(ue, MIX ? P.bc_T[bc] : 0.0, P.gamma, P.M, ext);
+                } else if (kind == 1) {
+                    ext = own;
+                } else {
+                    const double inn = 1.0 / sqrt(dotn<DIM>(nrm, nrm));
+                    double nh[DIM];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) nh[c] = nrm[c] * inn;
+                    double ue[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) ue[v] = uo[v];
+                    constexpr int off = MIX ? kNS : 1;
+                    double mn = 0.0;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) mn = fma(uo[off + c], nh[c], mn);
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) ue[off + c] = uo[off + c] - 2.0 * mn * nh[c];
+                    make_state<DIM, MIX>(ue, Tn, P.gamma, P.M, ext);
+                }
+            }
+            double F[NV];
+            if constexpr (SF == 0) {
+                if (side) rusanov<DIM, MIX>(own, ext, nrm, F);
+                else rusanov<DIM, MIX>(ext, own, nrm, F);
+            } else {
+                if (side) ranocha_state<DIM, MIX>(own, ext, nrm, P.gamma, F);
+                else ranocha_state<DIM, MIX>(ext, own, nrm, P.gamma, F);
+            }
+            const double sc = side ? 1.0 / P.B.w[N] : -1.0 / P.B.w[0];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) accs[v] = fma(sc, F[v], accs[v]);
+        }
+    }
+
+    const double Jn = CURV ? (valid ? sJ[node] : 1.0) : Jel;
+    const double iJ = 1.0 / Jn;
+    double du[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double tot = (1.0 - alpha) * acc[v] + alpha * accfv[v] + accs[v];
+        du[v] = -tot * iJ;
+    }
+
+    // ---- BR1 viscous divergence (perfect-gas Navier-Stokes, affine elements)
+    if constexpr (EQ == 1) {
+        constexpr int NW = DIM + 1;
+        double Fv[DIM][DIM + 1];  // Fv[c][k]: k < DIM momentum, k = DIM energy
+        auto visc_flux = [&](const double *g, const double *vel, double (*F)[DIM + 1]) {
+            // g[c*NW + w] = d W_w / d x_c
+            double div = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) div += g[k * NW + k];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                double en = 0.0;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    double t = P.mu * (g[c * NW + k] + g[k * NW + c]);
+                    if (k == c) t -= (2.0 / 3.0) * P.mu * div;
+                    F[c][k] = t;
+                    en = fma(t, vel[k], en);
+                }
+                F[c][DIM] = en + P.kappa * g[c * NW + DIM];
+            }
+        };
+        double g[DIM * NW];
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                for (int w = 0; w < NW; ++w) g[c * NW + w] = P.grad[(size_t)(c * NW + w) * stride + gi];
+        } else {
+#pragma unroll
+            for (int k = 0; k < DIM * NW; ++k) g[k] = 0.0;
+        }
+        visc_flux(g, own.v, Fv);
+        double Ft[DIM][DIM + 1];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) s = fma(Jaf[d * DIM + c], Fv[c][k], s);
+                Ft[d][k] = s;
+                if (valid) buf[(d * NW + k) * NN + node] = s;
+            }
+        __syncthreads();
+        if (valid) {
+            double vis[NW];
+#pragma unroll
+            for (int k = 0; k < NW; ++k) vis[k] = 0.0;
+#pragma unroll 1
+            for (int d = 0; d < DIM; ++d) {
+                const int a = node_pos<N1>(node, d);
+                const int l = node_line<N1, DIM>(node, d);
+#pragma unroll
+                for (int j = 0; j < N1; ++j) {
+                    const double Dj = P.B.D[a * N1 + j];
+                    const int nj = line_node<N1, DIM>(d, j, l);
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) vis[k] = fma(Dj, buf[(d * NW + k) * NN + nj], vis[k]);
+                }
+                if (a == 0 || a == N) {
+                    const int side = (a == N) ? 1 : 0;
+                    const int nb = P.nbr[(size_t)e * 2 * DIM + 2 * d + side];
+                    const int nbn = line_node<N1, DIM>(d, side ? 0 : N, l);
+                    const size_t gj = (size_t)nb * NN + nbn;
+                    double gn[DIM * NW];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                        for (int w = 0; w < NW; ++w) gn[c * NW + w] = P.grad[(size_t)(c * NW + w) * stride + gj];
+                    const double irn = 1.0 / P.u[gj];
+                    double vn[DIM];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) vn[c] = P.u[(1 + c) * stride + gj] * irn;
+                    double Fn[DIM][DIM + 1];
+                    visc_flux(gn, vn, Fn);
+                    double nrm[DIM];
+                    if (side) {
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) nrm[c] = Jaf[d * DIM + c];
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(size_t)nb * GA + d * DIM + c];
+                    }
+                    const double sc = side ? 1.0 / P.B.w[N] : -1.0 / P.B.w[0];
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) {
+                        double fo = 0.0, fn = 0.0;
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) {
+                            fo = fma(Fv[c][k], nrm[c], fo);
+                            fn = fma(Fn[c][k], nrm[c], fn);
+                        }
+                        const double fs = 0.5 * (fo + fn);
+                        vis[k] = fma(sc, fs - Ft[d][k], vis[k]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NW; ++k) du[1 + k] += vis[k] * iJ;
+        }
+    }
+
+    // ---- finite-rate chemistry source
+    if constexpr (EQ == 3) {
+        if (valid) {
+            const KinC &K = *P.kin;
+            const double T = Tn;
+            const double lnT = log(T);
+            const double iT = 1.0 / T;
+            double gRT[kNS], conc[kNS];
+#pragma unroll
+            for (int s = 0; s < kNS; ++s) {
+                double g = K.gconst[s] - (2.5 + P.M.mol[s]) * lnT + P.M.e0[s] * iT / P.M.Rs[s];
+                if (P.M.mol[s]) g += log(-expm1(-P.M.thv[s] * iT));
+                gRT[s] = g;
+                conc[s] = own.rs[s] / K.W[s];
+            }
+            double wdot[kNS];
+#pragma unroll
+            for (int s = 0; s < kNS; ++s) wdot[s] = 0.0;
+            const double lnpr = K.lnpref_Ru - lnT;
+            for (int r = 0; r < K.nr; ++r) {
+                double lnK = K.dnu_sum[r] * lnpr;
+                double fw = 1.0, bw = 1.0;
+#pragma unroll
+                for (int s = 0; s < kNS; ++s) {
+                    const int nu = K.nu[r][s], nup = K.nup[r][s];
+                    lnK -= (double)(nup - nu) * gRT[s];
+                    for (int q = 0; q < nu; ++q) fw *= conc[s];
+                    for (int q = 0; q < nup; ++q) bw *= conc[s];
+                }
+                const double kf = K.A[r] * pow(T, K.b[r]) * exp(-K.tha[r] * iT);
+                const double kb = kf / exp(lnK);
+                const double R = kf * fw - kb * bw;
+#pragma unroll
+                for (int s = 0; s < kNS; ++s) wdot[s] = fma((double)(K.nup[r][s] - K.nu[r][s]), R, wdot[s]);
+            }
+#pragma unroll
+            for (int s = 0; s < kNS; ++s) du[s] += K.W[s] * wdot[s];
+        }
+    }
+
+    if (valid) {
+        if (mode == 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) P.out[v * stride + gi] = du[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double base = P.sa != 0.0 ? P.sa * P.u0[v * stride + gi] : 0.0;
+                P.out[v * stride + gi] = base + P.sb * (uo[v] + P.dt * du[v]);
+            }
+        }
+    }
+}
+
+}  // namespace dgx

@@ -1,0 +1,246 @@
+// Device-side closures and fluxes of the DGSEM right-hand side.
+//
+// Physical flux: Sec. Governing Equations, Eq. adevctive_flux.
+// Two-point fluxes (Sec. Methodology, Eqs. fluxdiffcons and conssymm):
+//   * Ranocha's entropy-conservative, kinetic-energy-preserving flux for the
+//     perfect gas (logarithmic means of rho and rho/p);
+//   * the Ducros split form (perfect gas or mixture).
+// Riemann flux at faces and subcell interfaces (Eqs. riemann_problem1-3,
+// finitevolumeflux): local Lax-Friedrichs with the wave-speed bound
+// max(|v_L.n| + c_L|n|, |v_R.n| + c_R|n|).
+// Mixture closures: Appendix, Thermodynamics (RRHO energies without the
+// electronic mode) and Governing Equations, Eqs. internal_energies, eos.
+#pragma once
+
+#include "dgx_internal.h"
+
+namespace dgx {
+
+template <int DIM>
+__device__ __forceinline__ double dotn(const double *a, const double *b) {
+    double s = a[0] * b[0];
+#pragma unroll
+    for (int c = 1; c < DIM; ++c) s = fma(a[c], b[c], s);
+    return s;
+}
+
+// Primitive state of one node.  For the perfect gas rs[0] is unused.
+template <int DIM, bool MIX>
+struct St {
+    double rho, v[DIM], p, rhoE, c;
+    double rs[MIX ? kNS : 1];
+};
+
+// Logarithmic mean and its reciprocal from the values and their logs:
+// (y - x)/ln(y/x), with a 4-term series in z = ((x-y)/(x+y))^2 when z < 1e-4.
+__device__ __forceinline__ void ln_mean_pair(double x, double y, double lx, double ly,
+                                             double &mean, double &inv_mean) {
+    const double s = x + y;
+    const double d = y - x;
+    const double q = d / s;
+    const double z = q * q;
+    if (z < 1e-4) {
+        const double P = 2.0 + z * (2.0 / 3.0 + z * (2.0 / 5.0 + z * (2.0 / 7.0)));
+        mean = s / P;
+        inv_mean = P / s;
+    } else {
+        const double dl = ly - lx;
+        mean = d / dl;
+        inv_mean = dl / d;
+    }
+}
+
+// ---------------------------------------------------------------- mixture
+__device__ __forceinline__ void mix_energy_cv(const MixC &M, const double *rs, double T,
+                                              double &rhoe, double &rhocv) {
+    double e = 0.0, cv = 0.0;
+#pragma unroll
+    for (int s = 0; s < kNS; ++s) {
+        double es = 1.5 * M.Rs[s] * T + M.e0[s];
+        double cs = 1.5 * M.Rs[s];
+        if (M.mol[s]) {
+            const double x = M.thv[s] / T;
+            const double em1 = expm1(x);
+            es += M.Rs[s] * T + M.Rs[s] * M.thv[s] / em1;
+            cs += M.Rs[s] + M.Rs[s] * x * x * (em1 + 1.0) / (em1 * em1);
+        }
+        e = fma(rs[s], es, e);
+        cv = fma(rs[s], cs, cv);
+    }
+    rhoe = e;
+    rhocv = cv;
+}
+
+// Newton iteration on sum rho_s e_s(T) = rho e, from T0; returns iterations,
+// or -1 if maxit was reached.
+__device__ __forceinline__ int mix_newton(const MixC &M, const double *rs, double rhoe_target,
+                                          double &T, double tol, int maxit) {
+    for (int it = 1; it <= maxit; ++it) {
+        double f, fp;
+        mix_energy_cv(M, rs, T, f, fp);
+        const double dT = (f - rhoe_target) / fp;
+        T -= dT;
+        if (fabs(dT) <= tol * fabs(T)) return it;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ double mix_rR(const MixC &M, const double *rs) {
+    double r = 0.0;
+#pragma unroll
+    for (int s = 0; s < kNS; ++s) r = fma(rs[s], M.Rs[s], r);
+    return r;
+}
+
+// Frozen sound speed sqrt(gamma_f p / rho), gamma_f = 1 + sum rho_s R_s / sum rho_s cv_s.
+__device__ __forceinline__ double mix_sound(const MixC &M, const double *rs, double rho, double T) {
+    double cv = 0.0;
+#pragma unroll
+    for (int s = 0; s < kNS; ++s) {
+        double cs = 1.5 * M.Rs[s];
+        if (M.mol[s]) {
+            const double x = M.thv[s] / T;
+            const double em1 = expm1(x);
+            cs += M.Rs[s] + M.Rs[s] * x * x * (em1 + 1.0) / (em1 * em1);
+        }
+        cv = fma(rs[s], cs, cv);
+    }
+    const double rR = mix_rR(M, rs);
+    const double g = 1.0 + rR / cv;
+    return sqrt(g * rR * T / rho);
+}
+
+// State of a node from its conserved vector (and T for a mixture).
+template <int DIM, bool MIX>
+__device__ __forceinline__ void make_state(const double *u, double T, double gamma, const MixC &M,
+                                           St<DIM, MIX> &s) {
+    if constexpr (MIX) {
+        double rho = 0.0;
+#pragma unroll
+        for (int k = 0; k < kNS; ++k) {
+            s.rs[k] = u[k];
+            rho += u[k];
+        }
+        s.rho = rho;
+        const double ir = 1.0 / rho;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) s.v[c] = u[kNS + c] * ir;
+        s.rhoE = u[kNS + DIM];
+        const double rR = mix_rR(M, s.rs);
+        s.p = rR * T;
+        s.c = mix_sound(M, s.rs, rho, T);
+    } else {
+        s.rho = u[0];
+        const double ir = 1.0 / u[0];
+        double v2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            s.v[c] = u[1 + c] * ir;
+            v2 = fma(s.v[c], s.v[c], v2);
+        }
+        s.rhoE = u[1 + DIM];
+        s.p = (gamma - 1.0) * (s.rhoE - 0.5 * s.rho * v2);
+        s.c = sqrt(gamma * s.p / s.rho);
+        s.rs[0] = 0.0;
+    }
+}
+
+// f(u).n
+template <int DIM, bool MIX>
+__device__ __forceinline__ void phys_flux(const St<DIM, MIX> &s, const double *n, double *f) {
+    const double vn = dotn<DIM>(s.v, n);
+    constexpr int off = MIX ? kNS : 1;
+    if constexpr (MIX) {
+#pragma unroll
+        for (int k = 0; k < kNS; ++k) f[k] = s.rs[k] * vn;
+    } else {
+        f[0] = s.rho * vn;
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) f[off + c] = s.rho * s.v[c] * vn + s.p * n[c];
+    f[off + DIM] = (s.rhoE + s.p) * vn;
+}
+
+template <int DIM, bool MIX>
+__device__ __forceinline__ void cons_of(const St<DIM, MIX> &s, double *u) {
+    constexpr int off = MIX ? kNS : 1;
+    if constexpr (MIX) {
+#pragma unroll
+        for (int k = 0; k < kNS; ++k) u[k] = s.rs[k];
+    } else {
+        u[0] = s.rho;
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) u[off + c] = s.rho * s.v[c];
+    u[off + DIM] = s.rhoE;
+}
+
+template <int DIM, bool MIX>
+__device__ __forceinline__ void rusanov(const St<DIM, MIX> &L, const St<DIM, MIX> &R,
+                                        const double *n, double *F) {
+    constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
+    const double nn = sqrt(dotn<DIM>(n, n));
+    const double lam = fmax(fabs(dotn<DIM>(L.v, n)) + L.c * nn, fabs(dotn<DIM>(R.v, n)) + R.c * nn);
+    double fL[NV], fR[NV], uL[NV], uR[NV];
+    phys_flux<DIM, MIX>(L, n, fL);
+    phys_flux<DIM, MIX>(R, n, fR);
+    cons_of<DIM, MIX>(L, uL);
+    cons_of<DIM, MIX>(R, uR);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) F[k] = 0.5 * (fL[k] + fR[k]) - 0.5 * lam * (uR[k] - uL[k]);
+}
+
+// Ranocha flux from primitive values (perfect gas).
+template <int DIM>
+__device__ __forceinline__ void ranocha_prims(double rL, const double *vL, double pL, double bL,
+                                              double lrL, double lbL, double rR, const double *vR,
+                                              double pR, double bR, double lrR, double lbR,
+                                              const double *n, double gm1_inv, double *F) {
+    double rho_hat, irho_hat, beta_hat, ibeta_hat;
+    ln_mean_pair(rL, rR, lrL, lrR, rho_hat, irho_hat);
+    ln_mean_pair(bL, bR, lbL, lbR, beta_hat, ibeta_hat);
+    double vbar[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) vbar[c] = 0.5 * (vL[c] + vR[c]);
+    const double pbar = 0.5 * (pL + pR);
+    const double q = 0.5 * dotn<DIM>(vL, vR);
+    const double frho = rho_hat * dotn<DIM>(vbar, n);
+    F[0] = frho;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) F[1 + c] = frho * vbar[c] + pbar * n[c];
+    F[1 + DIM] = frho * (q + gm1_inv * ibeta_hat) + 0.5 * (pL * dotn<DIM>(vR, n) + pR * dotn<DIM>(vL, n));
+}
+
+template <int DIM, bool MIX>
+__device__ __forceinline__ void ranocha_state(const St<DIM, MIX> &L, const St<DIM, MIX> &R,
+                                              const double *n, double gamma, double *F) {
+    const double bL = L.rho / L.p, bR = R.rho / R.p;
+    ranocha_prims<DIM>(L.rho, L.v, L.p, bL, log(L.rho), log(bL), R.rho, R.v, R.p, bR, log(R.rho),
+                       log(bR), n, 1.0 / (gamma - 1.0), F);
+}
+
+// Ducros split-form flux: {{rho_s}} {{v}}.n, {{m}} {{v}}.n + {{p}} n, ({{rhoE}} + {{p}}) {{v}}.n
+template <int DIM, bool MIX>
+__device__ __forceinline__ void ducros_state(const St<DIM, MIX> &L, const St<DIM, MIX> &R,
+                                             const double *n, double *F) {
+    double vb[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) vb[c] = 0.5 * (L.v[c] + R.v[c]);
+    const double vn = dotn<DIM>(vb, n);
+    const double pbar = 0.5 * (L.p + R.p);
+    constexpr int off = MIX ? kNS : 1;
+    if constexpr (MIX) {
+#pragma unroll
+        for (int k = 0; k < kNS; ++k) F[k] = 0.5 * (L.rs[k] + R.rs[k]) * vn;
+    } else {
+        F[0] = 0.5 * (L.rho + R.rho) * vn;
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const double mbar = 0.5 * (L.rho * L.v[c] + R.rho * R.v[c]);
+        F[off + c] = mbar * vn + pbar * n[c];
+    }
+    F[off + DIM] = (0.5 * (L.rhoE + R.rhoE) + pbar) * vn;
+}
+
+}  // namespace dgx
