@@ -223,6 +223,29 @@ int dgx_check(dgx_ctx *ctx, void *stream);
  * states).  e, cv: host [5]. */
 int dgx_species_energy(const dgx_ctx *ctx, double T, double *e, double *cv);
 
+/* Kernel timing for profiling: enqueue `reps` evaluations of the
+ * right-hand side in the fused stage form used by dgx_ssprk3_step
+ * (out = 3/4 u + 1/4 (u + dt du), into library scratch; u is not modified),
+ * bracketing every kernel with HIP events on `stream`.  ms_out[k] receives
+ * the average duration of kernel k in launch order, names_out (may be NULL)
+ * a comma-separated list of the kernel names (buffer of names_len bytes);
+ * *nk the number of kernels (<= 8).  Synchronises. */
+int dgx_kernel_times(dgx_ctx *ctx, const double *u, int reps, double *ms_out, int *nk,
+                     char *names_out, size_t names_len, void *stream);
+
+/* Autotuner: time the right-hand side for each elements-per-workgroup
+ * candidate in {1, 2, 4, 8} that fits (<= 512 threads, <= 64 KB LDS) over
+ * `reps` launches each (HIP events on `stream`; u is read, not modified) and
+ * keep the fastest.  The winner is cached process-wide under the key
+ * (dim, N, equation, fluxes, geometry kind, element count) and reused by
+ * later dgx_set_mesh calls with the same key.  *epb_out (may be NULL)
+ * receives the choice, ms_out (may be NULL, [4]) the candidates' average
+ * milliseconds (-1 = not run).  Synchronises. */
+int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *ms_out, void *stream);
+
+/* Force the elements per workgroup (1, 2, 4 or 8; must fit as above). */
+int dgx_set_launch(dgx_ctx *ctx, int epb);
+
 /* Text of the last error on this context (never NULL). */
 const char *dgx_last_error(const dgx_ctx *ctx);
 

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <climits>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -152,6 +154,13 @@ int dalloc(dgx_ctx *ctx, DevBuf<T> &b, size_t n) {
 
 int threads_for(int nn, int epb) { return ((nn * epb + 63) / 64) * 64; }
 
+// process-wide autotuner cache: configuration key -> elements per workgroup
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+
+std::string tune_key(const dgx_ctx *ctx);
+bool epb_fits(const dgx_ctx *ctx, int epb);
+
 void clear_graph(dgx_ctx *ctx) {
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
@@ -238,12 +247,26 @@ int enqueue_thermo_mesh(dgx_ctx *ctx, const double *u, hipStream_t s) {
 
 // Everything of one right-hand-side evaluation.  mode 0: out = du;
 // mode 1: out = sa*u0 + sb*(u + dt*du).
+struct EventTape {
+    hipEvent_t ev[9];
+    const char *name[8];
+    int n = 0;  // kernels recorded
+};
+
+void tape_mark(EventTape *tp, const char *name, hipStream_t s) {
+    if (!tp || tp->n >= 8) return;
+    tp->name[tp->n] = name;
+    (void)hipEventRecord(tp->ev[++tp->n], s);
+}
+
 int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const double *u0, double sa, double sb,
-                double dt, hipStream_t s) {
+                double dt, hipStream_t s, EventTape *tp = nullptr) {
     const dgx_config &c = ctx->cfg;
+    if (tp) (void)hipEventRecord(tp->ev[0], s);
     if (is_mix(ctx)) {
         int rc = enqueue_thermo_mesh(ctx, u, s);
         if (rc) return set_err(ctx, rc, "thermo launch failed");
+        tape_mark(tp, "k_thermo", s);
     }
     RhsParams P = base_params(ctx);
     P.u = u;
@@ -270,6 +293,7 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
                            s);
         }
         P.alpha = ctx->alpha.p;
+        tape_mark(tp, "k_indicator", s);
     }
     if (c.equation == DGX_EQ_NS) {
         RhsParams G = P;
@@ -279,6 +303,7 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
         else if (c.dim == 3 && c.N == 4) grad_launch<3, 4>(G, blocks, th, lds, s);
         else if (c.dim == 2 && c.N == 3) grad_launch<2, 3>(G, blocks, th, lds, s);
         else return set_err(ctx, DGX_E_INVAL, "NS gradients not built for this dim/N");
+        tape_mark(tp, "k_grad", s);
     }
     P.out = out;
     P.u0 = u0;
@@ -286,9 +311,23 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
     P.sb = sb;
     P.dt = dt;
     ctx->rhs->fn(P, mode, blocks, th, (size_t)epb * ctx->rhs->slot * sizeof(double), s);
+    tape_mark(tp, "k_rhs", s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_err(ctx, DGX_E_DEVICE, std::string("rhs launch: ") + hipGetErrorString(e));
     return DGX_OK;
+}
+
+std::string tune_key(const dgx_ctx *ctx) {
+    const dgx_config &c = ctx->cfg;
+    return std::to_string(c.dim) + "," + std::to_string(c.N) + "," + std::to_string(c.equation) + "," +
+           std::to_string(c.volume_flux) + "," + std::to_string(c.surface_flux) + "," + std::to_string(ctx->curved) +
+           "," + std::to_string(ctx->nelem);
+}
+
+bool epb_fits(const dgx_ctx *ctx, int epb) {
+    if (epb < 1 || epb > 8 || !ctx->rhs) return false;
+    if (threads_for(ctx->nn, epb) > 512) return false;
+    return (size_t)epb * ctx->rhs->slot * sizeof(double) <= 64 * 1024;
 }
 
 int check_ctx(dgx_ctx *ctx) {
@@ -543,10 +582,16 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         if ((rc = dalloc(ctx, ctx->kin_d, 1))) return rc;
         HIPCHK(hipMemcpy(ctx->kin_d.p, &ctx->kin, sizeof(KinC), hipMemcpyHostToDevice));
     }
-    // default elements per block: about 256 threads, LDS <= 64 KB
+    // default elements per block: about 256 threads, LDS <= 64 KB; a cached
+    // autotuner choice for this configuration wins
     int epb = std::max(1, 256 / nn);
     while (epb > 1 && (size_t)epb * sel->slot * sizeof(double) > 64 * 1024) --epb;
     ctx->epb = epb;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(tune_key(ctx));
+        if (it != g_tune.end() && epb_fits(ctx, it->second)) ctx->epb = it->second;
+    }
     ctx->mesh_ok = true;
     return DGX_OK;
 }
@@ -761,6 +806,96 @@ int dgx_surrogate_predict(dgx_ctx *ctx, const double *states, int64_t count, dou
     if (!ctx->sur.ready) return set_err(ctx, DGX_E_STATE, "surrogate has no weights");
     int rc = surrogate_predict(ctx->sur, ctx->cfg.dim, states, count, Tg, (hipStream_t)stream);
     return rc ? set_err(ctx, rc, "surrogate launch failed") : DGX_OK;
+}
+
+int dgx_kernel_times(dgx_ctx *ctx, const double *u, int reps, double *ms_out, int *nk, char *names_out,
+                     size_t names_len, void *stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!u || reps < 1 || !ms_out || !nk) return set_err(ctx, DGX_E_INVAL, "bad kernel_times arguments");
+    const size_t n = (size_t)ctx->nvar * ctx->nelem * ctx->nn;
+    if ((rc = dalloc(ctx, ctx->u2, n))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<EventTape> tapes(reps);
+    for (auto &t : tapes)
+        for (auto &e : t.ev) HIPCHK(hipEventCreate(&e));
+    for (int r = 0; r < reps && !rc; ++r)
+        rc = enqueue_rhs(ctx, u, ctx->u2.p, 1, u, 0.75, 0.25, 1e-6, s, &tapes[r]);
+    HIPCHK(hipStreamSynchronize(s));
+    const int k = tapes[0].n;
+    for (int i = 0; i < k; ++i) {
+        double tot = 0.0;
+        for (int r = 0; r < reps; ++r) {
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, tapes[r].ev[i], tapes[r].ev[i + 1]));
+            tot += ms;
+        }
+        ms_out[i] = tot / reps;
+    }
+    *nk = k;
+    if (names_out && names_len) {
+        std::string all;
+        for (int i = 0; i < k; ++i) all += (i ? "," : "") + std::string(tapes[0].name[i]);
+        std::snprintf(names_out, names_len, "%s", all.c_str());
+    }
+    for (auto &t : tapes)
+        for (auto &e : t.ev) (void)hipEventDestroy(e);
+    return rc;
+}
+
+int dgx_set_launch(dgx_ctx *ctx, int epb) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!epb_fits(ctx, epb)) return set_err(ctx, DGX_E_INVAL, "elements per workgroup does not fit");
+    if (epb != ctx->epb) clear_graph(ctx);
+    ctx->epb = epb;
+    return DGX_OK;
+}
+
+int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *ms_out, void *stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!u || reps < 1) return set_err(ctx, DGX_E_INVAL, "bad autotune arguments");
+    const size_t n = (size_t)ctx->nvar * ctx->nelem * ctx->nn;
+    if ((rc = dalloc(ctx, ctx->u2, n))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int cand[4] = {1, 2, 4, 8};
+    const int saved = ctx->epb;
+    int best = saved;
+    double best_ms = 1e300;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int i = 0; i < 4; ++i) {
+        if (ms_out) ms_out[i] = -1.0;
+        if (!epb_fits(ctx, cand[i])) continue;
+        ctx->epb = cand[i];
+        for (int w = 0; w < 2 && !rc; ++w) rc = enqueue_rhs(ctx, u, ctx->u2.p, 1, u, 0.75, 0.25, 1e-6, s);
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && !rc; ++r) rc = enqueue_rhs(ctx, u, ctx->u2.p, 1, u, 0.75, 0.25, 1e-6, s);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = set_err(ctx, DGX_E_DEVICE, "autotune sync failed");
+        if (rc) break;
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double avg = ms / reps;
+        if (ms_out) ms_out[i] = avg;
+        if (avg < best_ms) {
+            best_ms = avg;
+            best = cand[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->epb = rc ? saved : best;
+    if (ctx->epb != saved) clear_graph(ctx);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(ctx)] = best;
+    }
+    if (epb_out) *epb_out = best;
+    return DGX_OK;
 }
 
 const char *dgx_last_error(const dgx_ctx *ctx) {

@@ -9,9 +9,11 @@ namespace dgx {
 // BR1 gradients of W = (v, T), T = p/(rho R)  (Sec. Methodology, Viscous
 // Fluxes, Eqs. auxil and auxstrongf with the interface value
 // W* = (W_own + W_nbr)/2; affine elements, strong form
-// q = (1/J) sum_d Ja^d [D_d W + lift(W* - W)]).
+// q = (1/J) sum_d Ja^d [D_d W + lift(W* - W)]), followed by the nodal viscous
+// flux F_v[c] = (tau_{.c}, (tau v)_c + kappa dT/dx_c) (Appendix, Transport,
+// Eq. stress with zero bulk viscosity), written to P.out as [dim][dim+1][E][nn].
 template <int DIM, int N>
-__global__ void __launch_bounds__(256) k_grad(RhsParams P) {
+__global__ void __launch_bounds__(512) k_grad(RhsParams P) {
     constexpr int N1 = N + 1;
     constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
     constexpr int NV = DIM + 2;
@@ -27,7 +29,6 @@ __global__ void __launch_bounds__(256) k_grad(RhsParams P) {
     double *sw = smem + el * NW * NN;
     const size_t stride = (size_t)P.nelem * NN;
     const size_t gi = (size_t)(valid ? e : 0) * NN + node;
-    const double Rinv = 1.0 / P.R;
 
     auto prim = [&](const double *u, double *W) {
         const double ir = 1.0 / u[0];
@@ -51,14 +52,13 @@ __global__ void __launch_bounds__(256) k_grad(RhsParams P) {
     }
     __syncthreads();
     if (!valid) return;
-    (void)Rinv;
     const double *g = P.geo + (size_t)e * GA;
     double q[DIM][NW];
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
 #pragma unroll
         for (int w = 0; w < NW; ++w) q[c][w] = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int d = 0; d < DIM; ++d) {
         const int a = node_pos<N1>(node, d);
         const int l = node_line<N1, DIM>(node, d);
@@ -97,7 +97,22 @@ __global__ void __launch_bounds__(256) k_grad(RhsParams P) {
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
 #pragma unroll
-        for (int w = 0; w < NW; ++w) P.out[(size_t)(c * NW + w) * stride + gi] = q[c][w] * iJ;
+        for (int w = 0; w < NW; ++w) q[c][w] *= iJ;
+    double div = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) div += q[k][k];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        double en = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double t = P.mu * (q[c][k] + q[k][c]);
+            if (k == c) t -= (2.0 / 3.0) * P.mu * div;
+            en = fma(t, Wo[k], en);
+            P.out[(size_t)(c * NW + k) * stride + gi] = t;
+        }
+        P.out[(size_t)(c * NW + DIM) * stride + gi] = en + P.kappa * q[c][DIM];
+    }
 }
 
 // Per-node T(e) Newton (Appendix, Thermodynamics).  Tguess may be null
@@ -137,7 +152,7 @@ __global__ void __launch_bounds__(256) k_thermo(const double *__restrict__ u, in
 // Sec. Methodology): eps = rho*p or p, orthonormal Legendre modes by V^-1
 // along each direction, energy ratio of the top modes, logistic map to alpha.
 template <int DIM, int N, bool MIX>
-__global__ void __launch_bounds__(256) k_indicator(RhsParams P, int ind_var, double alpha_max,
+__global__ void __launch_bounds__(512) k_indicator(RhsParams P, int ind_var, double alpha_max,
                                                    double alpha_min, double *__restrict__ alpha,
                                                    double *__restrict__ alpha_raw) {
     constexpr int N1 = N + 1;

@@ -14,11 +14,12 @@
 // (a < b) of a line is evaluated once and feeds both nodes.
 //
 // Work layout: thread <-> node, EPB elements per workgroup, the element's
-// conserved state, primitives and (curved meshes) metric terms staged in
-// LDS.  Interface fluxes are computed element-centrically by the face nodes
-// of each element, with one normal per face (taken from the element whose
-// xi_d = +1 face it is), so both neighbours obtain bitwise identical fluxes
-// without atomics.
+// primitives (and, for mixtures, the species densities; on curved meshes
+// the metric terms) staged in LDS.  Face work (Riemann fluxes, viscous
+// interface fluxes) is spread evenly over the element's threads, one item per
+// face node, with one normal per face (from the element whose xi_d = +1 face
+// it is) so both neighbours compute bitwise identical interface fluxes and
+// no atomics are needed.
 #pragma once
 
 #include "physics.h"
@@ -69,44 +70,69 @@ struct RhsShape {
     static constexpr int NF = NN / N1;
     static constexpr bool MIX = EQ >= 2;
     static constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
+    static constexpr int NW = DIM + 1;  // viscous flux components (momentum, energy)
     static constexpr bool EC = VF == 0;
-    static constexpr int NQ = DIM + 3 + (EC ? 3 : 0);  // rho, v, p, c [, beta, ln rho, ln beta]
+    // primitives: rho, v, p, rhoE [, c (mixture)] [, beta, ln rho, ln beta (EC)]
+    static constexpr int NQ = DIM + 3 + (MIX ? 1 : 0) + (EC ? 3 : 0);
+    static constexpr int SU = MIX ? kNS * NN : 0;  // species densities
     static constexpr int NPL = N1 * N / 2;
-    static constexpr int PD = NF * NPL;
-    static constexpr int NFV = NF * N;
+    static constexpr int PD = NF * NPL;      // pairs per direction
+    static constexpr int NFV = NF * N;       // interior subcell interfaces per direction
+    static constexpr int NSF = 2 * DIM * NF; // face nodes
     static constexpr int B1 = PD * NV;
     static constexpr int B2 = NFV * NV;
-    static constexpr int B3 = EQ == 1 ? DIM * (DIM + 1) * NN : 0;
-    static constexpr int BUF = B1 > B2 ? (B1 > B3 ? B1 : B3) : (B2 > B3 ? B2 : B3);
+    static constexpr int B3 = NSF * NV;
+    static constexpr int B4 = EQ == 1 ? NW * NN : 0;
+    static constexpr int B5 = EQ == 1 ? NSF * NW : 0;
+    static constexpr int M12 = B1 > B2 ? B1 : B2;
+    static constexpr int M34 = B3 > B4 ? B3 : B4;
+    static constexpr int M345 = M34 > B5 ? M34 : B5;
+    static constexpr int BUF = M12 > M345 ? M12 : M345;
     static constexpr int GEO = CURV ? (DIM * DIM + 1) * NN : 0;
-    static constexpr int SLOT = NV * NN + NQ * NN + GEO + BUF;
+    static constexpr int SLOT = SU + NQ * NN + GEO + BUF;
 };
 
-template <int DIM, bool MIX, int NQ>
-__device__ __forceinline__ void lds_state(const double *su, const double *sq, int NN, int n,
+// nrm = Jaf[d][:] for a runtime direction d without dynamic indexing of a
+// private array (which would live in scratch memory).
+template <int DIM>
+__device__ __forceinline__ void jaf_row(const double *Jaf, int d, double *nrm) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) nrm[c] = Jaf[c];
+#pragma unroll
+    for (int dd = 1; dd < DIM; ++dd)
+        if (d == dd) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) nrm[c] = Jaf[dd * DIM + c];
+        }
+}
+
+// Node state from the LDS primitives (and species densities).
+template <int DIM, bool MIX>
+__device__ __forceinline__ void lds_state(const double *su, const double *sq, int NN, int n, double gamma,
                                           St<DIM, MIX> &s) {
     s.rho = sq[n];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) s.v[c] = sq[(1 + c) * NN + n];
     s.p = sq[(1 + DIM) * NN + n];
-    s.c = sq[(2 + DIM) * NN + n];
+    s.rhoE = sq[(2 + DIM) * NN + n];
     if constexpr (MIX) {
+        s.c = sq[(3 + DIM) * NN + n];
 #pragma unroll
         for (int k = 0; k < kNS; ++k) s.rs[k] = su[k * NN + n];
-        s.rhoE = su[(kNS + DIM) * NN + n];
     } else {
+        s.c = sqrt(gamma * s.p * rcp(s.rho));
         s.rs[0] = 0.0;
-        s.rhoE = su[(1 + DIM) * NN + n];
     }
 }
 
 template <int DIM, int N, int EQ, int VF, int SF, bool CURV>
-__global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
+__global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     using S = RhsShape<DIM, N, EQ, VF, CURV>;
-    constexpr int N1 = S::N1, NN = S::NN, NF = S::NF, NV = S::NV, NQ = S::NQ;
-    constexpr int NPL = S::NPL, PD = S::PD, NFV = S::NFV;
+    constexpr int N1 = S::N1, NN = S::NN, NF = S::NF, NV = S::NV, NQ = S::NQ, NW = S::NW;
+    constexpr int NPL = S::NPL, PD = S::PD, NFV = S::NFV, NSF = S::NSF;
     constexpr bool MIX = S::MIX;
     constexpr int GA = DIM * DIM + 1;
+    constexpr int QB = DIM + 3 + (MIX ? 1 : 0);  // first EC slot in sq
     extern __shared__ double smem[];
 
     const int tid = threadIdx.x;
@@ -116,53 +142,57 @@ __global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
     const bool valid = (el < P.epb) && (e < P.nelem);
     if (el >= P.epb) el = 0;
     double *su = smem + el * S::SLOT;
-    double *sq = su + NV * NN;
+    double *sq = su + S::SU;
     double *sJa = sq + NQ * NN;
     double *sJ = sJa + DIM * DIM * NN;
     double *buf = sq + NQ * NN + S::GEO;
     const size_t stride = (size_t)P.nelem * NN;
     const size_t gi = (size_t)(valid ? e : 0) * NN + node;
+    const double gamma = P.gamma;
 
-    // ---- stage the element: conserved state, geometry, primitives
-    double uo[NV];
-    double Tn = 0.0;
-    if (valid) {
+    // ---- stage the element: primitives (+ species, metric terms)
+    {
+        double uo[NV];
+        double Tn = 1.0;
+        if (valid) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            uo[v] = P.u[v * stride + gi];
-            su[v * NN + node] = uo[v];
+            for (int v = 0; v < NV; ++v) uo[v] = P.u[v * stride + gi];
+            if constexpr (CURV) {
+#pragma unroll
+                for (int k = 0; k < DIM * DIM; ++k) sJa[k * NN + node] = P.geo[k * stride + gi];
+                sJ[node] = P.Jn[gi];
+            }
+            if constexpr (MIX) Tn = P.T[gi];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) uo[v] = 1.0;
         }
-        if constexpr (CURV) {
+        St<DIM, MIX> own;
+        make_state<DIM, MIX>(uo, Tn, gamma, P.M, own);
+        if (valid) {
+            sq[node] = own.rho;
 #pragma unroll
-            for (int k = 0; k < DIM * DIM; ++k) sJa[k * NN + node] = P.geo[k * stride + gi];
-            sJ[node] = P.Jn[gi];
+            for (int c = 0; c < DIM; ++c) sq[(1 + c) * NN + node] = own.v[c];
+            sq[(1 + DIM) * NN + node] = own.p;
+            sq[(2 + DIM) * NN + node] = own.rhoE;
+            if constexpr (MIX) {
+                sq[(3 + DIM) * NN + node] = own.c;
+#pragma unroll
+                for (int k = 0; k < kNS; ++k) su[k * NN + node] = own.rs[k];
+            }
+            if constexpr (S::EC) {
+                const double beta = own.rho / own.p;
+                sq[QB * NN + node] = beta;
+                sq[(QB + 1) * NN + node] = log(own.rho);
+                sq[(QB + 2) * NN + node] = log(beta);
+            }
+            bool ok = own.rho > 0.0 && own.p > 0.0 && isfinite(own.rhoE) && isfinite(own.p);
+            if constexpr (MIX) {
+#pragma unroll
+                for (int k = 0; k < kNS; ++k) ok = ok && own.rs[k] >= 0.0;
+            }
+            if (!ok) atomicOr(P.flags, FLAG_NONPHYS);
         }
-        if constexpr (MIX) Tn = P.T[gi];
-    } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) uo[v] = 1.0;
-        if constexpr (MIX) Tn = 1.0;
-    }
-    St<DIM, MIX> own;
-    make_state<DIM, MIX>(uo, Tn, P.gamma, P.M, own);
-    if (valid) {
-        sq[node] = own.rho;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) sq[(1 + c) * NN + node] = own.v[c];
-        sq[(1 + DIM) * NN + node] = own.p;
-        sq[(2 + DIM) * NN + node] = own.c;
-        if constexpr (S::EC) {
-            const double beta = own.rho / own.p;
-            sq[(3 + DIM) * NN + node] = beta;
-            sq[(4 + DIM) * NN + node] = log(own.rho);
-            sq[(5 + DIM) * NN + node] = log(beta);
-        }
-        bool ok = own.rho > 0.0 && own.p > 0.0 && isfinite(own.rhoE) && isfinite(own.p);
-        if constexpr (MIX) {
-#pragma unroll
-            for (int k = 0; k < kNS; ++k) ok = ok && own.rs[k] >= 0.0;
-        }
-        if (!ok) atomicOr(P.flags, FLAG_NONPHYS);
     }
     // affine element geometry
     double Jaf[DIM * DIM];
@@ -173,14 +203,105 @@ __global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
         for (int k = 0; k < DIM * DIM; ++k) Jaf[k] = g[k];
         Jel = g[DIM * DIM];
     }
+    const int ebase = (valid ? e : 0) * 2 * DIM;
+    __syncthreads();
+
+    double acc[NV];  // surface terms and alpha-weighted FV terms
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+
+    // ---- interface / boundary Riemann fluxes: one work item per face node
+#pragma unroll
+    for (int r = 0; r < (NSF + NN - 1) / NN; ++r) {
+        const int it = r * NN + node;
+        if (valid && it < NSF) {
+            const int f = it / NF;
+            const int q = it - f * NF;
+            const int d = f >> 1, side = f & 1;
+            const int nd = line_node<N1, DIM>(d, side ? N : 0, q);
+            St<DIM, MIX> own, ext;
+            lds_state<DIM, MIX>(su, sq, NN, nd, gamma, own);
+            double nrm[DIM];
+            if constexpr (CURV) {
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) nrm[c] = sJa[(d * DIM + c) * NN + nd];
+            } else {
+                jaf_row<DIM>(Jaf, d, nrm);
+            }
+            const int nb = P.nbr[ebase + f];
+            if (nb >= 0) {
+                const int nbn = line_node<N1, DIM>(d, side ? 0 : N, q);
+                const size_t gj = (size_t)nb * NN + nbn;
+                double ue[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) ue[v] = P.u[v * stride + gj];
+                const double Te = MIX ? P.T[gj] : 0.0;
+                make_state<DIM, MIX>(ue, Te, gamma, P.M, ext);
+                if (side == 0) {
+                    if constexpr (CURV) {
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(d * DIM + c) * stride + gj];
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(size_t)nb * GA + d * DIM + c];
+                    }
+                }
+            } else {
+                const int bc = -1 - nb;
+                const int kind = P.bc_kind[bc];
+                if (kind == 0) {
+                    double ue[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) ue[v] = P.bc_state[bc * NV + v];
+                    make_state<DIM, MIX>(ue, MIX ? P.bc_T[bc] : 0.0, gamma, P.M, ext);
+                } else if (kind == 1) {
+                    ext = own;
+                } else {
+                    // slip wall: mirror the velocity about the face (T and p unchanged)
+                    const double inn = rcp(dotn<DIM>(nrm, nrm));
+                    const double vn = dotn<DIM>(own.v, nrm) * inn;
+                    ext = own;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) ext.v[c] = own.v[c] - 2.0 * vn * nrm[c];
+                }
+            }
+            double F[NV];
+            if constexpr (SF == 0) {
+                if (side) rusanov<DIM, MIX>(own, ext, nrm, F);
+                else rusanov<DIM, MIX>(ext, own, nrm, F);
+            } else {
+                if (side) ranocha_state<DIM, MIX>(own, ext, nrm, gamma, F);
+                else ranocha_state<DIM, MIX>(ext, own, nrm, gamma, F);
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) buf[v * NSF + it] = F[v];
+        }
+    }
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const int a = node_pos<N1>(node, d);
+            const int l = node_line<N1, DIM>(node, d);
+            if (a == N) {
+                const double sc = 1.0 / P.B.w[N];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[v] = fma(sc, buf[v * NSF + (2 * d + 1) * NF + l], acc[v]);
+            } else if (a == 0) {
+                const double sc = -1.0 / P.B.w[0];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[v] = fma(sc, buf[v * NSF + (2 * d) * NF + l], acc[v]);
+            }
+        }
+    }
     __syncthreads();
 
     // ---- high-order volume term: symmetric two-point fluxes along lines
-    double acc[NV];
+    double dg[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-    const double gm1_inv = 1.0 / (P.gamma - 1.0);
-#pragma unroll 1
+    for (int v = 0; v < NV; ++v) dg[v] = 0.0;
+    const double gm1_inv = 1.0 / (gamma - 1.0);
+#pragma unroll
     for (int d = 0; d < DIM; ++d) {
 #pragma unroll
         for (int r = 0; r < (PD + NN - 1) / NN; ++r) {
@@ -204,14 +325,14 @@ __global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
                         vA[c] = sq[(1 + c) * NN + na];
                         vB[c] = sq[(1 + c) * NN + nb];
                     }
-                    ranocha_prims<DIM>(sq[na], vA, sq[(1 + DIM) * NN + na], sq[(3 + DIM) * NN + na],
-                                       sq[(4 + DIM) * NN + na], sq[(5 + DIM) * NN + na], sq[nb], vB,
-                                       sq[(1 + DIM) * NN + nb], sq[(3 + DIM) * NN + nb],
-                                       sq[(4 + DIM) * NN + nb], sq[(5 + DIM) * NN + nb], nbar, gm1_inv, F);
+                    ranocha_prims<DIM>(sq[na], vA, sq[(1 + DIM) * NN + na], sq[QB * NN + na],
+                                       sq[(QB + 1) * NN + na], sq[(QB + 2) * NN + na], sq[nb], vB,
+                                       sq[(1 + DIM) * NN + nb], sq[QB * NN + nb], sq[(QB + 1) * NN + nb],
+                                       sq[(QB + 2) * NN + nb], nbar, gm1_inv, F);
                 } else {
                     St<DIM, MIX> A, B;
-                    lds_state<DIM, MIX, NQ>(su, sq, NN, na, A);
-                    lds_state<DIM, MIX, NQ>(su, sq, NN, nb, B);
+                    lds_state<DIM, MIX>(su, sq, NN, na, gamma, A);
+                    lds_state<DIM, MIX>(su, sq, NN, nb, gamma, B);
                     ducros_state<DIM, MIX>(A, B, nbar, F);
                 }
 #pragma unroll
@@ -228,7 +349,7 @@ __global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
                 const int k = l * NPL + (a < b ? pair_index<N1>(a, b) : pair_index<N1>(b, a));
                 const double coef = 2.0 * P.B.D[a * N1 + b];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) acc[v] = fma(coef, buf[v * PD + k], acc[v]);
+                for (int v = 0; v < NV; ++v) dg[v] = fma(coef, buf[v * PD + k], dg[v]);
             }
         }
         __syncthreads();
@@ -236,11 +357,8 @@ __global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
 
     // ---- first-order subcell finite volumes (elements with alpha > 0)
     const double alpha = (P.alpha != nullptr && valid) ? P.alpha[e] : 0.0;
-    double accfv[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) accfv[v] = 0.0;
     if (__syncthreads_or(alpha > 0.0)) {
-#pragma unroll 1
+#pragma unroll
         for (int d = 0; d < DIM; ++d) {
 #pragma unroll
             for (int r = 0; r < (NFV + NN - 1) / NN; ++r) {
@@ -260,8 +378,8 @@ __global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
                         for (int c = 0; c < DIM; ++c) nrm[c] = Jaf[d * DIM + c];
                     }
                     St<DIM, MIX> A, B;
-                    lds_state<DIM, MIX, NQ>(su, sq, NN, nL, A);
-                    lds_state<DIM, MIX, NQ>(su, sq, NN, nR, B);
+                    lds_state<DIM, MIX>(su, sq, NN, nL, gamma, A);
+                    lds_state<DIM, MIX>(su, sq, NN, nR, gamma, B);
                     double F[NV];
                     rusanov<DIM, MIX>(A, B, nrm, F);
 #pragma unroll
@@ -272,94 +390,15 @@ __global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
             if (valid && alpha > 0.0) {
                 const int a = node_pos<N1>(node, d);
                 const int l = node_line<N1, DIM>(node, d);
-                const double iw = 1.0 / P.B.w[a];
+                const double aw = alpha / P.B.w[a];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     const double hi = a < N ? buf[v * NFV + l * N + a] : 0.0;
                     const double lo = a > 0 ? buf[v * NFV + l * N + a - 1] : 0.0;
-                    accfv[v] += (hi - lo) * iw;
+                    acc[v] = fma(aw, hi - lo, acc[v]);
                 }
             }
             __syncthreads();
-        }
-    }
-
-    // ---- interface / boundary Riemann fluxes, element-centric
-    double accs[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) accs[v] = 0.0;
-    if (valid) {
-#pragma unroll 1
-        for (int d = 0; d < DIM; ++d) {
-            const int a = node_pos<N1>(node, d);
-            if (a != 0 && a != N) continue;
-            const int side = (a == N) ? 1 : 0;
-            const int l = node_line<N1, DIM>(node, d);
-            const int nb = P.nbr[(size_t)e * 2 * DIM + 2 * d + side];
-            double nrm[DIM];
-            if constexpr (CURV) {
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) nrm[c] = sJa[(d * DIM + c) * NN + node];
-            } else {
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) nrm[c] = Jaf[d * DIM + c];
-            }
-            St<DIM, MIX> ext;
-            if (nb >= 0) {
-                const int nbn = line_node<N1, DIM>(d, side ? 0 : N, l);
-                const size_t gj = (size_t)nb * NN + nbn;
-                double ue[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) ue[v] = P.u[v * stride + gj];
-                const double Te = MIX ? P.T[gj] : 0.0;
-                make_state<DIM, MIX>(ue, Te, P.gamma, P.M, ext);
-                if (side == 0) {
-                    if constexpr (CURV) {
-#pragma unroll
-                        for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(d * DIM + c) * stride + gj];
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(size_t)nb * GA + d * DIM + c];
-                    }
-                }
-            } else {
-                const int bc = -1 - nb;
-                const int kind = P.bc_kind[bc];
-                if (kind == 0) {
-                    double ue[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) ue[v] = P.bc_state[bc * NV + v];
-                    make_state<DIM, MIX>(ue, MIX ? P.bc_T[bc] : 0.0, P.gamma, P.M, ext);
-                } else if (kind == 1) {
-                    ext = own;
-                } else {
-                    const double inn = 1.0 / sqrt(dotn<DIM>(nrm, nrm));
-                    double nh[DIM];
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) nh[c] = nrm[c] * inn;
-                    double ue[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) ue[v] = uo[v];
-                    constexpr int off = MIX ? kNS : 1;
-                    double mn = 0.0;
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) mn = fma(uo[off + c], nh[c], mn);
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) ue[off + c] = uo[off + c] - 2.0 * mn * nh[c];
-                    make_state<DIM, MIX>(ue, Tn, P.gamma, P.M, ext);
-                }
-            }
-            double F[NV];
-            if constexpr (SF == 0) {
-                if (side) rusanov<DIM, MIX>(own, ext, nrm, F);
-                else rusanov<DIM, MIX>(ext, own, nrm, F);
-            } else {
-                if (side) ranocha_state<DIM, MIX>(own, ext, nrm, P.gamma, F);
-                else ranocha_state<DIM, MIX>(ext, own, nrm, P.gamma, F);
-            }
-            const double sc = side ? 1.0 / P.B.w[N] : -1.0 / P.B.w[0];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) accs[v] = fma(sc, F[v], accs[v]);
         }
     }
 
@@ -367,62 +406,88 @@ __global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
     const double iJ = 1.0 / Jn;
     double du[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double tot = (1.0 - alpha) * acc[v] + alpha * accfv[v] + accs[v];
-        du[v] = -tot * iJ;
-    }
+    for (int v = 0; v < NV; ++v) du[v] = -fma(1.0 - alpha, dg[v], acc[v]) * iJ;
 
-    // ---- BR1 viscous divergence (perfect-gas Navier-Stokes, affine elements)
+    // ---- BR1 viscous divergence (perfect-gas Navier-Stokes, affine elements).
+    // P.grad holds the nodal viscous fluxes F_v[c][k] ([dim][dim+1][E][nn]).
     if constexpr (EQ == 1) {
-        constexpr int NW = DIM + 1;
-        double Fv[DIM][DIM + 1];  // Fv[c][k]: k < DIM momentum, k = DIM energy
-        auto visc_flux = [&](const double *g, const double *vel, double (*F)[DIM + 1]) {
-            // g[c*NW + w] = d W_w / d x_c
-            double div = 0.0;
+        double vis[NW];
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) div += g[k * NW + k];
+        for (int k = 0; k < NW; ++k) vis[k] = 0.0;
+        // interface terms: (F* - F~_own) / w with F* = (F_own + F_nbr).n / 2
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                double en = 0.0;
+        for (int r = 0; r < (NSF + NN - 1) / NN; ++r) {
+            const int it = r * NN + node;
+            if (valid && it < NSF) {
+                const int f = it / NF;
+                const int q = it - f * NF;
+                const int d = f >> 1, side = f & 1;
+                const int nd = line_node<N1, DIM>(d, side ? N : 0, q);
+                const int nb = P.nbr[ebase + f];
+                const int nbn = line_node<N1, DIM>(d, side ? 0 : N, q);
+                const size_t go = (size_t)e * NN + nd;
+                const size_t gj = (size_t)nb * NN + nbn;
+                double nrm[DIM], jown[DIM];
+                jaf_row<DIM>(Jaf, d, jown);
+                if (side) {
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) {
-                    double t = P.mu * (g[c * NW + k] + g[k * NW + c]);
-                    if (k == c) t -= (2.0 / 3.0) * P.mu * div;
-                    F[c][k] = t;
-                    en = fma(t, vel[k], en);
+                    for (int c = 0; c < DIM; ++c) nrm[c] = jown[c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(size_t)nb * GA + d * DIM + c];
                 }
-                F[c][DIM] = en + P.kappa * g[c * NW + DIM];
+#pragma unroll
+                for (int k = 0; k < NW; ++k) {
+                    double fo = 0.0, fn = 0.0, ft = 0.0;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        const double Fo = P.grad[(size_t)(c * NW + k) * stride + go];
+                        const double Fn = P.grad[(size_t)(c * NW + k) * stride + gj];
+                        fo = fma(Fo, nrm[c], fo);
+                        fn = fma(Fn, nrm[c], fn);
+                        ft = fma(jown[c], Fo, ft);
+                    }
+                    buf[k * NSF + it] = 0.5 * (fo + fn) - ft;
+                }
             }
-        };
-        double g[DIM * NW];
-        if (valid) {
-#pragma unroll
-            for (int c = 0; c < DIM; ++c)
-#pragma unroll
-                for (int w = 0; w < NW; ++w) g[c * NW + w] = P.grad[(size_t)(c * NW + w) * stride + gi];
-        } else {
-#pragma unroll
-            for (int k = 0; k < DIM * NW; ++k) g[k] = 0.0;
         }
-        visc_flux(g, own.v, Fv);
-        double Ft[DIM][DIM + 1];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d)
-#pragma unroll
-            for (int k = 0; k < NW; ++k) {
-                double s = 0.0;
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) s = fma(Jaf[d * DIM + c], Fv[c][k], s);
-                Ft[d][k] = s;
-                if (valid) buf[(d * NW + k) * NN + node] = s;
-            }
         __syncthreads();
         if (valid) {
-            double vis[NW];
 #pragma unroll
-            for (int k = 0; k < NW; ++k) vis[k] = 0.0;
-#pragma unroll 1
             for (int d = 0; d < DIM; ++d) {
+                const int a = node_pos<N1>(node, d);
+                const int l = node_line<N1, DIM>(node, d);
+                if (a == N) {
+                    const double sc = 1.0 / P.B.w[N];
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) vis[k] = fma(sc, buf[k * NSF + (2 * d + 1) * NF + l], vis[k]);
+                } else if (a == 0) {
+                    const double sc = -1.0 / P.B.w[0];
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) vis[k] = fma(sc, buf[k * NSF + (2 * d) * NF + l], vis[k]);
+                }
+            }
+        }
+        __syncthreads();
+        // volume terms: sum_d D_d (Ja^d . F_v)
+        double Fv[DIM][NW];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int k = 0; k < NW; ++k) Fv[c][k] = valid ? P.grad[(size_t)(c * NW + k) * stride + gi] : 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            if (valid) {
+#pragma unroll
+                for (int k = 0; k < NW; ++k) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) s = fma(Jaf[d * DIM + c], Fv[c][k], s);
+                    buf[k * NN + node] = s;
+                }
+            }
+            __syncthreads();
+            if (valid) {
                 const int a = node_pos<N1>(node, d);
                 const int l = node_line<N1, DIM>(node, d);
 #pragma unroll
@@ -430,56 +495,20 @@ __global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
                     const double Dj = P.B.D[a * N1 + j];
                     const int nj = line_node<N1, DIM>(d, j, l);
 #pragma unroll
-                    for (int k = 0; k < NW; ++k) vis[k] = fma(Dj, buf[(d * NW + k) * NN + nj], vis[k]);
-                }
-                if (a == 0 || a == N) {
-                    const int side = (a == N) ? 1 : 0;
-                    const int nb = P.nbr[(size_t)e * 2 * DIM + 2 * d + side];
-                    const int nbn = line_node<N1, DIM>(d, side ? 0 : N, l);
-                    const size_t gj = (size_t)nb * NN + nbn;
-                    double gn[DIM * NW];
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-                        for (int w = 0; w < NW; ++w) gn[c * NW + w] = P.grad[(size_t)(c * NW + w) * stride + gj];
-                    const double irn = 1.0 / P.u[gj];
-                    double vn[DIM];
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) vn[c] = P.u[(1 + c) * stride + gj] * irn;
-                    double Fn[DIM][DIM + 1];
-                    visc_flux(gn, vn, Fn);
-                    double nrm[DIM];
-                    if (side) {
-#pragma unroll
-                        for (int c = 0; c < DIM; ++c) nrm[c] = Jaf[d * DIM + c];
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(size_t)nb * GA + d * DIM + c];
-                    }
-                    const double sc = side ? 1.0 / P.B.w[N] : -1.0 / P.B.w[0];
-#pragma unroll
-                    for (int k = 0; k < NW; ++k) {
-                        double fo = 0.0, fn = 0.0;
-#pragma unroll
-                        for (int c = 0; c < DIM; ++c) {
-                            fo = fma(Fv[c][k], nrm[c], fo);
-                            fn = fma(Fn[c][k], nrm[c], fn);
-                        }
-                        const double fs = 0.5 * (fo + fn);
-                        vis[k] = fma(sc, fs - Ft[d][k], vis[k]);
-                    }
+                    for (int k = 0; k < NW; ++k) vis[k] = fma(Dj, buf[k * NN + nj], vis[k]);
                 }
             }
-#pragma unroll
-            for (int k = 0; k < NW; ++k) du[1 + k] += vis[k] * iJ;
+            __syncthreads();
         }
+#pragma unroll
+        for (int k = 0; k < NW; ++k) du[1 + k] = fma(vis[k], iJ, du[1 + k]);
     }
 
     // ---- finite-rate chemistry source
     if constexpr (EQ == 3) {
         if (valid) {
             const KinC &K = *P.kin;
-            const double T = Tn;
+            const double T = P.T[gi];
             const double lnT = log(T);
             const double iT = 1.0 / T;
             double gRT[kNS], conc[kNS];
@@ -488,7 +517,7 @@ __global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
                 double g = K.gconst[s] - (2.5 + P.M.mol[s]) * lnT + P.M.e0[s] * iT / P.M.Rs[s];
                 if (P.M.mol[s]) g += log(-expm1(-P.M.thv[s] * iT));
                 gRT[s] = g;
-                conc[s] = own.rs[s] / K.W[s];
+                conc[s] = su[s * NN + node] / K.W[s];
             }
             double wdot[kNS];
 #pragma unroll
@@ -522,8 +551,9 @@ __global__ void __launch_bounds__(256) k_rhs(RhsParams P, int mode) {
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
+                const double us = P.u[v * stride + gi];
                 const double base = P.sa != 0.0 ? P.sa * P.u0[v * stride + gi] : 0.0;
-                P.out[v * stride + gi] = base + P.sb * (uo[v] + P.dt * du[v]);
+                P.out[v * stride + gi] = base + P.sb * (us + P.dt * du[v]);
             }
         }
     }

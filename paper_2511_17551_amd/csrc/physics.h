@@ -31,23 +31,45 @@ struct St {
     double rs[MIX ? kNS : 1];
 };
 
-// Logarithmic mean and its reciprocal from the values and their logs:
-// (y - x)/ln(y/x), with a 4-term series in z = ((x-y)/(x+y))^2 when z < 1e-4.
-__device__ __forceinline__ void ln_mean_pair(double x, double y, double lx, double ly,
-                                             double &mean, double &inv_mean) {
+// 1/x: hardware v_rcp_f64 estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r) (each step squares the relative error).
+__device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Logarithmic mean (y - x)/ln(y/x) from the values and their logs.  For
+// z = ((y-x)/(y+x))^2 < 1e-4 the mean is (x+y)/P(z) with the 4-term series
+// P = 2 + 2z/3 + 2z^2/5 + 2z^3/7; here 1/P is itself expanded,
+// 2/P = 1 - z/3 - 4z^2/45 - 44z^3/945 + O(z^4) (remainder < 1e-17 relative),
+// which saves a reciprocal.
+__device__ __forceinline__ double ln_mean(double x, double y, double lx, double ly) {
     const double s = x + y;
     const double d = y - x;
-    const double q = d / s;
-    const double z = q * q;
-    if (z < 1e-4) {
-        const double P = 2.0 + z * (2.0 / 3.0 + z * (2.0 / 5.0 + z * (2.0 / 7.0)));
-        mean = s / P;
-        inv_mean = P / s;
-    } else {
-        const double dl = ly - lx;
-        mean = d / dl;
-        inv_mean = dl / d;
+    if (d * d < 1e-4 * (s * s)) {
+        const double q = d * rcp(s);
+        const double z = q * q;
+        const double h = 0.5 * s;
+        return fma(-h * z, 1.0 / 3.0 + z * (4.0 / 45.0 + z * (44.0 / 945.0)), h);
     }
+    return d * rcp(ly - lx);
+}
+
+// Reciprocal of the logarithmic mean, ln(y/x)/(y - x) (same branches).
+__device__ __forceinline__ double inv_ln_mean(double x, double y, double lx, double ly) {
+    const double s = x + y;
+    const double d = y - x;
+    if (d * d < 1e-4 * (s * s)) {
+        const double rs = rcp(s);
+        const double q = d * rs;
+        const double z = q * q;
+        const double P = 2.0 + z * (2.0 / 3.0 + z * (2.0 / 5.0 + z * (2.0 / 7.0)));
+        return P * rs;
+    }
+    return (ly - lx) * rcp(d);
 }
 
 // ---------------------------------------------------------------- mixture
@@ -122,7 +144,7 @@ __device__ __forceinline__ void make_state(const double *u, double T, double gam
             rho += u[k];
         }
         s.rho = rho;
-        const double ir = 1.0 / rho;
+        const double ir = rcp(rho);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) s.v[c] = u[kNS + c] * ir;
         s.rhoE = u[kNS + DIM];
@@ -131,7 +153,7 @@ __device__ __forceinline__ void make_state(const double *u, double T, double gam
         s.c = mix_sound(M, s.rs, rho, T);
     } else {
         s.rho = u[0];
-        const double ir = 1.0 / u[0];
+        const double ir = rcp(u[0]);
         double v2 = 0.0;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
@@ -140,7 +162,7 @@ __device__ __forceinline__ void make_state(const double *u, double T, double gam
         }
         s.rhoE = u[1 + DIM];
         s.p = (gamma - 1.0) * (s.rhoE - 0.5 * s.rho * v2);
-        s.c = sqrt(gamma * s.p / s.rho);
+        s.c = sqrt(gamma * s.p * ir);
         s.rs[0] = 0.0;
     }
 }
@@ -196,9 +218,8 @@ __device__ __forceinline__ void ranocha_prims(double rL, const double *vL, doubl
                                               double lrL, double lbL, double rR, const double *vR,
                                               double pR, double bR, double lrR, double lbR,
                                               const double *n, double gm1_inv, double *F) {
-    double rho_hat, irho_hat, beta_hat, ibeta_hat;
-    ln_mean_pair(rL, rR, lrL, lrR, rho_hat, irho_hat);
-    ln_mean_pair(bL, bR, lbL, lbR, beta_hat, ibeta_hat);
+    const double rho_hat = ln_mean(rL, rR, lrL, lrR);
+    const double ibeta_hat = inv_ln_mean(bL, bR, lbL, lbR);
     double vbar[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) vbar[c] = 0.5 * (vL[c] + vR[c]);

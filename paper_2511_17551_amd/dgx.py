@@ -85,6 +85,10 @@ def _load():
         "dgx_surrogate_predict": ([vp, vp, C.c_int64, vp, vp], C.c_int),
         "dgx_check": ([vp, vp], C.c_int),
         "dgx_species_energy": ([vp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+        "dgx_kernel_times": ([vp, vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_char_p,
+                              C.c_size_t, vp], C.c_int),
+        "dgx_autotune": ([vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), vp], C.c_int),
+        "dgx_set_launch": ([vp, C.c_int], C.c_int),
         "dgx_last_error": ([vp], C.c_char_p),
         "dgx_destroy": ([vp], None),
     }
@@ -98,7 +102,8 @@ def _load():
 lib = _load()
 EXPORTED = ("dgx_create", "dgx_set_mesh", "dgx_rhs", "dgx_ssprk3_step", "dgx_max_dt", "dgx_thermo",
             "dgx_last_alpha", "dgx_surrogate_set", "dgx_surrogate_get", "dgx_surrogate_train",
-            "dgx_surrogate_predict", "dgx_check", "dgx_species_energy", "dgx_last_error", "dgx_destroy")
+            "dgx_surrogate_predict", "dgx_check", "dgx_species_energy", "dgx_kernel_times", "dgx_autotune",
+            "dgx_set_launch", "dgx_last_error", "dgx_destroy")
 
 
 def _ptr(a, ctype=C.c_double):
@@ -277,6 +282,27 @@ def dgx_species_energy(ctx, T):
     cv = (C.c_double * 5)()
     _raise(ctx, lib.dgx_species_energy(ctx, float(T), e, cv))
     return np.array(e[:]), np.array(cv[:])
+
+
+def dgx_kernel_times(ctx, u, reps=20, stream=None):
+    """{kernel name: average ms} of one fused-stage right-hand side."""
+    ms = (C.c_double * 8)()
+    nk = C.c_int()
+    names = C.create_string_buffer(256)
+    _raise(ctx, lib.dgx_kernel_times(ctx, _dev(u), int(reps), ms, C.byref(nk), names, 256, _stream(stream)))
+    return dict(zip(names.value.decode().split(","), ms[:nk.value]))
+
+
+def dgx_autotune(ctx, u, reps=10, stream=None):
+    """Returns (chosen elements per workgroup, {candidate: ms})."""
+    epb = C.c_int()
+    ms = (C.c_double * 4)()
+    _raise(ctx, lib.dgx_autotune(ctx, _dev(u), int(reps), C.byref(epb), ms, _stream(stream)))
+    return epb.value, {c: ms[i] for i, c in enumerate((1, 2, 4, 8)) if ms[i] >= 0}
+
+
+def dgx_set_launch(ctx, epb):
+    _raise(ctx, lib.dgx_set_launch(ctx, int(epb)))
 
 
 def dgx_last_error(ctx):
