@@ -25,20 +25,25 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
-def rhs_bytes_per_launch(nelem, nn, nvar, dim, grad=True, stage_base=True):
-    """Algorithmic HBM bytes of one fused k_rhs launch (each datum once).
+def rhs_bytes_per_launch(nelem, nn, nvar, dim, n1, stage_base=True):
+    """Algorithmic HBM bytes of one fused k_rhs launch (every datum once).
 
-    per node: state u (nvar) + gradients (dim*(dim+1), Navier-Stokes) +
-    stage base u0 (nvar, stages 2 and 3) read, next stage (nvar) written;
-    per element: dim*dim+1 affine geometry doubles and 2*dim int32 neighbours.
+    per node: state u (nvar) and stage base u0 (nvar, stages 2 and 3) read,
+    next stage (nvar) written, element-local viscous divergence (dim+1) read;
+    per element: the neighbours' face viscous fluxes (2 dim faces x (dim+1) x
+    n1^(dim-1) face nodes), dim*dim+1 affine geometry doubles and 2*dim int32
+    neighbour indices.
     """
-    per_node = nvar + (dim * (dim + 1) if grad else 0) + (nvar if stage_base else 0) + nvar
-    return nelem * nn * per_node * 8 + nelem * ((dim * dim + 1) * 8 + 2 * dim * 4)
+    nf = n1 ** (dim - 1)
+    per_node = nvar + (nvar if stage_base else 0) + nvar + (dim + 1)
+    per_elem = 2 * dim * (dim + 1) * nf * 8 + (dim * dim + 1) * 8 + 2 * dim * 4
+    return nelem * nn * per_node * 8 + nelem * per_elem
 
 
-def grad_bytes_per_launch(nelem, nn, nvar, dim):
-    """k_grad: state read, dim*(dim+1) gradient fields written, geometry."""
-    return nelem * nn * (nvar + dim * (dim + 1)) * 8 + nelem * ((dim * dim + 1) * 8 + 2 * dim * 4)
+def grad_bytes_per_launch(nelem, nn, nvar, dim, n1):
+    """k_grad: state read; local viscous divergence and face fluxes written."""
+    nf = n1 ** (dim - 1)
+    return nelem * nn * (nvar + dim + 1) * 8 + nelem * (2 * dim * (dim + 1) * nf * 8 + (dim * dim + 1) * 8 + 2 * dim * 4)
 
 
 def cpu_baseline(case, budget_s=20.0):
@@ -112,8 +117,8 @@ def main():
     # per-kernel durations (HIP events on the launch stream, same fused stage form)
     kt = dgx.dgx_kernel_times(solver.ctx, u, reps=20)
     k_rhs_ms = kt["k_rhs"]
-    rb = rhs_bytes_per_launch(nelem, nn, nvar, 3)
-    gb = grad_bytes_per_launch(nelem, nn, nvar, 3)
+    rb = rhs_bytes_per_launch(nelem, nn, nvar, 3, 4)
+    gb = grad_bytes_per_launch(nelem, nn, nvar, 3, 4)
     achieved = rb / (k_rhs_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,

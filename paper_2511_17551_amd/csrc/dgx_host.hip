@@ -114,7 +114,7 @@ struct dgx_ctx {
     bool curved = false;
     bool mesh_ok = false;
     int nbc = 0;
-    DevBuf<double> geo, Jn, nsub, bc_state, bc_T, T, alpha, alpha_tmp, alpha_raw, grad, u1, u2, dtbuf;
+    DevBuf<double> geo, Jn, nsub, bc_state, bc_T, T, alpha, alpha_tmp, alpha_raw, grad, vpart, u1, u2, dtbuf;
     DevBuf<int> nbr, bc_kind;
     DevBuf<KinC> kin_d;
     DevBuf<unsigned> flags;
@@ -208,6 +208,7 @@ RhsParams base_params(dgx_ctx *ctx) {
     P.nsub = ctx->nsub.p;
     P.T = ctx->T.p;
     P.grad = ctx->grad.p;
+    P.vpart = ctx->vpart.p;
     P.bc_kind = ctx->bc_kind.p;
     P.bc_state = ctx->bc_state.p;
     P.bc_T = ctx->bc_T.p;
@@ -297,7 +298,8 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
     }
     if (c.equation == DGX_EQ_NS) {
         RhsParams G = P;
-        G.out = ctx->grad.p;
+        G.out = ctx->vpart.p;
+        G.out2 = ctx->grad.p;
         const size_t lds = (size_t)epb * (c.dim + 1) * ctx->nn * sizeof(double);
         if (c.dim == 3 && c.N == 3) grad_launch<3, 3>(G, blocks, th, lds, s);
         else if (c.dim == 3 && c.N == 4) grad_launch<3, 4>(G, blocks, th, lds, s);
@@ -577,7 +579,10 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         HIPCHK(hipMemcpy(ctx->alpha.p, a.data(), E * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(ctx->alpha_raw.p, a.data(), E * sizeof(double), hipMemcpyHostToDevice));
     }
-    if (ctx->cfg.equation == DGX_EQ_NS && (rc = dalloc(ctx, ctx->grad, (size_t)dim * (dim + 1) * E * nn))) return rc;
+    if (ctx->cfg.equation == DGX_EQ_NS) {
+        if ((rc = dalloc(ctx, ctx->grad, (size_t)E * 2 * dim * (dim + 1) * ctx->nf))) return rc;
+        if ((rc = dalloc(ctx, ctx->vpart, (size_t)(dim + 1) * E * nn))) return rc;
+    }
     if (ctx->cfg.equation == DGX_EQ_REACT_MIX) {
         if ((rc = dalloc(ctx, ctx->kin_d, 1))) return rc;
         HIPCHK(hipMemcpy(ctx->kin_d.p, &ctx->kin, sizeof(KinC), hipMemcpyHostToDevice));
@@ -910,7 +915,7 @@ void dgx_destroy(dgx_ctx *ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     DevBuf<double> *bufs[] = {&ctx->geo,   &ctx->Jn,        &ctx->nsub,      &ctx->bc_state, &ctx->bc_T, &ctx->T,
                               &ctx->alpha, &ctx->alpha_tmp, &ctx->alpha_raw, &ctx->grad,     &ctx->u1,   &ctx->u2,
-                              &ctx->dtbuf};
+                              &ctx->dtbuf, &ctx->vpart};
     for (auto *b : bufs) b->release();
     ctx->nbr.release();
     ctx->bc_kind.release();

@@ -52,7 +52,9 @@ struct RhsParams {
     const double *nsub;     // curved + shock: [E][dim][nf][N][dim] subcell normals
     const double *alpha;    // [E] or null
     const double *T;        // mixture temperature [E][nn]
-    const double *grad;     // NS gradients [dim][dim+1][E][nn]
+    const double *grad;     // NS: neighbours' face viscous fluxes [E][2 dim][dim+1][nf]
+    const double *vpart;    // NS: element-local viscous divergence [dim+1][E][nn]
+    double *out2;           // second output (k_grad: face viscous fluxes)
     const int *bc_kind;     // [nbc]
     const double *bc_state; // [nbc][nvar]
     const double *bc_T;     // [nbc] temperatures of Dirichlet states (mixture)

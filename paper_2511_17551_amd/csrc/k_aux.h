@@ -6,16 +6,25 @@
 
 namespace dgx {
 
-// BR1 gradients of W = (v, T), T = p/(rho R)  (Sec. Methodology, Viscous
-// Fluxes, Eqs. auxil and auxstrongf with the interface value
-// W* = (W_own + W_nbr)/2; affine elements, strong form
-// q = (1/J) sum_d Ja^d [D_d W + lift(W* - W)]), followed by the nodal viscous
-// flux F_v[c] = (tau_{.c}, (tau v)_c + kappa dT/dx_c) (Appendix, Transport,
-// Eq. stress with zero bulk viscosity), written to P.out as [dim][dim+1][E][nn].
+// BR1 viscous terms, element-local part (Sec. Methodology, Viscous Fluxes,
+// Eqs. auxil and auxstrongf; Appendix, Transport, Eq. stress).
+//
+// Per element: gradients q = (1/J) sum_d Ja^d [D_d W + lift(W* - W)] of
+// W = (v, T = p/(rho R)) with W* = (W_own + W_nbr)/2, the nodal viscous flux
+// F_v[c] = (tau_{.c}, (tau v)_c + kappa dT/dx_c) and its contravariant form
+// Ft^d = Ja^d . F_v.  The divergence with the averaged interface flux,
+//   (1/J) [ sum_d D_d Ft^d + (Ft* - Ft_own)/w_N |_{xi_d = 1} - (Ft* - Ft_own)/w_0 |_{xi_d = -1} ],
+//   Ft* = (Ft_own + Ft_nbr) / 2,
+// is split into what this element knows (written to P.out, [dim+1][E][nn]:
+// everything except +-Ft_nbr/(2w)) and the face values Ft^d at its face nodes
+// (written to P.grad as [E][2 dim][dim+1][nf]) that its neighbours add.
+// Affine elements (Ja^d constant); on a conforming face of two affine
+// elements Ja^d of both sides is the area vector of the shared face.
 template <int DIM, int N>
 __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
     constexpr int N1 = N + 1;
     constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+    constexpr int NF = NN / N1;
     constexpr int NV = DIM + 2;
     constexpr int NW = DIM + 1;
     constexpr int GA = DIM * DIM + 1;
@@ -27,11 +36,11 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
     const bool valid = (el < P.epb) && (e < P.nelem);
     if (el >= P.epb) el = 0;
     double *sw = smem + el * NW * NN;
-    const size_t stride = (size_t)P.nelem * NN;
-    const size_t gi = (size_t)(valid ? e : 0) * NN + node;
+    const unsigned stride = (unsigned)P.nelem * NN;
+    const unsigned gi = (unsigned)(valid ? e : 0) * NN + node;
 
     auto prim = [&](const double *u, double *W) {
-        const double ir = 1.0 / u[0];
+        const double ir = rcp(u[0]);
         double v2 = 0.0;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
@@ -39,79 +48,136 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
             v2 = fma(W[c], W[c], v2);
         }
         const double p = (P.gamma - 1.0) * (u[1 + DIM] - 0.5 * u[0] * v2);
-        W[DIM] = p / (u[0] * P.R);
+        W[DIM] = p * ir / P.R;
     };
     double Wo[NW];
     if (valid) {
         double uo[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) uo[v] = P.u[v * stride + gi];
+        for (int v = 0; v < NV; ++v) uo[v] = (P.u + (size_t)v * stride)[gi];
         prim(uo, Wo);
 #pragma unroll
         for (int w = 0; w < NW; ++w) sw[w * NN + node] = Wo[w];
+    } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) Wo[w] = 0.0;
     }
     __syncthreads();
-    if (!valid) return;
-    const double *g = P.geo + (size_t)e * GA;
+    const double *g = P.geo + (size_t)(valid ? e : 0) * GA;
+    double Ja[DIM * DIM];
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) Ja[k] = g[k];
+    const double iJ = 1.0 / g[DIM * DIM];
     double q[DIM][NW];
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
 #pragma unroll
         for (int w = 0; w < NW; ++w) q[c][w] = 0.0;
+    if (valid) {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        const int a = node_pos<N1>(node, d);
-        const int l = node_line<N1, DIM>(node, d);
-        double dW[NW];
+        for (int d = 0; d < DIM; ++d) {
+            const int a = node_pos<N1>(node, d);
+            const int l = node_line<N1, DIM>(node, d);
+            double dW[NW];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) dW[w] = 0.0;
+            for (int w = 0; w < NW; ++w) dW[w] = 0.0;
 #pragma unroll
-        for (int j = 0; j < N1; ++j) {
-            const double Dj = P.B.D[a * N1 + j];
-            const int nj = line_node<N1, DIM>(d, j, l);
+            for (int j = 0; j < N1; ++j) {
+                const double Dj = P.B.D[a * N1 + j];
+                const int nj = line_node<N1, DIM>(d, j, l);
 #pragma unroll
-            for (int w = 0; w < NW; ++w) dW[w] = fma(Dj, sw[w * NN + nj], dW[w]);
-        }
-        if (a == 0 || a == N) {
-            const int side = (a == N) ? 1 : 0;
-            const int nb = P.nbr[(size_t)e * 2 * DIM + 2 * d + side];
-            const int nbn = line_node<N1, DIM>(d, side ? 0 : N, l);
-            const size_t gj = (size_t)nb * NN + nbn;
-            double un[NV], Wn[NW];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) un[v] = P.u[v * stride + gj];
-            prim(un, Wn);
-            const double sc = side ? 1.0 / P.B.w[N] : -1.0 / P.B.w[0];
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const double ws = 0.5 * (Wo[w] + Wn[w]);
-                dW[w] = fma(sc, ws - Wo[w], dW[w]);
+                for (int w = 0; w < NW; ++w) dW[w] = fma(Dj, sw[w * NN + nj], dW[w]);
             }
+            if (a == 0 || a == N) {
+                const int side = (a == N) ? 1 : 0;
+                const int nb = P.nbr[e * 2 * DIM + 2 * d + side];
+                const unsigned gj = (unsigned)nb * NN + line_node<N1, DIM>(d, side ? 0 : N, l);
+                double un[NV], Wn[NW];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) un[v] = (P.u + (size_t)v * stride)[gj];
+                prim(un, Wn);
+                const double sc = side ? 1.0 / P.B.w[N] : -1.0 / P.B.w[0];
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const double ws = 0.5 * (Wo[w] + Wn[w]);
+                    dW[w] = fma(sc, ws - Wo[w], dW[w]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                for (int w = 0; w < NW; ++w) q[c][w] = fma(Ja[d * DIM + c], dW[w], q[c][w]);
         }
-#pragma unroll
-        for (int c = 0; c < DIM; ++c)
-#pragma unroll
-            for (int w = 0; w < NW; ++w) q[c][w] = fma(g[d * DIM + c], dW[w], q[c][w]);
     }
-    const double iJ = 1.0 / g[DIM * DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
 #pragma unroll
         for (int w = 0; w < NW; ++w) q[c][w] *= iJ;
-    double div = 0.0;
+    // nodal viscous flux
+    double Fv[DIM][NW];
+    {
+        double div = 0.0;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) div += q[k][k];
+        for (int k = 0; k < DIM; ++k) div += q[k][k];
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-        double en = 0.0;
+        for (int c = 0; c < DIM; ++c) {
+            double en = 0.0;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            double t = P.mu * (q[c][k] + q[k][c]);
-            if (k == c) t -= (2.0 / 3.0) * P.mu * div;
-            en = fma(t, Wo[k], en);
-            P.out[(size_t)(c * NW + k) * stride + gi] = t;
+            for (int k = 0; k < DIM; ++k) {
+                double t = P.mu * (q[c][k] + q[k][c]);
+                if (k == c) t -= (2.0 / 3.0) * P.mu * div;
+                en = fma(t, Wo[k], en);
+                Fv[c][k] = t;
+            }
+            Fv[c][DIM] = en + P.kappa * q[c][DIM];
         }
-        P.out[(size_t)(c * NW + DIM) * stride + gi] = en + P.kappa * q[c][DIM];
+    }
+    // divergence: volume part and the element's own half of the face terms
+    double vis[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) vis[k] = 0.0;
+    double *ff = P.out2;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        double Ft[NW];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) s = fma(Ja[d * DIM + c], Fv[c][k], s);
+            Ft[k] = s;
+        }
+        __syncthreads();  // previous readers of sw are done
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < NW; ++k) sw[k * NN + node] = Ft[k];
+        }
+        __syncthreads();
+        if (valid) {
+            const int a = node_pos<N1>(node, d);
+            const int l = node_line<N1, DIM>(node, d);
+#pragma unroll
+            for (int j = 0; j < N1; ++j) {
+                const double Dj = P.B.D[a * N1 + j];
+                const int nj = line_node<N1, DIM>(d, j, l);
+#pragma unroll
+                for (int k = 0; k < NW; ++k) vis[k] = fma(Dj, sw[k * NN + nj], vis[k]);
+            }
+            if (a == 0 || a == N) {
+                const int side = (a == N) ? 1 : 0;
+                const double sc = side ? -0.5 / P.B.w[N] : 0.5 / P.B.w[0];
+                double *fo = ff + ((size_t)e * 2 * DIM + 2 * d + side) * NW * NF + l;
+#pragma unroll
+                for (int k = 0; k < NW; ++k) {
+                    vis[k] = fma(sc, Ft[k], vis[k]);
+                    fo[k * NF] = Ft[k];
+                }
+            }
+        }
+    }
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) (P.out + (size_t)k * stride)[gi] = vis[k] * iJ;
     }
 }
 

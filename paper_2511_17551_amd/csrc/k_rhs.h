@@ -82,7 +82,7 @@ struct RhsShape {
     static constexpr int B1 = PD * NV;
     static constexpr int B2 = NFV * NV;
     static constexpr int B3 = NSF * NV;
-    static constexpr int B4 = EQ == 1 ? NW * NN : 0;
+    static constexpr int B4 = 0;
     static constexpr int B5 = EQ == 1 ? NSF * NW : 0;
     static constexpr int M12 = B1 > B2 ? B1 : B2;
     static constexpr int M34 = B3 > B4 ? B3 : B4;
@@ -409,46 +409,24 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     for (int v = 0; v < NV; ++v) du[v] = -fma(1.0 - alpha, dg[v], acc[v]) * iJ;
 
     // ---- BR1 viscous divergence (perfect-gas Navier-Stokes, affine elements).
-    // P.grad holds the nodal viscous fluxes F_v[c][k] ([dim][dim+1][E][nn]).
+    // k_grad wrote the element-local part (P.vpart) and every element's face
+    // contravariant viscous fluxes (P.grad); what remains are the neighbours'
+    // halves of the averaged interface fluxes, +-Ft_nbr / (2 w).
     if constexpr (EQ == 1) {
         double vis[NW];
 #pragma unroll
         for (int k = 0; k < NW; ++k) vis[k] = 0.0;
-        // interface terms: (F* - F~_own) / w with F* = (F_own + F_nbr).n / 2
 #pragma unroll
         for (int r = 0; r < (NSF + NN - 1) / NN; ++r) {
             const int it = r * NN + node;
             if (valid && it < NSF) {
                 const int f = it / NF;
                 const int q = it - f * NF;
-                const int d = f >> 1, side = f & 1;
-                const int nd = line_node<N1, DIM>(d, side ? N : 0, q);
                 const int nb = P.nbr[ebase + f];
-                const int nbn = line_node<N1, DIM>(d, side ? 0 : N, q);
-                const size_t go = (size_t)e * NN + nd;
-                const size_t gj = (size_t)nb * NN + nbn;
-                double nrm[DIM], jown[DIM];
-                jaf_row<DIM>(Jaf, d, jown);
-                if (side) {
+                const double *fn = P.grad + ((size_t)nb * 2 * DIM + (f ^ 1)) * NW * NF + q;
+                const double sc = (f & 1) ? 0.5 / P.B.w[N] : -0.5 / P.B.w[0];
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) nrm[c] = jown[c];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(size_t)nb * GA + d * DIM + c];
-                }
-#pragma unroll
-                for (int k = 0; k < NW; ++k) {
-                    double fo = 0.0, fn = 0.0, ft = 0.0;
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) {
-                        const double Fo = P.grad[(size_t)(c * NW + k) * stride + go];
-                        const double Fn = P.grad[(size_t)(c * NW + k) * stride + gj];
-                        fo = fma(Fo, nrm[c], fo);
-                        fn = fma(Fn, nrm[c], fn);
-                        ft = fma(jown[c], Fo, ft);
-                    }
-                    buf[k * NSF + it] = 0.5 * (fo + fn) - ft;
-                }
+                for (int k = 0; k < NW; ++k) buf[k * NSF + it] = sc * fn[k * NF];
             }
         }
         __syncthreads();
@@ -458,50 +436,16 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                 const int a = node_pos<N1>(node, d);
                 const int l = node_line<N1, DIM>(node, d);
                 if (a == N) {
-                    const double sc = 1.0 / P.B.w[N];
 #pragma unroll
-                    for (int k = 0; k < NW; ++k) vis[k] = fma(sc, buf[k * NSF + (2 * d + 1) * NF + l], vis[k]);
+                    for (int k = 0; k < NW; ++k) vis[k] += buf[k * NSF + (2 * d + 1) * NF + l];
                 } else if (a == 0) {
-                    const double sc = -1.0 / P.B.w[0];
 #pragma unroll
-                    for (int k = 0; k < NW; ++k) vis[k] = fma(sc, buf[k * NSF + (2 * d) * NF + l], vis[k]);
+                    for (int k = 0; k < NW; ++k) vis[k] += buf[k * NSF + (2 * d) * NF + l];
                 }
             }
+#pragma unroll
+            for (int k = 0; k < NW; ++k) du[1 + k] += fma(vis[k], iJ, P.vpart[(size_t)k * stride + gi]);
         }
-        __syncthreads();
-        // volume terms: sum_d D_d (Ja^d . F_v)
-        double Fv[DIM][NW];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c)
-#pragma unroll
-            for (int k = 0; k < NW; ++k) Fv[c][k] = valid ? P.grad[(size_t)(c * NW + k) * stride + gi] : 0.0;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            if (valid) {
-#pragma unroll
-                for (int k = 0; k < NW; ++k) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) s = fma(Jaf[d * DIM + c], Fv[c][k], s);
-                    buf[k * NN + node] = s;
-                }
-            }
-            __syncthreads();
-            if (valid) {
-                const int a = node_pos<N1>(node, d);
-                const int l = node_line<N1, DIM>(node, d);
-#pragma unroll
-                for (int j = 0; j < N1; ++j) {
-                    const double Dj = P.B.D[a * N1 + j];
-                    const int nj = line_node<N1, DIM>(d, j, l);
-#pragma unroll
-                    for (int k = 0; k < NW; ++k) vis[k] = fma(Dj, buf[k * NN + nj], vis[k]);
-                }
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int k = 0; k < NW; ++k) du[1 + k] = fma(vis[k], iJ, du[1 + k]);
     }
 
     // ---- finite-rate chemistry source
