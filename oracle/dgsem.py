@@ -177,7 +177,7 @@ class Operator:
             d, side = divmod(int(f), 2)
             nodes = self.fn[f]
             ui = u[:, e, nodes]
-            si = gas.take(s, (np.array([e]), nodes))
+            si = gas.take(s, (np.array([[e]]), nodes[None, :]))
             si = {k: (v[..., 0, :] if isinstance(v, np.ndarray) else v) for k, v in si.items()}
             n = self.Ja[d][:, e, nodes]
             Ti = si.get("T")

@@ -49,9 +49,11 @@ class Mixture:
         out = np.array(np.broadcast_to(1.5 * self._col(self.Rs, nd), (self.ns,) + np.shape(T)))
         for s in range(self.ns):
             if self.mol[s]:
+                # d/dT of R theta/(e^x - 1), x = theta/T, in the overflow-free
+                # form R x^2 e^-x / (1 - e^-x)^2
                 x = self.th[s] / T
-                ex = np.exp(x)
-                out[s] = out[s] + self.Rs[s] + self.Rs[s] * x * x * ex / (ex - 1.0) ** 2
+                em = np.exp(-x)
+                out[s] = out[s] + self.Rs[s] + self.Rs[s] * x * x * em / (-np.expm1(-x)) ** 2
         return out
 
     def rho_e(self, rs, T):
@@ -67,26 +69,29 @@ class Mixture:
         Returns T and the iteration count per node; raises if any node
         fails to converge within maxit.
         """
-        T = np.array(np.broadcast_to(T0, np.shape(rhoe)), float)
-        it = np.zeros(np.shape(rhoe), np.int64)
-        active = np.ones(np.shape(rhoe), bool)
+        shape = np.shape(rhoe)
+        rs = rs.reshape(self.ns, -1)
+        target = np.reshape(rhoe, -1)
+        T = np.array(np.broadcast_to(T0, shape), float).reshape(-1)
+        it = np.zeros(T.shape, np.int64)
+        active = np.ones(T.shape, bool)
         for _ in range(maxit):
             if not active.any():
                 break
-            Ta = T[active]
-            rsa = rs[:, active]
-            f = self.rho_e(rsa, Ta) - rhoe[active]
+            idx = np.flatnonzero(active)
+            Ta = T[idx]
+            rsa = rs[:, idx]
+            f = self.rho_e(rsa, Ta) - target[idx]
             fp = self.rho_cv(rsa, Ta)
             dT = f / fp
             Tn = Ta - dT
-            T[active] = Tn
-            it[active] += 1
+            T[idx] = Tn
+            it[idx] += 1
             done = np.abs(dT) <= tol * np.abs(Tn)
-            idx = np.flatnonzero(active)
             active[idx[done]] = False
         if active.any():
             raise RuntimeError("Newton for T(e) did not converge")
-        return T, it
+        return T.reshape(shape), it.reshape(shape)
 
     def pressure(self, rs, T):
         return np.sum(rs * self.Rs.reshape((-1,) + (1,) * np.ndim(T)), axis=0) * T

@@ -81,10 +81,13 @@ __device__ __forceinline__ void mix_energy_cv(const MixC &M, const double *rs, d
         double es = 1.5 * M.Rs[s] * T + M.e0[s];
         double cs = 1.5 * M.Rs[s];
         if (M.mol[s]) {
-            const double x = M.thv[s] / T;
-            const double em1 = expm1(x);
-            es += M.Rs[s] * T + M.Rs[s] * M.thv[s] / em1;
-            cs += M.Rs[s] + M.Rs[s] * x * x * (em1 + 1.0) / (em1 * em1);
+            const double x = M.thv[s] * rcp(T);
+            const double em = exp(-x);
+            const double om = -expm1(-x);  // 1 - e^-x
+            // R theta/(e^x - 1) = R theta e^-x / (1 - e^-x); its T-derivative R x^2 e^-x / (1 - e^-x)^2
+            const double q = em * rcp(om);
+            es += M.Rs[s] * T + M.Rs[s] * M.thv[s] * q;
+            cs += M.Rs[s] + M.Rs[s] * x * x * q * rcp(om);
         }
         e = fma(rs[s], es, e);
         cv = fma(rs[s], cs, cv);
@@ -121,9 +124,9 @@ __device__ __forceinline__ double mix_sound(const MixC &M, const double *rs, dou
     for (int s = 0; s < kNS; ++s) {
         double cs = 1.5 * M.Rs[s];
         if (M.mol[s]) {
-            const double x = M.thv[s] / T;
-            const double em1 = expm1(x);
-            cs += M.Rs[s] + M.Rs[s] * x * x * (em1 + 1.0) / (em1 * em1);
+            const double x = M.thv[s] * rcp(T);
+            const double om = -expm1(-x);
+            cs += M.Rs[s] + M.Rs[s] * x * x * exp(-x) * rcp(om * om);
         }
         cv = fma(rs[s], cs, cv);
     }

@@ -421,11 +421,14 @@ def case_c3(energy, cv, n=24, N=4, seed=3, T1=300.0, p1=1.0e4, mach=3.0, xs=0.3,
 
 
 def case_c4(energy, cv, nr=64, nth=128, N=3, seed=4, T=300.0, p=1.0e3, mach=8.0,
-            r0=1.0, r1=8.0, shock=True):
+            r0=1.0, r1=8.0, shock=True, hot=False):
     """2D reacting 5-species Euler around a cylinder on an annular O-grid.
 
     Freestream (T, p, mach along +x) everywhere at t = 0; slip wall at
-    r = r0, freestream Dirichlet state at r = r1.
+    r = r0, freestream Dirichlet state at r = r1.  ``hot=True`` replaces the
+    impulsive start by a state with a hot, partly dissociated, decelerated
+    layer in front of the cylinder (a seeded stand-in for the post-shock
+    region) so that every term of the right-hand side is active.
     """
     sp = Species()
     rx = park17_reactions(seed)
@@ -441,6 +444,19 @@ def case_c4(energy, cv, nr=64, nth=128, N=3, seed=4, T=300.0, p=1.0e3, mach=8.0,
     E = energy(rs[:, None], np.array([T]))[0] + 0.5 * rho * uinf * uinf
     state = np.concatenate([rs, [rho * uinf, 0.0, E]])
     u0 = np.broadcast_to(state[:, None, None], (8,) + x.shape[1:]).copy()
+    if hot:
+        rng = np.random.default_rng(seed + 100)
+        g = np.exp(-((x[0] + 1.6) ** 2 + 0.5 * x[1] ** 2) / 0.6)
+        Tn = 3000.0 + 5000.0 * g         # hot everywhere: finite, well-scaled sources
+        f = 0.05 + 0.5 * g               # dissociated fraction
+        jit = 1.0 + 0.02 * rng.uniform(-1, 1, (5, 1, 1))
+        Y = np.stack([0.767 * (1 - f), 0.233 * (1 - 0.8 * f), 0.05 * f * jit[2],
+                      0.767 * f * 0.9 * jit[3], 0.233 * 0.8 * f * jit[4]], 0)
+        Y = Y / Y.sum(0)[None]
+        rho_n = rho * (1.0 + 4.0 * g)
+        ux = uinf * (1.0 - 0.85 * g)
+        uy = 0.1 * uinf * g * np.sign(x[1])
+        u0 = mixture_state(Y, rho_n, (ux, uy), Tn, energy)
     mesh = Mesh(2, N, x, faces, bfaces, np.zeros((0, 5), np.int32),
                 np.array([BC_SLIPWALL, BC_DIRICHLET], np.int32),
                 np.stack([state, state]))

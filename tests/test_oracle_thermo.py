@@ -1,0 +1,133 @@
+"""Pins of the oracle's RRHO thermodynamics, T(e) Newton and kinetics.
+
+Thermodynamics: round trip T -> e -> T; atoms-only closed form; the
+theta_v -> infinity limit; cv as the derivative of e.  Kinetics: total mass
+and element conservation of the sources, detailed balance at the
+equilibrium composition fixed by K_c, and the Gibbs-Helmholtz relation
+d(g_s/T)/dT = -h_s/T^2 (which pins the signs of every modal Gibbs term).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2511_17551_amd import workloads as W
+from oracle.thermo import Mixture
+from oracle.kinetics import Kinetics
+
+
+@pytest.fixture(scope="module")
+def mix():
+    return Mixture(W.Species())
+
+
+@pytest.fixture(scope="module")
+def kin():
+    return Kinetics(W.Species(), W.park17_reactions(4))
+
+
+def test_round_trip(mix):
+    rng = np.random.default_rng(0)
+    T = np.exp(rng.uniform(math.log(100.0), math.log(30000.0), 2000))
+    rs = rng.uniform(0.0, 1.0, (5, 2000)) * 10.0 ** rng.uniform(-4, 0, (5, 2000))
+    rhoe = mix.rho_e(rs, T)
+    T2, it = mix.solve_T(rs, rhoe, 300.0)
+    assert np.max(np.abs(T2 - T) / T) < 1e-13
+    assert it.max() <= 50
+
+
+def test_atoms_closed_form(mix):
+    rs = np.zeros((5, 3))
+    rs[3] = [0.1, 0.3, 0.0]
+    rs[4] = [0.2, 0.0, 0.5]
+    T = np.array([500.0, 4000.0, 12000.0])
+    sp = W.Species()
+    Rs = sp.Ru / sp.W
+    e = mix.rho_e(rs, T)
+    exact = (rs * (1.5 * Rs[:, None] * T + sp.e0[:, None])).sum(0)
+    assert np.allclose(e, exact, rtol=1e-14)
+    T2, _ = mix.solve_T(rs, e, 300.0)
+    Tc = (e - (rs * sp.e0[:, None]).sum(0)) / (1.5 * (rs * Rs[:, None]).sum(0))
+    assert np.allclose(T2, Tc, rtol=1e-13)
+
+
+def test_frozen_vibration_limit():
+    sp = W.Species()
+    sp.theta_v = np.array([1e7, 1e7, 1e7, 0.0, 0.0])
+    m = Mixture(sp)
+    T = np.array([300.0, 1000.0])
+    rs = np.zeros((5, 2))
+    rs[0] = 1.0
+    Rs = sp.Ru / sp.W
+    assert np.allclose(m.rho_e(rs, T), 2.5 * Rs[0] * T + sp.e0[0], rtol=1e-14)
+    assert np.allclose(m.rho_cv(rs, T), 2.5 * Rs[0], rtol=1e-14)
+
+
+def test_cv_is_de_dT(mix):
+    T = np.linspace(200.0, 20000.0, 50)
+    h = 1e-4 * T
+    for s in range(5):
+        rs = np.zeros((5, T.size))
+        rs[s] = 1.0
+        fd = (mix.rho_e(rs, T + h) - mix.rho_e(rs, T - h)) / (2 * h)
+        assert np.allclose(mix.rho_cv(rs, T), fd, rtol=1e-8)
+
+
+def test_gibbs_helmholtz(kin, mix):
+    T = np.linspace(300.0, 20000.0, 40)
+    h = 1e-4 * T
+    gT = lambda t: kin.gibbs_species(t) / t
+    fd = (gT(T + h) - gT(T - h)) / (2 * h)
+    hs = kin.enthalpy_species(T, mix)
+    assert np.allclose(fd, -hs / T ** 2, rtol=1e-7)
+
+
+def test_sources_conserve_mass_and_elements(kin):
+    rng = np.random.default_rng(1)
+    rs = rng.uniform(1e-6, 1e-2, (5, 500))
+    T = rng.uniform(2000.0, 15000.0, 500)
+    w = kin.omega_dot(rs, T)
+    scale = np.abs(w).max(0)
+    assert np.all(np.abs(w.sum(0)) <= 1e-12 * scale)
+    sp = W.Species()
+    nN = np.array([2, 0, 1, 1, 0])
+    nO = np.array([0, 2, 1, 0, 1])
+    molar = w / sp.W[:, None]
+    mscale = np.abs(molar).max(0)
+    assert np.all(np.abs((nN[:, None] * molar).sum(0)) <= 1e-12 * mscale)
+    assert np.all(np.abs((nO[:, None] * molar).sum(0)) <= 1e-12 * mscale)
+
+
+def test_detailed_balance(kin):
+    """At [N]^2 = K1 [N2], [O]^2 = K6 [O2], [NO] = [N][O]/K11 every rate vanishes."""
+    sp = W.Species()
+    for T in (3000.0, 6000.0, 10000.0):
+        lnK = kin.ln_Kc(np.array(T))
+        K_N2, K_O2, K_NO = math.exp(lnK[0]), math.exp(lnK[5]), math.exp(lnK[10])
+        cN2, cO2 = 10.0, 3.0
+        cN = math.sqrt(K_N2 * cN2)
+        cO = math.sqrt(K_O2 * cO2)
+        cNO = cN * cO / K_NO
+        conc = np.array([cN2, cO2, cNO, cN, cO])
+        rs = (conc * sp.W)[:, None]
+        R = kin.rates(rs, np.array([T]))
+        kf = kin.kf(np.array([T]))
+        fwd_scale = np.abs(kf[:, 0]) * conc.max() ** 2
+        assert np.all(np.abs(R[:, 0]) <= 1e-10 * fwd_scale)
+
+
+def test_single_reaction_closed_form(kin):
+    """Reaction 15, N2 + O <=> NO + N, against its mass-action formula."""
+    sp = W.Species()
+    T = 7000.0
+    conc = np.array([5.0, 1.0, 0.5, 0.2, 0.8])
+    rs = (conc * sp.W)[:, None]
+    rx = kin.rx
+    r = 15
+    kf = rx.A[r] * T ** rx.b[r] * math.exp(-rx.theta_a[r] / T)
+    G = kin.gibbs_species(np.array([T]))[:, 0] * sp.W
+    dG = G[2] + G[3] - G[0] - G[4]
+    Kc = math.exp(-dG / (sp.Ru * T))
+    R = kf * conc[0] * conc[4] - kf / Kc * conc[2] * conc[3]
+    got = kin.rates(rs, np.array([T]))[r, 0]
+    assert abs(got - R) <= 1e-12 * abs(kf * conc[0] * conc[4])
