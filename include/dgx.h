@@ -210,6 +210,20 @@ int dgx_surrogate_train(dgx_ctx *ctx, const double *states, const double *T, int
                         int epochs, int batch, float lr, uint64_t seed, float *loss_host,
                         void *stream);
 
+/* Initialise the surrogate for a training set (packed device states
+ * [nvar][count] and labels T [count]): normalisation statistics (feature and
+ * temperature means and standard deviations, FP64 on the host) and
+ * Glorot-uniform weights drawn from `seed`; resets the Adam state.
+ * Synchronises. */
+int dgx_surrogate_init(dgx_ctx *ctx, const double *states, const double *T, int64_t count, uint64_t seed,
+                       void *stream);
+
+/* Gradient of the mean squared error of the standardised temperature over
+ * all `count` samples with the current parameters (no update): grad_host
+ * [8833] FP32, *loss_host (may be NULL) the loss.  Synchronises. */
+int dgx_surrogate_grad(dgx_ctx *ctx, const double *states, const double *T, int64_t count, float *grad_host,
+                       float *loss_host, void *stream);
+
 /* Surrogate prediction T_guess for packed states (device [nvar][count]) into
  * Tg (device [count], FP64).  Enqueued on stream. */
 int dgx_surrogate_predict(dgx_ctx *ctx, const double *states, int64_t count, double *Tg,

@@ -806,6 +806,23 @@ int dgx_surrogate_train(dgx_ctx *ctx, const double *states, const double *T, int
     return DGX_OK;
 }
 
+int dgx_surrogate_init(dgx_ctx *ctx, const double *states, const double *T, int64_t count, uint64_t seed,
+                       void *stream) {
+    if (!ctx || !is_mix(ctx)) return set_err(ctx, DGX_E_INVAL, "surrogate needs a mixture context");
+    if (!states || !T || count < 2) return set_err(ctx, DGX_E_INVAL, "bad init arguments");
+    int rc = surrogate_init(ctx->sur, ctx->cfg.dim, states, T, count, seed, (hipStream_t)stream);
+    return rc ? set_err(ctx, rc, "surrogate init failed") : DGX_OK;
+}
+
+int dgx_surrogate_grad(dgx_ctx *ctx, const double *states, const double *T, int64_t count, float *grad_host,
+                       float *loss_host, void *stream) {
+    if (!ctx || !is_mix(ctx)) return set_err(ctx, DGX_E_INVAL, "surrogate needs a mixture context");
+    if (!states || !T || !grad_host || count < 1) return set_err(ctx, DGX_E_INVAL, "bad grad arguments");
+    if (!ctx->sur.ready) return set_err(ctx, DGX_E_STATE, "surrogate has no weights");
+    int rc = surrogate_grad(ctx->sur, ctx->cfg.dim, states, T, count, grad_host, loss_host, (hipStream_t)stream);
+    return rc ? set_err(ctx, rc, "surrogate gradient failed") : DGX_OK;
+}
+
 int dgx_surrogate_predict(dgx_ctx *ctx, const double *states, int64_t count, double *Tg, void *stream) {
     if (!ctx || !is_mix(ctx) || !states || !Tg || count <= 0) return set_err(ctx, DGX_E_INVAL, "bad predict arguments");
     if (!ctx->sur.ready) return set_err(ctx, DGX_E_STATE, "surrogate has no weights");

@@ -19,6 +19,7 @@ struct Surrogate {
     bool ready = false;
     float *params = nullptr;  // device [kSurParams + kSurNorm] FP32 master copy
     float *adam_m = nullptr, *adam_v = nullptr, *grads = nullptr;
+    int64_t step = 0;  // Adam steps taken
     std::string err;
 };
 
@@ -27,6 +28,10 @@ int surrogate_get(Surrogate &S, float *host_params);
 int surrogate_predict(Surrogate &S, int dim, const double *states, int64_t count, double *Tg, hipStream_t s);
 int surrogate_train(Surrogate &S, int dim, const double *states, const double *T, int64_t count, int epochs,
                     int batch, float lr, uint64_t seed, float *loss_host, hipStream_t s);
+int surrogate_grad(Surrogate &S, int dim, const double *states, const double *T, int64_t count, float *grad_host,
+                   float *loss_host, hipStream_t s);
+int surrogate_init(Surrogate &S, int dim, const double *states, const double *T, int64_t count, uint64_t seed,
+                   hipStream_t s);
 void surrogate_free(Surrogate &S);
 
 }  // namespace dgx

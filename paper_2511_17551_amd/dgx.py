@@ -83,6 +83,8 @@ def _load():
         "dgx_surrogate_train": ([vp, vp, vp, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_uint64,
                                  C.POINTER(C.c_float), vp], C.c_int),
         "dgx_surrogate_predict": ([vp, vp, C.c_int64, vp, vp], C.c_int),
+        "dgx_surrogate_init": ([vp, vp, vp, C.c_int64, C.c_uint64, vp], C.c_int),
+        "dgx_surrogate_grad": ([vp, vp, vp, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float), vp], C.c_int),
         "dgx_check": ([vp, vp], C.c_int),
         "dgx_species_energy": ([vp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
         "dgx_kernel_times": ([vp, vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_char_p,
@@ -102,7 +104,7 @@ def _load():
 lib = _load()
 EXPORTED = ("dgx_create", "dgx_set_mesh", "dgx_rhs", "dgx_ssprk3_step", "dgx_max_dt", "dgx_thermo",
             "dgx_last_alpha", "dgx_surrogate_set", "dgx_surrogate_get", "dgx_surrogate_train",
-            "dgx_surrogate_predict", "dgx_check", "dgx_species_energy", "dgx_kernel_times", "dgx_autotune",
+            "dgx_surrogate_predict", "dgx_surrogate_init", "dgx_surrogate_grad", "dgx_check", "dgx_species_energy", "dgx_kernel_times", "dgx_autotune",
             "dgx_set_launch", "dgx_last_error", "dgx_destroy")
 
 
@@ -263,6 +265,18 @@ def dgx_surrogate_train(ctx, states, T, epochs, batch, lr, seed=42, stream=None)
     _raise(ctx, lib.dgx_surrogate_train(ctx, _dev(states), _dev(T), count, epochs, batch, lr, seed,
                                         _ptr(loss, C.c_float), _stream(stream)))
     return loss
+
+
+def dgx_surrogate_init(ctx, states, T, seed=41, stream=None):
+    _raise(ctx, lib.dgx_surrogate_init(ctx, _dev(states), _dev(T), T.shape[0], int(seed), _stream(stream)))
+
+
+def dgx_surrogate_grad(ctx, states, T, stream=None):
+    g = np.zeros(SUR_PARAMS, np.float32)
+    loss = C.c_float()
+    _raise(ctx, lib.dgx_surrogate_grad(ctx, _dev(states), _dev(T), T.shape[0], _ptr(g, C.c_float), C.byref(loss),
+                                       _stream(stream)))
+    return g, loss.value
 
 
 def dgx_surrogate_predict(ctx, states, Tg, stream=None):
