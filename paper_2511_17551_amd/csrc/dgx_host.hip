@@ -115,7 +115,10 @@ struct dgx_ctx {
     bool mesh_ok = false;
     int nbc = 0;
     DevBuf<double> geo, Jn, nsub, bc_state, bc_T, T, alpha, alpha_tmp, alpha_raw, grad, vpart, u1, u2, dtbuf;
-    DevBuf<int> nbr, bc_kind;
+    DevBuf<int> nbr, bc_kind, mort;
+    DevBuf<double> mflux;
+    int nmortar = 0;
+    double Im[2][25] = {}, Pm[2][25] = {};
     DevBuf<KinC> kin_d;
     DevBuf<unsigned> flags;
     DevBuf<unsigned long long> rate;
@@ -213,6 +216,10 @@ RhsParams base_params(dgx_ctx *ctx) {
     P.bc_state = ctx->bc_state.p;
     P.bc_T = ctx->bc_T.p;
     P.kin = ctx->kin_d.p;
+    P.mort = ctx->mort.p;
+    P.mflux = ctx->mflux.p;
+    std::memcpy(P.Im, ctx->Im, sizeof(P.Im));
+    std::memcpy(P.Pm, ctx->Pm, sizeof(P.Pm));
     P.gamma = ctx->cfg.gamma;
     P.R = ctx->cfg.R;
     P.mu = ctx->cfg.mu;
@@ -307,6 +314,18 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
         else return set_err(ctx, DGX_E_INVAL, "NS gradients not built for this dim/N");
         tape_mark(tp, "k_grad", s);
     }
+    if (ctx->nmortar) {
+        const int th2 = c.dim == 3 ? 128 : 64;
+        const int key = c.dim * 100 + c.N * 10 + c.surface_flux;
+        switch (key) {
+            case 330: hipLaunchKernelGGL((k_mortar<3, 3, 0>), dim3(ctx->nmortar), dim3(th2), 0, s, P, ctx->nmortar); break;
+            case 331: hipLaunchKernelGGL((k_mortar<3, 3, 1>), dim3(ctx->nmortar), dim3(th2), 0, s, P, ctx->nmortar); break;
+            case 340: hipLaunchKernelGGL((k_mortar<3, 4, 0>), dim3(ctx->nmortar), dim3(th2), 0, s, P, ctx->nmortar); break;
+            case 230: hipLaunchKernelGGL((k_mortar<2, 3, 0>), dim3(ctx->nmortar), dim3(th2), 0, s, P, ctx->nmortar); break;
+            default: return set_err(ctx, DGX_E_INVAL, "no mortar kernel for this configuration");
+        }
+        tape_mark(tp, "k_mortar", s);
+    }
     P.out = out;
     P.u0 = u0;
     P.sa = sa;
@@ -367,6 +386,7 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
     ctx->nf = ctx->nn / ctx->N1;
     ctx->nvar = (mix ? 5 : 1) + cfg->dim + 1;
     ctx->basis = make_basis(cfg->N);
+    mortar_operators(ctx->basis, ctx->Im, ctx->Pm);
     for (int i = 0; i < ctx->N1 * ctx->N1; ++i) {
         ctx->bc.D[i] = ctx->basis.D[i];
         ctx->bc.Vinv[i] = ctx->basis.Vinv[i];
@@ -446,7 +466,9 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
     if (m->nface < 0 || (m->nface && !m->faces) || m->nbface < 0 || (m->nbface && !m->bfaces) ||
         m->nbc < 0 || (m->nbc && (!m->bc_kind || !m->bc_state)))
         return set_err(ctx, DGX_E_INVAL, "bad mesh tables");
-    if (m->nmortar != 0) return set_err(ctx, DGX_E_INVAL, "mortar meshes need the AMR path");
+    if (m->nmortar < 0 || (m->nmortar && !m->mortars)) return set_err(ctx, DGX_E_INVAL, "bad mortar table");
+    if (m->nmortar && ctx->cfg.equation != DGX_EQ_EULER)
+        return set_err(ctx, DGX_E_INVAL, "mortars are supported for the perfect-gas Euler equations");
     clear_graph(ctx);
     ctx->mesh_ok = false;
     // connectivity
@@ -463,6 +485,19 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         if (e < 0 || e >= E || f < 0 || f >= 2 * dim || b < 0 || b >= m->nbc)
             return set_err(ctx, DGX_E_INVAL, "bad boundary face " + std::to_string(i));
         nbr[(size_t)e * 2 * dim + f] = -1 - b;
+    }
+    const int nsub = dim == 3 ? 4 : 2;
+    for (int i = 0; i < m->nmortar; ++i) {
+        const int32_t *row = m->mortars + (size_t)i * (3 + nsub);
+        const int eL = row[0], fL = row[1], fS = row[2 + nsub];
+        if (eL < 0 || eL >= E || fL < 0 || fL >= 2 * dim || fS != (fL ^ 1))
+            return set_err(ctx, DGX_E_INVAL, "bad mortar row " + std::to_string(i));
+        nbr[(size_t)eL * 2 * dim + fL] = kMortBase - (8 * i + 7);
+        for (int s2 = 0; s2 < nsub; ++s2) {
+            const int es = row[2 + s2];
+            if (es < 0 || es >= E) return set_err(ctx, DGX_E_INVAL, "bad mortar element");
+            nbr[(size_t)es * 2 * dim + fS] = kMortBase - (8 * i + s2);
+        }
     }
     for (size_t i = 0; i < nbr.size(); ++i)
         if (nbr[i] == INT_MIN) return set_err(ctx, DGX_E_INVAL, "element face without neighbour or boundary");
@@ -492,6 +527,7 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         if (dev > 1e-12 * mx) affine = false;
     }
     if (ctx->cfg.equation == DGX_EQ_NS && !affine) return set_err(ctx, DGX_E_INVAL, "NS needs affine elements");
+    if (m->nmortar && !affine) return set_err(ctx, DGX_E_INVAL, "mortars need affine elements");
     // pick the kernel variant for this geometry
     const RhsEntry *sel = nullptr;
     for (const auto &e : kRhs)
@@ -555,6 +591,13 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
             if ((rc = dalloc(ctx, ctx->nsub, ns.size()))) return rc;
             HIPCHK(hipMemcpy(ctx->nsub.p, ns.data(), ns.size() * sizeof(double), hipMemcpyHostToDevice));
         }
+    }
+    // mortars
+    ctx->nmortar = m->nmortar;
+    if (m->nmortar) {
+        if ((rc = dalloc(ctx, ctx->mort, (size_t)m->nmortar * (3 + nsub)))) return rc;
+        HIPCHK(hipMemcpy(ctx->mort.p, m->mortars, (size_t)m->nmortar * (3 + nsub) * sizeof(int), hipMemcpyHostToDevice));
+        if ((rc = dalloc(ctx, ctx->mflux, (size_t)m->nmortar * nsub * nv * ctx->nf))) return rc;
     }
     // boundary states
     if (m->nbc) {
@@ -936,6 +979,8 @@ void dgx_destroy(dgx_ctx *ctx) {
     for (auto *b : bufs) b->release();
     ctx->nbr.release();
     ctx->bc_kind.release();
+    ctx->mort.release();
+    ctx->mflux.release();
     ctx->kin_d.release();
     ctx->flags.release();
     ctx->rate.release();

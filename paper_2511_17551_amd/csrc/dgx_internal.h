@@ -37,6 +37,11 @@ struct KinC {
     double lnpref_Ru;               // ln(p_ref / R_u)
 };
 
+// Face codes of the element-neighbour table: >= 0 conforming neighbour,
+// in (kMortBase, -1] boundary -1 - bc, <= kMortBase mortar
+// kMortBase - (8 m + role), role = small position (0..3) or 7 (large side).
+constexpr int kMortBase = -(1 << 24);
+
 // Device error flags (bit mask), sticky until dgx_check.
 enum : unsigned { FLAG_NONPHYS = 1u, FLAG_NOCONV = 2u };
 
@@ -59,7 +64,10 @@ struct RhsParams {
     const double *bc_state; // [nbc][nvar]
     const double *bc_T;     // [nbc] temperatures of Dirichlet states (mixture)
     const KinC *kin;        // reacting mixture
-    const int *mort;        // element -> mortar slot table (unused when null)
+    const int *mort;        // mortar table [nm][3 + 2^(dim-1)] (eL, fL, eS.., fS)
+    const double *mflux;    // mortar sub-face fluxes [nm][2^(dim-1)][nvar][nf]
+    double Im[2][25];       // interpolation to the lower / upper half of a face edge
+    double Pm[2][25];       // L2 projection back from the halves
     double gamma, R, mu, kappa;
     int epb;                // elements per block
     unsigned *flags;

@@ -157,4 +157,82 @@ inline void element_metrics(const HostBasis &B, int dim, const double *const *xe
     }
 }
 
+// Value of the Lagrange basis polynomial j on the LGL nodes at point y.
+inline double lagrange(const HostBasis &B, int j, double y) {
+    double v = 1.0;
+    for (int k = 0; k < B.N1; ++k)
+        if (k != j) v *= (y - B.x[k]) / (B.x[j] - B.x[k]);
+    return v;
+}
+
+// Mortar operators: interpolation of a face edge to its lower/upper half,
+// I_s[i][j] = l_j((x_i -+ 1)/2), and the exact L2 projection back,
+// P_s = 1/2 M^-1 I_s^T M with the exact mass matrix M_ij = int l_i l_j
+// (Gauss-Legendre quadrature with N+1 points).
+inline void mortar_operators(const HostBasis &B, double Im[2][25], double Pm[2][25]) {
+    const int n1 = B.N1;
+    // Gauss-Legendre points: roots of P_{n1} by Newton
+    std::vector<double> xg(n1), wg(n1);
+    for (int i = 0; i < n1; ++i) {
+        double x = -std::cos(M_PI * (i + 0.75) / (n1 + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p, dp;
+            legendre_pd(n1, x, p, dp);
+            const double dx = p / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        double p, dp;
+        legendre_pd(n1, x, p, dp);
+        xg[i] = x;
+        wg[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    std::vector<double> M(n1 * n1, 0.0);
+    for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < n1; ++j)
+            for (int q = 0; q < n1; ++q) M[i * n1 + j] += wg[q] * lagrange(B, i, xg[q]) * lagrange(B, j, xg[q]);
+    // inverse by Gauss-Jordan elimination with partial pivoting
+    std::vector<double> A(M), Inv(n1 * n1, 0.0);
+    for (int i = 0; i < n1; ++i) Inv[i * n1 + i] = 1.0;
+    for (int c = 0; c < n1; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n1; ++r)
+            if (std::fabs(A[r * n1 + c]) > std::fabs(A[piv * n1 + c])) piv = r;
+        for (int k = 0; k < n1; ++k) {
+            std::swap(A[c * n1 + k], A[piv * n1 + k]);
+            std::swap(Inv[c * n1 + k], Inv[piv * n1 + k]);
+        }
+        const double d = A[c * n1 + c];
+        for (int k = 0; k < n1; ++k) {
+            A[c * n1 + k] /= d;
+            Inv[c * n1 + k] /= d;
+        }
+        for (int r = 0; r < n1; ++r) {
+            if (r == c) continue;
+            const double f = A[r * n1 + c];
+            for (int k = 0; k < n1; ++k) {
+                A[r * n1 + k] -= f * A[c * n1 + k];
+                Inv[r * n1 + k] -= f * Inv[c * n1 + k];
+            }
+        }
+    }
+    for (int s = 0; s < 2; ++s) {
+        const double sh = s == 0 ? -1.0 : 1.0;
+        std::vector<double> I(n1 * n1), T(n1 * n1, 0.0);
+        for (int i = 0; i < n1; ++i)
+            for (int j = 0; j < n1; ++j) I[i * n1 + j] = lagrange(B, j, 0.5 * (B.x[i] + sh));
+        // T = I^T M
+        for (int i = 0; i < n1; ++i)
+            for (int j = 0; j < n1; ++j)
+                for (int k = 0; k < n1; ++k) T[i * n1 + j] += I[k * n1 + i] * M[k * n1 + j];
+        for (int i = 0; i < n1; ++i)
+            for (int j = 0; j < n1; ++j) {
+                double v = 0.0;
+                for (int k = 0; k < n1; ++k) v += Inv[i * n1 + k] * T[k * n1 + j];
+                Pm[s][i * n1 + j] = 0.5 * v;
+                Im[s][i * n1 + j] = I[i * n1 + j];
+            }
+    }
+}
+
 }  // namespace dgx

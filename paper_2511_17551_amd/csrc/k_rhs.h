@@ -229,6 +229,40 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                 jaf_row<DIM>(Jaf, d, nrm);
             }
             const int nb = P.nbr[ebase + f];
+            double F[NV];
+            if (nb <= kMortBase) {
+                // non-conforming face: sub-face fluxes from k_mortar
+                constexpr int NSUB = DIM == 3 ? 4 : 2;
+                const int code = kMortBase - nb;
+                const int m = code >> 3, role = code & 7;
+                const double *mf = P.mflux + (size_t)m * NSUB * NV * NF;
+                if (role < NSUB) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) F[v] = mf[(role * NV + v) * NF + q];
+                } else {
+                    // large side: 2^(dim-1) sum_s (P_a x P_b) F*_s
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) F[v] = 0.0;
+                    const int qa = q % N1, qb = q / N1;
+#pragma unroll
+                    for (int sb = 0; sb < NSUB; ++sb) {
+                        const int a = sb & 1, bsel = sb >> 1;
+#pragma unroll
+                        for (int qq = 0; qq < NF; ++qq) {
+                            const int ja = qq % N1, jb = qq / N1;
+                            double w = P.Pm[a][qa * N1 + ja];
+                            if (DIM == 3) w *= P.Pm[bsel][qb * N1 + jb];
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) F[v] = fma(w, mf[(sb * NV + v) * NF + qq], F[v]);
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) F[v] *= (double)NSUB;
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) buf[v * NSF + it] = F[v];
+                continue;
+            }
             if (nb >= 0) {
                 const int nbn = line_node<N1, DIM>(d, side ? 0 : N, q);
                 const size_t gj = (size_t)nb * NN + nbn;
@@ -265,7 +299,6 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                     for (int c = 0; c < DIM; ++c) ext.v[c] = own.v[c] - 2.0 * vn * nrm[c];
                 }
             }
-            double F[NV];
             if constexpr (SF == 0) {
                 if (side) rusanov<DIM, MIX>(own, ext, nrm, F);
                 else rusanov<DIM, MIX>(ext, own, nrm, F);
@@ -501,6 +534,65 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
             }
         }
     }
+}
+
+// Mortar sub-face fluxes (Sec. New Developments: interpolation to the small
+// sides): one workgroup per mortar, one thread per small-face node.  The
+// large element's face trace is interpolated to the node with I_a x I_b, the
+// Riemann flux uses the small element's trace and scaled normal and is
+// oriented along +xi_d (lower-xi state first).  Perfect gas, affine elements.
+template <int DIM, int N, int SF>
+__global__ void __launch_bounds__(128) k_mortar(RhsParams P, int nmort) {
+    constexpr int N1 = N + 1;
+    constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+    constexpr int NF = NN / N1;
+    constexpr int NV = DIM + 2;
+    constexpr int NSUB = DIM == 3 ? 4 : 2;
+    constexpr int GA = DIM * DIM + 1;
+    const int m = blockIdx.x;
+    const int t = threadIdx.x;
+    if (m >= nmort || t >= NSUB * NF) return;
+    const int s = t / NF, q = t - s * NF;
+    const int *row = P.mort + (size_t)m * (3 + NSUB);
+    const int eL = row[0], fL = row[1], es = row[2 + s], fS = row[2 + NSUB];
+    const int d = fL >> 1, sideL = fL & 1;
+    const size_t stride = (size_t)P.nelem * NN;
+    // interpolate the large trace to small-face node q of sub-face s
+    const int a = s & 1, bsel = s >> 1;
+    const int qa = q % N1, qb = q / N1;
+    double ui[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ui[v] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        const int ja = j % N1, jb = j / N1;
+        double w = P.Im[a][qa * N1 + ja];
+        if (DIM == 3) w *= P.Im[bsel][qb * N1 + jb];
+        const size_t gj = (size_t)eL * NN + line_node<N1, DIM>(d, sideL ? N : 0, j);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ui[v] = fma(w, P.u[v * stride + gj], ui[v]);
+    }
+    const size_t gs = (size_t)es * NN + line_node<N1, DIM>(d, (fS & 1) ? N : 0, q);
+    double us[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) us[v] = P.u[v * stride + gs];
+    St<DIM, false> A, B;
+    make_state<DIM, false>(ui, 0.0, P.gamma, P.M, A);
+    make_state<DIM, false>(us, 0.0, P.gamma, P.M, B);
+    double nrm[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(size_t)es * GA + d * DIM + c];
+    double F[NV];
+    if constexpr (SF == 0) {
+        if (sideL) rusanov<DIM, false>(A, B, nrm, F);
+        else rusanov<DIM, false>(B, A, nrm, F);
+    } else {
+        if (sideL) ranocha_state<DIM, false>(A, B, nrm, P.gamma, F);
+        else ranocha_state<DIM, false>(B, A, nrm, P.gamma, F);
+    }
+    double *out = const_cast<double *>(P.mflux) + (size_t)m * NSUB * NV * NF;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[(s * NV + v) * NF + q] = F[v];
 }
 
 }  // namespace dgx

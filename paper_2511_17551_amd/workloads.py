@@ -463,3 +463,211 @@ def case_c4(energy, cv, nr=64, nth=128, N=3, seed=4, T=300.0, p=1.0e3, mach=8.0,
     cfg = base_cfg(2, N, EQ_REACT_MIX, volume_flux=VF_DUCROS, shock=shock, T_guess=T)
     return Case("cylinder_air5_react", cfg, mesh, u0, species=sp, reactions=rx,
                 extra=dict(T=T, p=p, uinf=uinf, rho=rho))
+
+
+# ----------------------------------------------------------------------------
+# Non-conforming 2:1 octree meshes (mortars) and batched cases
+def _periodic_dist(a, b):
+    d = np.abs(a - b)
+    return np.minimum(d, 1.0 - d)
+
+
+def octree_mesh(N, base=16, radii=(0.51, 0.35), centre=(0.5, 0.5, 0.5)):
+    """Periodic unit cube, base^3 level-0 hexes, refined 2:1 inside spheres.
+
+    A leaf of level L is split into 8 children while L < len(radii) and its
+    centre lies within radii[L] (periodic distance) of ``centre``; then 2:1
+    face balance is enforced.  Returns nodal coordinates, conforming faces
+    (+d of eL to -d of eR), mortars (large face, 4 small elements ordered
+    s = a + 2b over the two tangential directions in increasing order, small
+    face) and the level of every element.
+    """
+    centre = np.asarray(centre, float)
+    leaves = set()
+    for k in range(base):
+        for j in range(base):
+            for i in range(base):
+                leaves.add((0, i, j, k))
+
+    def centre_of(c):
+        L, i, j, k = c
+        h = 1.0 / (base * 2 ** L)
+        return np.array([(i + 0.5) * h, (j + 0.5) * h, (k + 0.5) * h])
+
+    def split(c):
+        L, i, j, k = c
+        leaves.discard(c)
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    leaves.add((L + 1, 2 * i + dx, 2 * j + dy, 2 * k + dz))
+
+    for L, r in enumerate(radii):
+        for c in [c for c in leaves if c[0] == L]:
+            if np.sqrt((_periodic_dist(centre_of(c), centre) ** 2).sum()) < r:
+                split(c)
+
+    def find_leaf(L, i, j, k):
+        """Leaf containing the level-L cell (i, j, k), or None if it is refined."""
+        n = base * 2 ** L
+        i, j, k = i % n, j % n, k % n
+        for LL in range(L, -1, -1):
+            s = L - LL
+            c = (LL, i >> s, j >> s, k >> s)
+            if c in leaves:
+                return c
+        return None
+
+    # 2:1 balance
+    changed = True
+    while changed:
+        changed = False
+        for c in list(leaves):
+            if c not in leaves:
+                continue
+            L, i, j, k = c
+            for d in range(3):
+                for sgn in (-1, 1):
+                    ii = [i, j, k]
+                    ii[d] += sgn
+                    nb = find_leaf(L, *ii)
+                    if nb is None:
+                        # neighbour region is refined: its cells adjacent to c
+                        # must be at most level L + 1
+                        n2 = base * 2 ** (L + 1)
+                        q = [2 * i, 2 * j, 2 * k]
+                        q[d] = (2 * ii[d] + (1 if sgn < 0 else 0)) % n2
+                        for a in (0, 1):
+                            for b in (0, 1):
+                                t = [x for x in range(3) if x != d]
+                                qq = list(q)
+                                qq[t[0]] += a
+                                qq[t[1]] += b
+                                if find_leaf(L + 1, *qq) is None:
+                                    split(c)
+                                    changed = True
+                                    break
+                            if c not in leaves:
+                                break
+                    if c not in leaves:
+                        break
+                if c not in leaves:
+                    break
+    order = sorted(leaves)
+    eid = {c: e for e, c in enumerate(order)}
+    xi = _mesh_nodes(N)
+    n1 = N + 1
+    nn = n1 ** 3
+    nidx = np.stack(np.unravel_index(np.arange(nn), (n1,) * 3)[::-1], 0)
+    E = len(order)
+    x = np.empty((3, E, nn))
+    level = np.empty(E, np.int32)
+    for e, (L, i, j, k) in enumerate(order):
+        h = 1.0 / (base * 2 ** L)
+        level[e] = L
+        for d, cc in enumerate((i, j, k)):
+            x[d, e] = h * (cc + 0.5 * (xi[nidx[d]] + 1.0))
+    faces, mortars = [], []
+    for e, c in enumerate(order):
+        L, i, j, k = c
+        for d in range(3):
+            t = [x_ for x_ in range(3) if x_ != d]
+            for sgn in (1, -1):
+                ii = [i, j, k]
+                ii[d] += sgn
+                nb = find_leaf(L, *ii)
+                if nb is not None and nb[0] == L:
+                    if sgn == 1:
+                        faces.append((e, 2 * d + 1, eid[nb], 2 * d))
+                    continue
+                if nb is not None:
+                    continue  # coarser neighbour: recorded by the large element
+                # finer neighbour: this element is the large side
+                n2 = base * 2 ** (L + 1)
+                q = [2 * i, 2 * j, 2 * k]
+                q[d] = (2 * ii[d] + (1 if sgn < 0 else 0)) % n2
+                small = []
+                for b in (0, 1):
+                    for a in (0, 1):
+                        qq = list(q)
+                        qq[t[0]] += a
+                        qq[t[1]] += b
+                        sc = find_leaf(L + 1, *qq)
+                        assert sc is not None and sc[0] == L + 1, "2:1 balance violated"
+                        small.append(eid[sc])
+                fl = 2 * d + (1 if sgn == 1 else 0)
+                fs = 2 * d + (0 if sgn == 1 else 1)
+                mortars.append(tuple([e, fl] + small + [fs]))
+    return x, np.asarray(faces, np.int32).reshape(-1, 4), np.asarray(mortars, np.int32).reshape(-1, 7), level
+
+
+def density_wave(x):
+    """rho = 1 + 0.5 sin(2 pi (x + y + z)), v = (1, 0.5, 0.25), p = 1."""
+    rho = 1.0 + 0.5 * np.sin(2.0 * math.pi * (x[0] + x[1] + x[2]))
+    return rho, (np.ones_like(rho), 0.5 * np.ones_like(rho), 0.25 * np.ones_like(rho)), np.ones_like(rho)
+
+
+def case_amr(N=3, base=16, radii=(0.51, 0.35), seed=5, centre=None):
+    """3D Euler density wave on the 2-level non-conforming octree mesh."""
+    if centre is None:
+        rng = np.random.default_rng(seed)
+        centre = rng.uniform(0.35, 0.65, 3)
+    x, faces, mortars, level = octree_mesh(N, base, radii, centre)
+    cfg = base_cfg(3, N, EQ_EULER)
+    rho, v, p = density_wave(x)
+    u0 = _pg_conserved(rho, v, p, cfg["gamma"])
+    mesh = Mesh(3, N, x, faces, np.zeros((0, 3), np.int32), mortars, np.zeros(0, np.int32),
+                np.zeros((0, 5)), level=level)
+    return Case("amr_density_wave", cfg, mesh, u0, extra=dict(centre=np.asarray(centre)))
+
+
+def vortex_tube_case(n, N=3, length=10.0):
+    """The isentropic vortex extruded along z (w = 0), periodic n^3 hexes."""
+    x, faces, bfaces = structured_mesh(3, N, (n, n, n), (0.0,) * 3, (length,) * 3, (True,) * 3)
+    rho, (vx, vy), p = isentropic_vortex(x[0], x[1], 1.4, xc=0.5 * length, yc=0.5 * length)
+    u0 = _pg_conserved(rho, (vx, vy, np.zeros_like(vx)), p, 1.4)
+    return x, faces, u0
+
+
+def concat_cases(parts):
+    """Concatenate independent meshes (x, faces, mortars, u0) into one."""
+    xs, fs, ms, us, offs = [], [], [], [], [0]
+    off = 0
+    for x, faces, mortars, u0 in parts:
+        xs.append(x)
+        us.append(u0)
+        f = faces.copy()
+        f[:, 0] += off
+        f[:, 2] += off
+        fs.append(f)
+        if mortars is not None and len(mortars):
+            m = mortars.copy()
+            m[:, 0] += off
+            m[:, 2:6] += off
+            ms.append(m)
+        off += x.shape[1]
+        offs.append(off)
+    mort = np.concatenate(ms, 0) if ms else np.zeros((0, 7), np.int32)
+    return (np.concatenate(xs, 1), np.concatenate(fs, 0).astype(np.int32), mort.astype(np.int32),
+            np.concatenate(us, 1), np.asarray(offs, np.int64))
+
+
+def batch_sizes(seed=55, ncases=16, lo=8, hi=24):
+    return [int(v) for v in np.random.default_rng(seed).integers(lo, hi + 1, ncases)]
+
+
+def case_c5(N=3, base=16, radii=(0.51, 0.35), seed=5, batch_seed=55, ncases=16, sizes=None):
+    """The AMR density wave plus a batch of independent vortex-tube cases in
+    one mesh (element ranges in ``mesh.case_offsets``: case 0 is the AMR
+    domain)."""
+    amr = case_amr(N, base, radii, seed)
+    parts = [(amr.mesh.x, amr.mesh.faces, amr.mesh.mortars, amr.u0)]
+    sizes = batch_sizes(batch_seed, ncases) if sizes is None else sizes
+    for n in sizes:
+        x, faces, u0 = vortex_tube_case(n, N)
+        parts.append((x, faces, None, u0))
+    x, faces, mortars, u0, offs = concat_cases(parts)
+    cfg = base_cfg(3, N, EQ_EULER)
+    mesh = Mesh(3, N, x, faces, np.zeros((0, 3), np.int32), mortars, np.zeros(0, np.int32),
+                np.zeros((0, 5)), case_offsets=offs)
+    return Case("amr_plus_batch", cfg, mesh, u0, extra=dict(sizes=sizes, amr_elements=amr.mesh.nelem))
