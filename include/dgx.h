@@ -115,6 +115,7 @@ typedef struct dgx_config {
     double newton_tol;     /* relative step tolerance of T(e) */
     int newton_maxit;
     double T_guess;        /* freestream guess of T(e) */
+    int positivity;        /* 1 = Zhang-Shu positivity limiter after every SSPRK3 stage */
     const dgx_species *species;      /* mixture equations, else NULL */
     const dgx_reactions *reactions;  /* DGX_EQ_REACT_MIX, else NULL  */
 } dgx_config;
@@ -175,6 +176,15 @@ int dgx_rhs(dgx_ctx *ctx, const double *u, double t, double *du, void *stream);
  * The three stages are captured once into a HIP graph per u pointer and
  * replayed.  Enqueued on stream. */
 int dgx_ssprk3_step(dgx_ctx *ctx, double *u, double t, double dt, int nsteps, void *stream);
+
+/* Zhang-Shu positivity-preserving scaling limiter (Sec. Results: species
+ * densities and pressure kept positive weakly), applied in place to the
+ * device state u: per element, each density is scaled toward its quadrature
+ * mean until its minimum is admissible, then the whole state is scaled until
+ * rho E - |m|^2/(2 rho) - sum rho_s e0_s (positive iff p > 0) is admissible at
+ * every node.  Elements with an inadmissible mean are left unchanged (the
+ * non-physical flag is then raised).  Enqueued on stream. */
+int dgx_limit_positivity(dgx_ctx *ctx, double *u, void *stream);
 
 /* Largest stable dt estimate: cfl * 2/(N+1) / max_n sum_d (|v.Ja^d| + c|Ja^d|)/J.
  * Synchronises; result written to *dt_host. */

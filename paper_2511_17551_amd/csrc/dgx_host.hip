@@ -351,6 +351,35 @@ bool epb_fits(const dgx_ctx *ctx, int epb) {
     return (size_t)epb * ctx->rhs->slot * sizeof(double) <= 64 * 1024;
 }
 
+template <int DIM, int N, bool MIX, bool CURV>
+void pos_launch(const RhsParams &P, double *u, int blocks, int threads, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_positivity<DIM, N, MIX, CURV>), dim3(blocks), dim3(threads), lds, s, P, u);
+}
+
+int enqueue_positivity(dgx_ctx *ctx, double *u, hipStream_t s) {
+    const dgx_config &c = ctx->cfg;
+    RhsParams P = base_params(ctx);
+    const int epb = ctx->epb;
+    const int th = threads_for(ctx->nn, epb);
+    const int blocks = (ctx->nelem + epb - 1) / epb;
+    const int nv = ctx->nvar, nd = is_mix(ctx) ? 5 : 1;
+    const size_t lds = (size_t)epb * ((nv + 1) * ctx->nn + nv + nd + 2) * sizeof(double);
+    const int key = c.dim * 1000 + c.N * 100 + (is_mix(ctx) ? 10 : 0) + (ctx->curved ? 1 : 0);
+    switch (key) {
+        case 2300: pos_launch<2, 3, false, false>(P, u, blocks, th, lds, s); break;
+        case 2301: pos_launch<2, 3, false, true>(P, u, blocks, th, lds, s); break;
+        case 2311: pos_launch<2, 3, true, true>(P, u, blocks, th, lds, s); break;
+        case 2310: pos_launch<2, 3, true, false>(P, u, blocks, th, lds, s); break;
+        case 3300: pos_launch<3, 3, false, false>(P, u, blocks, th, lds, s); break;
+        case 3301: pos_launch<3, 3, false, true>(P, u, blocks, th, lds, s); break;
+        case 3401: pos_launch<3, 4, false, true>(P, u, blocks, th, lds, s); break;
+        case 3411: pos_launch<3, 4, true, true>(P, u, blocks, th, lds, s); break;
+        case 3311: pos_launch<3, 3, true, true>(P, u, blocks, th, lds, s); break;
+        default: return set_err(ctx, DGX_E_INVAL, "no positivity kernel for this configuration");
+    }
+    return hipGetLastError() == hipSuccess ? DGX_OK : set_err(ctx, DGX_E_DEVICE, "positivity launch failed");
+}
+
 int check_ctx(dgx_ctx *ctx) {
     if (!ctx) return DGX_E_INVAL;
     if (!ctx->mesh_ok) return set_err(ctx, DGX_E_STATE, "no mesh set");
@@ -666,9 +695,13 @@ int dgx_ssprk3_step(dgx_ctx *ctx, double *u, double t, double dt, int nsteps, vo
         clear_graph(ctx);
         if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        const bool lim = ctx->cfg.positivity != 0;
         int r1 = enqueue_rhs(ctx, u, ctx->u1.p, 1, nullptr, 0.0, 1.0, dt, ctx->cap_stream);
+        if (!r1 && lim) r1 = enqueue_positivity(ctx, ctx->u1.p, ctx->cap_stream);
         int r2 = r1 ? r1 : enqueue_rhs(ctx, ctx->u1.p, ctx->u2.p, 1, u, 0.75, 0.25, dt, ctx->cap_stream);
+        if (!r2 && lim) r2 = enqueue_positivity(ctx, ctx->u2.p, ctx->cap_stream);
         int r3 = r2 ? r2 : enqueue_rhs(ctx, ctx->u2.p, u, 1, u, 1.0 / 3.0, 2.0 / 3.0, dt, ctx->cap_stream);
+        if (!r3 && lim) r3 = enqueue_positivity(ctx, u, ctx->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &g);
         if (r3) {
@@ -683,6 +716,13 @@ int dgx_ssprk3_step(dgx_ctx *ctx, double *u, double t, double dt, int nsteps, vo
     }
     for (int i = 0; i < nsteps; ++i) HIPCHK(hipGraphLaunch(ctx->gexec, s));
     return DGX_OK;
+}
+
+int dgx_limit_positivity(dgx_ctx *ctx, double *u, void *stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!u) return set_err(ctx, DGX_E_INVAL, "null state");
+    return enqueue_positivity(ctx, u, (hipStream_t)stream);
 }
 
 int dgx_max_dt(dgx_ctx *ctx, const double *u, double cfl, double *dt_host, void *stream) {

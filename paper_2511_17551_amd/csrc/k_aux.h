@@ -283,6 +283,140 @@ __global__ void __launch_bounds__(512) k_indicator(RhsParams P, int ind_var, dou
     }
 }
 
+// Zhang-Shu positivity-preserving scaling limiter, in place on u (see
+// dgx_limit_positivity in the C ABI).  Means and minima are reduced over the
+// element's nodes by one thread in a fixed order (deterministic).
+template <int DIM, bool MIX>
+__device__ __forceinline__ double zs_psi(const double *u, const MixC &M) {
+    constexpr int off = MIX ? kNS : 1;
+    double rho = 0.0, lin = u[off + DIM];
+    if constexpr (MIX) {
+#pragma unroll
+        for (int s = 0; s < kNS; ++s) {
+            rho += u[s];
+            lin -= M.e0[s] * u[s];
+        }
+    } else {
+        rho = u[0];
+    }
+    double m2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) m2 = fma(u[off + c], u[off + c], m2);
+    return lin - 0.5 * m2 / rho;
+}
+
+template <int DIM, int N, bool MIX, bool CURV>
+__global__ void __launch_bounds__(512) k_positivity(RhsParams P, double *__restrict__ u) {
+    constexpr int N1 = N + 1;
+    constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+    constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
+    constexpr int ND = MIX ? kNS : 1;  // density variables
+    constexpr int GA = DIM * DIM + 1;
+    constexpr int SL = (NV + 1) * NN + NV + ND + 2;
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
+    int el = tid / NN;
+    const int node = tid - el * NN;
+    const int e = blockIdx.x * P.epb + el;
+    const bool valid = (el < P.epb) && (e < P.nelem);
+    if (el >= P.epb) el = 0;
+    double *sw = smem + el * SL;         // [NV+1][NN] weighted values, then scratch
+    double *sbar = sw + (NV + 1) * NN;   // [NV] means
+    double *sth = sbar + NV;             // [ND] density thetas, [ND] pressure theta, flag
+    const size_t stride = (size_t)P.nelem * NN;
+    const size_t gi = (size_t)(valid ? e : 0) * NN + node;
+    double uo[NV];
+    double wJ = 0.0;
+    if (valid) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uo[v] = u[v * stride + gi];
+        double w = 1.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) w *= P.B.w[node_pos<N1>(node, d)];
+        const double J = CURV ? P.Jn[gi] : P.geo[(size_t)e * GA + DIM * DIM];
+        wJ = w * J;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sw[v * NN + node] = wJ * uo[v];
+        sw[NV * NN + node] = wJ;
+    }
+    __syncthreads();
+    if (valid && node == 0) {
+        double vol = 0.0;
+        for (int n = 0; n < NN; ++n) vol += sw[NV * NN + n];
+        for (int v = 0; v < NV; ++v) {
+            double s = 0.0;
+            for (int n = 0; n < NN; ++n) s += sw[v * NN + n];
+            sbar[v] = s / vol;
+        }
+    }
+    __syncthreads();
+    double ubar[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ubar[v] = sbar[v];
+    // 1. densities
+    if (valid) {
+#pragma unroll
+        for (int s = 0; s < ND; ++s) sw[s * NN + node] = uo[s];
+    }
+    __syncthreads();
+    if (valid && node == 0) {
+        for (int s = 0; s < ND; ++s) {
+            double mn = sw[s * NN];
+            for (int n = 1; n < NN; ++n) mn = fmin(mn, sw[s * NN + n]);
+            const double eps = MIX ? 1e-14 * fmax(ubar[s], 0.0) : fmin(1e-13, ubar[s]);
+            sth[s] = (mn < eps && ubar[s] > eps) ? (ubar[s] - eps) / (ubar[s] - mn) : 1.0;
+        }
+    }
+    __syncthreads();
+    bool changed = false;
+#pragma unroll
+    for (int s = 0; s < ND; ++s) {
+        const double th = sth[s];
+        if (th < 1.0) {
+            uo[s] = ubar[s] + th * (uo[s] - ubar[s]);
+            changed = true;
+        }
+    }
+    // 2. pressure
+    double rho_bar = 0.0;
+#pragma unroll
+    for (int s = 0; s < ND; ++s) rho_bar += ubar[s];
+    const double pb = zs_psi<DIM, MIX>(ubar, P.M);
+    const double eps_p = fmin(1e-13 * rho_bar * (MIX ? 1e5 : 1.0), pb);
+    double tn = 1.0;
+    if (valid && pb > 0.0 && zs_psi<DIM, MIX>(uo, P.M) < eps_p) {
+        double lo = 0.0, hi = 1.0, ut[NV];
+        for (int it = 0; it < 64; ++it) {
+            const double mid = 0.5 * (lo + hi);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ut[v] = ubar[v] + mid * (uo[v] - ubar[v]);
+            if (zs_psi<DIM, MIX>(ut, P.M) >= eps_p) lo = mid;
+            else hi = mid;
+        }
+        tn = lo;
+    }
+    __syncthreads();
+    if (valid) sw[node] = tn;
+    __syncthreads();
+    if (valid && node == 0) {
+        double mn = 1.0;
+        for (int n = 0; n < NN; ++n) mn = fmin(mn, sw[n]);
+        sth[ND] = mn;
+        if (pb <= 0.0) atomicOr(P.flags, FLAG_NONPHYS);
+    }
+    __syncthreads();
+    const double thp = sth[ND];
+    if (thp < 1.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uo[v] = ubar[v] + thp * (uo[v] - ubar[v]);
+        changed = true;
+    }
+    if (valid && changed) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v * stride + gi] = uo[v];
+    }
+}
+
 // alpha_k <- max(alpha_k, alpha_nbr / 2) over conforming neighbours.
 template <int DIM>
 __global__ void k_alpha_smooth(const int *__restrict__ nbr, int nelem, const double *__restrict__ ain,

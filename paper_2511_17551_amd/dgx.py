@@ -50,6 +50,7 @@ class dgx_config(C.Structure):
                 ("Pr", C.c_double), ("shock", C.c_int), ("alpha_max", C.c_double), ("alpha_min", C.c_double),
                 ("ind_var", C.c_int), ("alpha_smooth", C.c_int), ("force_alpha", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int), ("T_guess", C.c_double),
+                ("positivity", C.c_int),
                 ("species", C.POINTER(dgx_species)), ("reactions", C.POINTER(dgx_reactions))]
 
 
@@ -75,6 +76,7 @@ def _load():
         "dgx_set_mesh": ([vp, C.POINTER(dgx_mesh)], C.c_int),
         "dgx_rhs": ([vp, vp, C.c_double, vp, vp], C.c_int),
         "dgx_ssprk3_step": ([vp, vp, C.c_double, C.c_double, C.c_int, vp], C.c_int),
+        "dgx_limit_positivity": ([vp, vp, vp], C.c_int),
         "dgx_max_dt": ([vp, vp, C.c_double, C.POINTER(C.c_double), vp], C.c_int),
         "dgx_thermo": ([vp, vp, C.c_int64, vp, vp, C.c_int, C.POINTER(dgx_newton_stats), vp], C.c_int),
         "dgx_last_alpha": ([vp], vp),
@@ -102,7 +104,7 @@ def _load():
 
 
 lib = _load()
-EXPORTED = ("dgx_create", "dgx_set_mesh", "dgx_rhs", "dgx_ssprk3_step", "dgx_max_dt", "dgx_thermo",
+EXPORTED = ("dgx_create", "dgx_set_mesh", "dgx_rhs", "dgx_ssprk3_step", "dgx_limit_positivity", "dgx_max_dt", "dgx_thermo",
             "dgx_last_alpha", "dgx_surrogate_set", "dgx_surrogate_get", "dgx_surrogate_train",
             "dgx_surrogate_predict", "dgx_surrogate_init", "dgx_surrogate_grad", "dgx_check", "dgx_species_energy", "dgx_kernel_times", "dgx_autotune",
             "dgx_set_launch", "dgx_last_error", "dgx_destroy")
@@ -163,6 +165,7 @@ def dgx_create(cfg: dict, species=None, reactions=None):
     c.alpha_max, c.alpha_min = cfg["alpha_max"], cfg["alpha_min"]
     c.ind_var, c.alpha_smooth, c.force_alpha = cfg["ind_var"], int(bool(cfg["alpha_smooth"])), cfg["force_alpha"]
     c.newton_tol, c.newton_maxit, c.T_guess = cfg["newton_tol"], cfg["newton_maxit"], cfg["T_guess"]
+    c.positivity = int(bool(cfg.get("positivity", False)))
     if species is not None:
         keep.sp = make_species(species)
         c.species = C.pointer(keep.sp)
@@ -208,6 +211,10 @@ def dgx_rhs(ctx, u, t, du, stream=None):
 
 def dgx_ssprk3_step(ctx, u, t, dt, nsteps, stream=None):
     _raise(ctx, lib.dgx_ssprk3_step(ctx, _dev(u), float(t), float(dt), int(nsteps), _stream(stream)))
+
+
+def dgx_limit_positivity(ctx, u, stream=None):
+    _raise(ctx, lib.dgx_limit_positivity(ctx, _dev(u), _stream(stream)))
 
 
 def dgx_max_dt(ctx, u, cfl, stream=None):

@@ -254,7 +254,7 @@ def base_cfg(dim, N, eq, **kw):
                volume_flux=VF_RANOCHA, surface_flux=SF_RUSANOV,
                shock=False, alpha_max=0.5, alpha_min=1e-3, ind_var=IND_RHO_P,
                alpha_smooth=False, force_alpha=-1.0,
-               newton_tol=1e-10, newton_maxit=50, T_guess=300.0)
+               newton_tol=1e-10, newton_maxit=50, T_guess=300.0, positivity=False)
     cfg.update(kw)
     return cfg
 
@@ -460,7 +460,7 @@ def case_c4(energy, cv, nr=64, nth=128, N=3, seed=4, T=300.0, p=1.0e3, mach=8.0,
     mesh = Mesh(2, N, x, faces, bfaces, np.zeros((0, 5), np.int32),
                 np.array([BC_SLIPWALL, BC_DIRICHLET], np.int32),
                 np.stack([state, state]))
-    cfg = base_cfg(2, N, EQ_REACT_MIX, volume_flux=VF_DUCROS, shock=shock, T_guess=T)
+    cfg = base_cfg(2, N, EQ_REACT_MIX, volume_flux=VF_DUCROS, shock=shock, T_guess=T, positivity=True)
     return Case("cylinder_air5_react", cfg, mesh, u0, species=sp, reactions=rx,
                 extra=dict(T=T, p=p, uinf=uinf, rho=rho))
 

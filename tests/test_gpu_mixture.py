@@ -135,3 +135,43 @@ def test_reacting_cylinder_impulsive_start(dgx, thermo_fns):
     e = parity_err(got, ref, flux_scale(op, c.u0))
     print("impulsive start parity %.3e" % e)
     assert e < RHS_TOL
+
+
+def test_positivity_limiter_matches_oracle(dgx, thermo_fns):
+    from oracle.positivity import limit
+    c = W.case_c4(*thermo_fns, nr=8, nth=16, hot=True)
+    op = Operator(c.cfg, c.mesh, species=c.species, reactions=c.reactions)
+    rng = np.random.default_rng(3)
+    u = c.u0.copy()
+    for e in rng.choice(c.mesh.nelem, 12, replace=False):
+        u[3, e, rng.integers(0, 16, 3)] *= -0.2
+        u[7, e, rng.integers(0, 16, 2)] *= 0.3
+    wq = np.outer(op.b.w, op.b.w).reshape(-1)
+    ref, _ = limit(u, op.J, wq, 2, c.species.e0)
+    s = dgx.Solver(c)
+    ud = to_dev(u)
+    dgx.dgx_limit_positivity(s.ctx, ud)
+    got = to_host(ud)
+    s.close()
+    print("positivity limiter rel err %.3e" % rel_err(got, ref))
+    assert rel_err(got, ref) < 1e-12
+
+
+def test_reacting_cylinder_steps_with_limiter(dgx, thermo_fns):
+    """A few SSPRK3 steps of the hot reacting state, limiter on every stage."""
+    from oracle import ssprk
+    from oracle.positivity import limit
+    c = W.case_c4(*thermo_fns, nr=8, nth=16, hot=True)
+    op = Operator(c.cfg, c.mesh, species=c.species, reactions=c.reactions)
+    wq = np.outer(op.b.w, op.b.w).reshape(-1)
+    lim = lambda v: limit(v, op.J, wq, 2, c.species.e0)[0]
+    dt = 2e-9
+    ref, _ = ssprk.run(lambda v, t: op.rhs(v, t), c.u0, 0.0, dt, 5, limiter=lim)
+    s = dgx.Solver(c)
+    u = to_dev(c.u0)
+    s.ssprk3(u, dt, 5)
+    s.check()
+    got = to_host(u)
+    s.close()
+    print("reacting 5 steps rel err %.3e" % rel_err(got, ref))
+    assert rel_err(got, ref) < 1e-9
