@@ -51,7 +51,8 @@ def limit(u, J, wq, dim, e0=None):
         mn = u[s].min(1)
         bad = (mn < eps) & (ubar[s] > eps)
         theta = np.where(bad, (ubar[s] - eps) / np.where(bad, ubar[s] - mn, 1.0), 1.0)
-        u[s] = ubar[s][:, None] + theta[:, None] * (u[s] - ubar[s][:, None])
+        k = np.flatnonzero(bad)
+        u[s, k] = ubar[s, k][:, None] + theta[k][:, None] * (u[s, k] - ubar[s, k][:, None])
     rho_bar = ubar[:5].sum(0) if mix else ubar[0]
     pb = psi(ubar[:, :, None], dim, e0)[:, 0]
     eps_p = np.minimum(1e-13 * rho_bar * (1e5 if mix else 1.0), pb)
