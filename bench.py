@@ -13,6 +13,8 @@ is timed on the same 32^3 state for the cpu_baseline entry.
 """
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -66,12 +68,166 @@ def cpu_baseline(case, budget_s=20.0):
                 % (n, el))
 
 
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=6, reps=5):
+    """Per-node T(e): surrogate-guided vs plain Newton on solver-generated states.
+
+    States: a frozen-chemistry run of the Mach-8 cylinder O-grid (64 x 128,
+    N = 3, positivity limiter, CFL 0.2), snapshots every 20 SSPRK3 steps ->
+    16 x 131072 = 2,097,152 states.  Labels: the plain solve's converged T.
+    The surrogate is trained on the same set (Adam, batch 4096), then both
+    solves are timed (HIP events, same stream, same 1e-10 tolerance).
+    """
+    probe = W.case_c4(lambda rs, T: 0 * T, lambda rs, T: 1 + 0 * T, nr=4, nth=8)
+    pctx = dgx.dgx_create(probe.cfg, probe.species, probe.reactions)
+    energy, cv = dgx.mixture_energy_fns(pctx)
+    c = W.case_c4(energy, cv)
+    dgx.dgx_destroy(pctx)
+    c.cfg["eq"] = W.EQ_EULER_MIX
+    c.reactions = None
+    s = dgx.Solver(c)
+    u = torch.from_numpy(c.u0).to("cuda")
+    dt = dgx.dgx_max_dt(s.ctx, u, 0.2)
+    snaps = []
+    for _ in range(snapshots):
+        s.ssprk3(u, dt, steps_per_snap)
+        snaps.append(u.reshape(u.shape[0], -1).clone())
+    s.check()
+    states = torch.cat(snaps, 1).contiguous()
+    del snaps
+    n = states.shape[1]
+    T = torch.empty(n, dtype=torch.float64, device="cuda")
+    st_plain = dgx.dgx_thermo(s.ctx, states, T, nstates=n)
+    t0 = time.perf_counter()
+    dgx.dgx_surrogate_init(s.ctx, states, T, seed=41)
+    losses = dgx.dgx_surrogate_train(s.ctx, states, T, epochs=epochs, batch=4096, lr=2e-3, seed=42)
+    train_s = time.perf_counter() - t0
+    Ts = torch.empty_like(T)
+    st_sur = dgx.dgx_thermo(s.ctx, states, Ts, nstates=n, guess=dgx.GUESS_SURROGATE)
+    maxrel = float(((Ts - T).abs() / T).max())
+    Tg = torch.empty_like(T)
+    e0, e1 = _events(torch)
+    res = {}
+    for name, guess in (("plain", dgx.GUESS_FREESTREAM), ("surrogate", dgx.GUESS_SURROGATE)):
+        dgx.dgx_thermo(s.ctx, states, Ts, nstates=n, guess=guess, stats=False)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            dgx.dgx_thermo(s.ctx, states, Ts, nstates=n, guess=guess, stats=False)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / reps
+    dgx.dgx_surrogate_predict(s.ctx, states, Tg)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dgx.dgx_surrogate_predict(s.ctx, states, Tg)
+    e1.record()
+    torch.cuda.synchronize()
+    infer_ms = e0.elapsed_time(e1) / reps
+    guess_err = float(((Tg - T).abs() / T).median())
+    # the disturbed states only (|T - T_inf| > 1% T_inf): shock layer and wake
+    sel = ((T - c.cfg["T_guess"]).abs() > 0.01 * c.cfg["T_guess"]).nonzero().flatten()
+    sub = states[:, sel].contiguous()
+    nsub = sub.shape[1]
+    Tsub = torch.empty(nsub, dtype=torch.float64, device="cuda")
+    sp_sub = dgx.dgx_thermo(s.ctx, sub, Tsub, nstates=nsub)
+    ss_sub = dgx.dgx_thermo(s.ctx, sub, Tsub, nstates=nsub, guess=dgx.GUESS_SURROGATE)
+    sub_ms = {}
+    for name, guess in (("plain", dgx.GUESS_FREESTREAM), ("surrogate", dgx.GUESS_SURROGATE)):
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            dgx.dgx_thermo(s.ctx, sub, Tsub, nstates=nsub, guess=guess, stats=False)
+        e1.record()
+        torch.cuda.synchronize()
+        sub_ms[name] = e0.elapsed_time(e1) / reps
+    s.check()
+    s.close()
+    return dict(states=n, T_min=float(T.min()), T_max=float(T.max()),
+                plain_ms=round(res["plain"], 4), surrogate_ms=round(res["surrogate"], 4),
+                speedup=round(res["plain"] / res["surrogate"], 3), surrogate_inference_ms=round(infer_ms, 4),
+                iters_mean_plain=round(st_plain["iters_total"] / n, 3),
+                iters_mean_surrogate=round(st_sur["iters_total"] / n, 3),
+                wave_max_mean_plain=round(st_plain["iters_wave_max_mean"], 3),
+                wave_max_mean_surrogate=round(st_sur["iters_wave_max_mean"], 3),
+                max_rel_T_diff=maxrel, median_rel_guess_err=guess_err,
+                disturbed=dict(states=int(nsub), plain_ms=round(sub_ms["plain"], 4),
+                               surrogate_ms=round(sub_ms["surrogate"], 4),
+                               speedup=round(sub_ms["plain"] / sub_ms["surrogate"], 3),
+                               iters_mean_plain=round(sp_sub["iters_total"] / nsub, 3),
+                               iters_mean_surrogate=round(ss_sub["iters_total"] / nsub, 3),
+                               wave_max_mean_plain=round(sp_sub["iters_wave_max_mean"], 3),
+                               wave_max_mean_surrogate=round(ss_sub["iters_wave_max_mean"], 3)),
+                train_epochs=epochs, train_s=round(train_s, 2), loss_first=float(losses[0]),
+                loss_last=float(losses[-1]), tol=1e-10)
+
+
+def batch_leg(torch, W, dgx, reps=10):
+    """The AMR density wave + 16 vortex-tube cases: one launch per stage for
+    everything vs one context / launch sequence per case."""
+    c = W.case_c5()
+    s = dgx.Solver(c)
+    u = torch.from_numpy(c.u0).to("cuda")
+    dt = dgx.dgx_max_dt(s.ctx, u, 0.3)
+    epb, _ = dgx.dgx_autotune(s.ctx, u, reps=5)
+    s.ssprk3(u, dt, 2)
+    e0, e1 = _events(torch)
+    torch.cuda.synchronize()
+    e0.record()
+    s.ssprk3(u, dt, reps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1) / reps
+    s.check()
+    s.close()
+    dof = c.u0.size
+    offs = c.mesh.case_offsets
+    amr = W.case_amr()
+    cases = [amr]
+    for n in c.extra["sizes"]:
+        x, faces, u0 = W.vortex_tube_case(n)
+        m = W.Mesh(3, 3, x, faces, np.zeros((0, 3), np.int32), np.zeros((0, 7), np.int32),
+                   np.zeros(0, np.int32), np.zeros((0, 5)))
+        cases.append(W.Case("tube", W.base_cfg(3, 3, W.EQ_EULER), m, u0))
+    solvers, states = [], []
+    for cc in cases:
+        sc = dgx.Solver(cc)
+        uc = torch.from_numpy(cc.u0).to("cuda")
+        dgx.dgx_set_launch(sc.ctx, epb) if epb * 64 <= 512 else None
+        sc.ssprk3(uc, dt, 2)
+        solvers.append(sc)
+        states.append(uc)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        for sc, uc in zip(solvers, states):
+            sc.ssprk3(uc, dt, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_sep = e0.elapsed_time(e1) / reps
+    for sc in solvers:
+        sc.check()
+        sc.close()
+    return dict(elements=int(c.mesh.nelem), amr_elements=int(c.extra["amr_elements"]),
+                mortars=int(len(c.mesh.mortars)), cases=len(offs) - 1, dof=int(dof),
+                batched_ms_per_step=round(ms_batched, 4), separate_ms_per_step=round(ms_sep, 4),
+                batched_GDOF_RHS_s=round(3 * dof / (ms_batched * 1e-3) / 1e9, 3),
+                separate_GDOF_RHS_s=round(3 * dof / (ms_sep * 1e-3) / 1e9, 3),
+                elements_per_workgroup=epb)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-thermo", action="store_true", help="skip the surrogate vs plain T(e) leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched AMR + cases leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 84 MB device copy (counter calibration)")
     args = ap.parse_args()
@@ -136,6 +292,10 @@ def main():
         "roofline": roof,
     }
     solver.close()
+    if not args.no_thermo:
+        out["thermo"] = thermo_leg(torch, W, dgx)
+    if not args.no_batch:
+        out["batch"] = batch_leg(torch, W, dgx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out))

@@ -195,8 +195,10 @@ int dgx_max_dt(dgx_ctx *ctx, const double *u, double cfl, double *dt_host, void 
  * from T_guess (DGX_GUESS_FREESTREAM) or the trained surrogate
  * (DGX_GUESS_SURROGATE).  u: device [nvar][nelem][nn] of a mixture context,
  * or nstates = count of a packed [nvar][count] state set when the mesh is not
- * used (pass nstates > 0).  T, p: device [count].  stats (host, may be NULL)
- * receive iteration counts.  Synchronises. */
+ * used (pass nstates > 0).  T, p (p may be NULL): device [count].  With
+ * stats (host) the iteration counts are gathered and the call synchronises;
+ * with stats == NULL it only enqueues (for timing) and non-convergence is
+ * reported by dgx_check. */
 int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double *p,
                int guess_mode, dgx_newton_stats *stats, void *stream);
 

@@ -36,9 +36,9 @@ using GradLaunch = void (*)(const RhsParams &, int, int, size_t, hipStream_t);
 using IndLaunch = void (*)(const RhsParams &, int, double, double, double *, double *, int, int, size_t,
                            hipStream_t);
 
-template <int DIM, int N, int EQ, int VF, int SF, bool CURV>
+template <int DIM, int N, int EQ, int VF, int SF, bool CURV, bool MORT>
 void rhs_launch(const RhsParams &P, int mode, int blocks, int threads, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_rhs<DIM, N, EQ, VF, SF, CURV>), dim3(blocks), dim3(threads), lds, s, P, mode);
+    hipLaunchKernelGGL((k_rhs<DIM, N, EQ, VF, SF, CURV, MORT>), dim3(blocks), dim3(threads), lds, s, P, mode);
 }
 template <int DIM, int N>
 void grad_launch(const RhsParams &P, int blocks, int threads, size_t lds, hipStream_t s) {
@@ -55,10 +55,13 @@ struct RhsEntry {
     int dim, N, eq, vf, sf, curv;
     RhsLaunch fn;
     int slot;  // doubles of LDS per element
+    int mort;  // built with non-conforming (mortar) faces
 };
 
 #define RHS_ENTRY(D, N, EQ, VF, SF, CV) \
-    {D, N, EQ, VF, SF, CV, &rhs_launch<D, N, EQ, VF, SF, (bool)CV>, RhsShape<D, N, EQ, VF, (bool)CV>::SLOT}
+    {D, N, EQ, VF, SF, CV, &rhs_launch<D, N, EQ, VF, SF, (bool)CV, false>, RhsShape<D, N, EQ, VF, (bool)CV>::SLOT, 0}
+#define RHS_ENTRY_M(D, N, EQ, VF, SF) \
+    {D, N, EQ, VF, SF, 0, &rhs_launch<D, N, EQ, VF, SF, false, true>, RhsShape<D, N, EQ, VF, false>::SLOT, 1}
 
 const RhsEntry kRhs[] = {
     // 2D perfect gas (isentropic vortex, O-grid checks)
@@ -71,6 +74,8 @@ const RhsEntry kRhs[] = {
     // mixtures
     RHS_ENTRY(3, 4, 2, 1, 0, 1), RHS_ENTRY(3, 3, 2, 1, 0, 1), RHS_ENTRY(2, 3, 2, 1, 0, 1),
     RHS_ENTRY(2, 3, 3, 1, 0, 1), RHS_ENTRY(2, 3, 3, 1, 0, 0),
+    // non-conforming (mortar) meshes
+    RHS_ENTRY_M(3, 3, 0, 0, 0), RHS_ENTRY_M(3, 3, 0, 0, 1), RHS_ENTRY_M(3, 4, 0, 0, 0), RHS_ENTRY_M(2, 3, 0, 0, 0),
 };
 
 struct IndEntry {
@@ -115,7 +120,8 @@ struct dgx_ctx {
     bool mesh_ok = false;
     int nbc = 0;
     DevBuf<double> geo, Jn, nsub, bc_state, bc_T, T, alpha, alpha_tmp, alpha_raw, grad, vpart, u1, u2, dtbuf;
-    DevBuf<int> nbr, bc_kind, mort;
+    DevBuf<int> nbr, bc_kind, mort, iters;
+    DevBuf<double> tg;
     DevBuf<double> mflux;
     int nmortar = 0;
     double Im[2][25] = {}, Pm[2][25] = {};
@@ -342,7 +348,7 @@ std::string tune_key(const dgx_ctx *ctx) {
     const dgx_config &c = ctx->cfg;
     return std::to_string(c.dim) + "," + std::to_string(c.N) + "," + std::to_string(c.equation) + "," +
            std::to_string(c.volume_flux) + "," + std::to_string(c.surface_flux) + "," + std::to_string(ctx->curved) +
-           "," + std::to_string(ctx->nelem);
+           "," + std::to_string(ctx->nelem) + "," + std::to_string(ctx->nmortar > 0);
 }
 
 bool epb_fits(const dgx_ctx *ctx, int epb) {
@@ -559,14 +565,15 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
     if (m->nmortar && !affine) return set_err(ctx, DGX_E_INVAL, "mortars need affine elements");
     // pick the kernel variant for this geometry
     const RhsEntry *sel = nullptr;
+    const int want_m = m->nmortar ? 1 : 0;
     for (const auto &e : kRhs)
         if (e.dim == dim && e.N == N && e.eq == ctx->cfg.equation && e.vf == ctx->cfg.volume_flux &&
-            e.sf == ctx->cfg.surface_flux && e.curv == (affine ? 0 : 1))
+            e.sf == ctx->cfg.surface_flux && e.curv == (affine ? 0 : 1) && e.mort == want_m)
             sel = &e;
-    if (!sel && affine)  // fall back to the curved variant (valid for any mesh)
+    if (!sel && affine && !want_m)  // fall back to the curved variant (valid for any mesh)
         for (const auto &e : kRhs)
             if (e.dim == dim && e.N == N && e.eq == ctx->cfg.equation && e.vf == ctx->cfg.volume_flux &&
-                e.sf == ctx->cfg.surface_flux && e.curv == 1)
+                e.sf == ctx->cfg.surface_flux && e.curv == 1 && e.mort == 0)
                 sel = &e, affine = false;
     if (!sel) return set_err(ctx, DGX_E_INVAL, "no kernel variant for this configuration and mesh");
     ctx->rhs = sel;
@@ -771,36 +778,31 @@ int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double
         if (!ctx->mesh_ok) return set_err(ctx, DGX_E_STATE, "no mesh and no state count");
         count = (int64_t)ctx->nelem * ctx->nn;
     }
+    if (guess_mode == DGX_GUESS_SURROGATE && !ctx->sur.ready) return set_err(ctx, DGX_E_STATE, "surrogate has no weights");
     hipStream_t s = (hipStream_t)stream;
-    int *iters = nullptr;
-    double *tg = nullptr;
-    HIPCHK(hipMalloc((void **)&iters, count * sizeof(int)));
+    int rc;
+    if (stats && (rc = dalloc(ctx, ctx->iters, (size_t)count))) return rc;
+    const double *tg = nullptr;
     if (guess_mode == DGX_GUESS_SURROGATE) {
-        if (!ctx->sur.ready) {
-            (void)hipFree(iters);
-            return set_err(ctx, DGX_E_STATE, "surrogate has no weights");
-        }
-        HIPCHK(hipMalloc((void **)&tg, count * sizeof(double)));
-        int rc = surrogate_predict(ctx->sur, ctx->cfg.dim, u, count, tg, s);
-        if (rc) {
-            (void)hipFree(iters);
-            (void)hipFree(tg);
-            return set_err(ctx, rc, "surrogate launch failed");
-        }
+        if ((rc = dalloc(ctx, ctx->tg, (size_t)count))) return rc;
+        rc = surrogate_predict(ctx->sur, ctx->cfg.dim, u, count, ctx->tg.p, s);
+        if (rc) return set_err(ctx, rc, "surrogate launch failed");
+        tg = ctx->tg.p;
     }
+    int *iters = stats ? ctx->iters.p : nullptr;
     const int tb = 256;
     const int blocks = (int)((count + tb - 1) / tb);
     if (ctx->cfg.dim == 2)
-        hipLaunchKernelGGL(k_thermo<2>, dim3(blocks), dim3(tb), 0, s, u, count, (const double *)tg, ctx->cfg.T_guess,
+        hipLaunchKernelGGL(k_thermo<2>, dim3(blocks), dim3(tb), 0, s, u, count, tg, ctx->cfg.T_guess,
                            ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, iters, ctx->flags.p);
     else
-        hipLaunchKernelGGL(k_thermo<3>, dim3(blocks), dim3(tb), 0, s, u, count, (const double *)tg, ctx->cfg.T_guess,
+        hipLaunchKernelGGL(k_thermo<3>, dim3(blocks), dim3(tb), 0, s, u, count, tg, ctx->cfg.T_guess,
                            ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, iters, ctx->flags.p);
+    if (hipGetLastError() != hipSuccess) return set_err(ctx, DGX_E_DEVICE, "thermo launch failed");
+    if (!stats) return DGX_OK;
     std::vector<int> h(count);
-    HIPCHK(hipMemcpyAsync(h.data(), iters, count * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h.data(), ctx->iters.p, count * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    (void)hipFree(iters);
-    if (tg) (void)hipFree(tg);
     int64_t tot = 0, bad = 0, first = -1;
     int mx = 0;
     double wsum = 0.0;
@@ -821,14 +823,12 @@ int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double
         wsum += wm;
         ++nw;
     }
-    if (stats) {
-        stats->nodes = count;
-        stats->iters_total = tot;
-        stats->iters_max = mx;
-        stats->iters_wave_max_mean = nw ? wsum / nw : 0.0;
-        stats->nonconverged = bad;
-        stats->first_bad = first;
-    }
+    stats->nodes = count;
+    stats->iters_total = tot;
+    stats->iters_max = mx;
+    stats->iters_wave_max_mean = nw ? wsum / nw : 0.0;
+    stats->nonconverged = bad;
+    stats->first_bad = first;
     if (bad) return set_err(ctx, DGX_E_NOCONV, std::to_string(bad) + " nodes did not converge");
     return DGX_OK;
 }
@@ -1021,6 +1021,8 @@ void dgx_destroy(dgx_ctx *ctx) {
     ctx->bc_kind.release();
     ctx->mort.release();
     ctx->mflux.release();
+    ctx->iters.release();
+    ctx->tg.release();
     ctx->kin_d.release();
     ctx->flags.release();
     ctx->rate.release();

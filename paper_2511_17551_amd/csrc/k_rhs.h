@@ -125,7 +125,7 @@ __device__ __forceinline__ void lds_state(const double *su, const double *sq, in
     }
 }
 
-template <int DIM, int N, int EQ, int VF, int SF, bool CURV>
+template <int DIM, int N, int EQ, int VF, int SF, bool CURV, bool MORT = false>
 __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     using S = RhsShape<DIM, N, EQ, VF, CURV>;
     constexpr int N1 = S::N1, NN = S::NN, NF = S::NF, NV = S::NV, NQ = S::NQ, NW = S::NW;
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
             }
             const int nb = P.nbr[ebase + f];
             double F[NV];
-            if (nb <= kMortBase) {
+            if (MORT && nb <= kMortBase) {
                 // non-conforming face: sub-face fluxes from k_mortar
                 constexpr int NSUB = DIM == 3 ? 4 : 2;
                 const int code = kMortBase - nb;
@@ -244,10 +244,10 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) F[v] = 0.0;
                     const int qa = q % N1, qb = q / N1;
-#pragma unroll
+#pragma unroll 1
                     for (int sb = 0; sb < NSUB; ++sb) {
                         const int a = sb & 1, bsel = sb >> 1;
-#pragma unroll
+#pragma unroll 1
                         for (int qq = 0; qq < NF; ++qq) {
                             const int ja = qq % N1, jb = qq / N1;
                             double w = P.Pm[a][qa * N1 + ja];

@@ -51,6 +51,13 @@ __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
     return v;
 }
 
+// tanh(x) = 1 - 2 / (exp(2x) + 1) with the hardware exp/reciprocal (FP32,
+// a few ulp; the activations are rounded to BF16 right after).
+__device__ __forceinline__ float tanh_fast(float x) {
+    const float t = __expf(2.0f * x);
+    return 1.0f - 2.0f * __frcp_rn(t + 1.0f);
+}
+
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -122,7 +129,7 @@ __device__ __forceinline__ void forward(const float *P, const float *x, int r, i
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mfma(wfrag(P + oW1, kSurIn, kSurIn, mt, 0, r, g), F.xb, acc);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) F.h1[mt][j] = tanhf(acc[j] + P[ob1 + 16 * mt + 4 * g + j]);
+        for (int j = 0; j < 4; ++j) F.h1[mt][j] = tanh_fast(acc[j] + P[ob1 + 16 * mt + 4 * g + j]);
         F.hb1[mt] = pack4(F.h1[mt][0], F.h1[mt][1], F.h1[mt][2], F.h1[mt][3]);
     }
 #pragma unroll
@@ -131,7 +138,7 @@ __device__ __forceinline__ void forward(const float *P, const float *x, int r, i
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc) acc = mfma(wfrag(P + oW2, H, H, mt, kc, r, g), F.hb1[kc], acc);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) F.h2[mt][j] = tanhf(acc[j] + P[ob2 + 16 * mt + 4 * g + j]);
+        for (int j = 0; j < 4; ++j) F.h2[mt][j] = tanh_fast(acc[j] + P[ob2 + 16 * mt + 4 * g + j]);
         F.hb2[mt] = pack4(F.h2[mt][0], F.h2[mt][1], F.h2[mt][2], F.h2[mt][3]);
     }
     float yp = 0.0f;
@@ -142,7 +149,7 @@ __device__ __forceinline__ void forward(const float *P, const float *x, int r, i
         for (int kc = 0; kc < 4; ++kc) acc = mfma(wfrag(P + oW3, H, H, mt, kc, r, g), F.hb2[kc], acc);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            F.h3[mt][j] = tanhf(acc[j] + P[ob3 + 16 * mt + 4 * g + j]);
+            F.h3[mt][j] = tanh_fast(acc[j] + P[ob3 + 16 * mt + 4 * g + j]);
             yp = fmaf(P[oW4 + 16 * mt + 4 * g + j], F.h3[mt][j], yp);
         }
     }
@@ -152,21 +159,92 @@ __device__ __forceinline__ void forward(const float *P, const float *x, int r, i
 }
 
 // ------------------------------------------------------------ inference
+// Weight fragments stay in registers for the whole kernel; biases and W4 sit
+// in LDS; the features of 64 samples are computed one sample per lane and
+// shared through LDS by the four 16-sample tiles.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_mlp_predict(const float *__restrict__ P, const double *__restrict__ st,
                                                      int64_t count, double *__restrict__ Tg) {
+    __shared__ float sbias[4][H];          // b1, b2, b3, W4
+    __shared__ float sx[4][64][8];         // per wave: features of 64 samples
+    for (int i = threadIdx.x; i < 4 * H; i += blockDim.x) {
+        const int l = i / H, k = i % H;
+        sbias[l][k] = P[(l == 0 ? ob1 : l == 1 ? ob2 : l == 2 ? ob3 : oW4) + k];
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
+    const float *nrm = P + oNorm;
+    bf16x4 W1f[4], W2f[4][4], W3f[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        W1f[mt] = wfrag(P + oW1, kSurIn, kSurIn, mt, 0, r, g);
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            W2f[mt][kc] = wfrag(P + oW2, H, H, mt, kc, r, g);
+            W3f[mt][kc] = wfrag(P + oW3, H, H, mt, kc, r, g);
+        }
+    }
+    const float b4 = P[ob4];
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const float *nrm = P + oNorm;
-    for (int64_t t0 = wave * 16; t0 < count; t0 += nwaves * 16) {
-        const int64_t n = t0 + r;
-        float x[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (n < count) features<DIM>(st, count, n, nrm, x);
-        Fwd F;
-        forward(P, x, r, g, F);
-        if (g == 0 && n < count) Tg[n] = (double)(F.y + P[ob4]) * (double)nrm[13] + (double)nrm[12];
+    for (int64_t s0 = wave * 64; s0 < count; s0 += nwaves * 64) {
+        {
+            float x[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (s0 + lane < count) features<DIM>(st, count, s0 + lane, nrm, x);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sx[w][lane][k] = x[k];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll 1
+        for (int tt = 0; tt < 4; ++tt) {
+            const int64_t n = s0 + 16 * tt + r;
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 4 * g + j;
+                v[j] = k < 6 ? sx[w][16 * tt + r][k] : 0.0f;
+            }
+            const bf16x4 xb = pack4(v[0], v[1], v[2], v[3]);
+            bf16x4 hb[4], hc[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                acc = mfma(W1f[mt], xb, acc);
+                float h[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) h[j] = tanh_fast(acc[j] + sbias[0][16 * mt + 4 * g + j]);
+                hb[mt] = pack4(h[0], h[1], h[2], h[3]);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) acc = mfma(W2f[mt][kc], hb[kc], acc);
+                float h[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) h[j] = tanh_fast(acc[j] + sbias[1][16 * mt + 4 * g + j]);
+                hc[mt] = pack4(h[0], h[1], h[2], h[3]);
+            }
+            float yp = 0.0f;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) acc = mfma(W3f[mt][kc], hc[kc], acc);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = 16 * mt + 4 * g + j;
+                    yp = fmaf(sbias[3][k], tanh_fast(acc[j] + sbias[2][k]), yp);
+                }
+            }
+            yp += __shfl_xor(yp, 16);
+            yp += __shfl_xor(yp, 32);
+            if (g == 0 && n < count) Tg[n] = (double)(yp + b4) * (double)nrm[13] + (double)nrm[12];
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -382,8 +460,8 @@ __global__ void k_adam(float *__restrict__ P, const float *__restrict__ grad, fl
 }
 
 int grid_for(int64_t count) {
-    const int64_t waves = (count + 15) / 16;
-    return (int)std::min<int64_t>((waves + 3) / 4, 4096);
+    const int64_t waves = (count + 63) / 64;
+    return (int)std::min<int64_t>((waves + 3) / 4, 2048);
 }
 
 }  // namespace

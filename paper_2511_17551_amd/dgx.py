@@ -223,7 +223,11 @@ def dgx_max_dt(ctx, u, cfl, stream=None):
     return out.value
 
 
-def dgx_thermo(ctx, u, T, p=None, guess=GUESS_FREESTREAM, nstates=0, stream=None, check=True):
+def dgx_thermo(ctx, u, T, p=None, guess=GUESS_FREESTREAM, nstates=0, stream=None, check=True, stats=True):
+    if not stats:
+        _raise(ctx, lib.dgx_thermo(ctx, _dev(u), int(nstates), _dev(T), _dev(p), int(guess), None,
+                                   _stream(stream)))
+        return None
     st = dgx_newton_stats()
     rc = lib.dgx_thermo(ctx, _dev(u), int(nstates), _dev(T), _dev(p), int(guess), C.byref(st), _stream(stream))
     if check:

@@ -73,8 +73,10 @@ def test_full_amr_rhs_and_conservation(dgx):
 
 
 def test_batched_equals_separate(dgx):
-    """One launch over the AMR domain + 4 vortex-tube cases gives bitwise the
-    same right-hand side as each case run on its own."""
+    """One launch over the AMR domain + 4 vortex-tube cases gives the same
+    right-hand side as each case run on its own (to roundoff: the batched mesh
+    has mortars and runs the mortar-enabled kernel variant, a lone tube the
+    conforming one, whose instruction schedules differ)."""
     sizes = [5, 7, 4, 6]
     c = W.case_c5(base=4, radii=(0.4, 0.25), sizes=sizes)
     got = gpu_rhs(dgx, c)
@@ -88,7 +90,7 @@ def test_batched_equals_separate(dgx):
         parts.append(gpu_rhs(dgx, W.Case("tube", W.base_cfg(3, 3, W.EQ_EULER), m, u0)))
     for i, ref in enumerate(parts):
         sl = got[:, offs[i]:offs[i + 1]]
-        assert np.array_equal(sl, ref), i
+        assert rel_err(sl, ref) < 1e-13, (i, rel_err(sl, ref))
 
 
 def test_c5_full_rhs(dgx):
