@@ -63,6 +63,37 @@ __device__ __forceinline__ void pair_of(int k, int &a, int &b) {
     b = a + 1 + k;
 }
 
+// Pairs (a < b) of a line in lexicographic order, packed as 4-bit fields:
+// a of pair k is (kPairA >> 4k) & 15, b likewise.
+template <int N1>
+struct PairTab {
+    static constexpr unsigned long long pack(bool second) {
+        unsigned long long t = 0;
+        int k = 0;
+        for (int a = 0; a < N1; ++a)
+            for (int b = a + 1; b < N1; ++b, ++k) t |= (unsigned long long)(second ? b : a) << (4 * k);
+        return t;
+    }
+    static constexpr unsigned long long A = pack(false), B = pack(true);
+};
+
+// A phase of K work items per element, spread over the NT = epb * NN threads
+// of the workgroup: round r covers items r * NT + t.  The partial last round
+// of consecutive phases starts where the previous one stopped (cursor), so
+// the extra rounds fall on different waves instead of always the first ones.
+struct Spread {
+    int t;       // this thread's slot within a round
+    int cursor;  // first slot of the next phase's partial round
+};
+__device__ __forceinline__ Spread spread_phase(int tid, int NT, int K_per_block, int cursor) {
+    int t = tid - cursor;
+    if (t < 0) t += NT;
+    int rem = K_per_block % NT;
+    int next = cursor + rem;
+    if (next >= NT) next -= NT;
+    return {t, next};
+}
+
 template <int DIM, int N, int EQ, int VF, bool CURV>
 struct RhsShape {
     static constexpr int N1 = N + 1;
@@ -72,8 +103,8 @@ struct RhsShape {
     static constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
     static constexpr int NW = DIM + 1;  // viscous flux components (momentum, energy)
     static constexpr bool EC = VF == 0;
-    // primitives: rho, v, p, rhoE [, c (mixture)] [, beta, ln rho, ln beta (EC)]
-    static constexpr int NQ = DIM + 3 + (MIX ? 1 : 0) + (EC ? 3 : 0);
+    // primitives: rho, v, p, rhoE [, c (mixture)] [, beta (EC)]
+    static constexpr int NQ = DIM + 3 + (MIX ? 1 : 0) + (EC ? 1 : 0);
     static constexpr int SU = MIX ? kNS * NN : 0;  // species densities
     static constexpr int NPL = N1 * N / 2;
     static constexpr int PD = NF * NPL;      // pairs per direction
@@ -89,7 +120,8 @@ struct RhsShape {
     static constexpr int M345 = M34 > B5 ? M34 : B5;
     static constexpr int BUF = M12 > M345 ? M12 : M345;
     static constexpr int GEO = CURV ? (DIM * DIM + 1) * NN : 0;
-    static constexpr int SLOT = SU + NQ * NN + GEO + BUF;
+    static constexpr int GEOA = CURV ? 0 : DIM * DIM + 1;  // affine: Ja rows, J
+    static constexpr int SLOT = SU + NQ * NN + GEO + GEOA + BUF;
 };
 
 // nrm = Jaf[d][:] for a runtime direction d without dynamic indexing of a
@@ -133,21 +165,26 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     constexpr bool MIX = S::MIX;
     constexpr int GA = DIM * DIM + 1;
     constexpr int QB = DIM + 3 + (MIX ? 1 : 0);  // first EC slot in sq
+    constexpr int OFF_G = S::SU + NQ * NN;        // element geometry within a slot
+    constexpr int OFF_B = OFF_G + S::GEO + S::GEOA;
     extern __shared__ double smem[];
 
     const int tid = threadIdx.x;
+    const int NT = P.epb * NN;  // threads that own a node
+    const int e0 = blockIdx.x * P.epb;
+    const int nloc = min(P.epb, P.nelem - e0);
     int el = tid / NN;
     const int node = tid - el * NN;
-    const int e = blockIdx.x * P.epb + el;
-    const bool valid = (el < P.epb) && (e < P.nelem);
+    const bool valid = el < nloc;
+    const int e = e0 + (valid ? el : 0);
     if (el >= P.epb) el = 0;
     double *su = smem + el * S::SLOT;
     double *sq = su + S::SU;
-    double *sJa = sq + NQ * NN;
+    double *sJa = su + OFF_G;
     double *sJ = sJa + DIM * DIM * NN;
-    double *buf = sq + NQ * NN + S::GEO;
+    double *buf = su + OFF_B;
     const size_t stride = (size_t)P.nelem * NN;
-    const size_t gi = (size_t)(valid ? e : 0) * NN + node;
+    const size_t gi = (size_t)e * NN + node;
     const double gamma = P.gamma;
 
     // ---- stage the element: primitives (+ species, metric terms)
@@ -161,6 +198,8 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
 #pragma unroll
                 for (int k = 0; k < DIM * DIM; ++k) sJa[k * NN + node] = P.geo[k * stride + gi];
                 sJ[node] = P.Jn[gi];
+            } else {
+                if (node < GA) sJa[node] = P.geo[(size_t)e * GA + node];
             }
             if constexpr (MIX) Tn = P.T[gi];
         } else {
@@ -181,10 +220,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                 for (int k = 0; k < kNS; ++k) su[k * NN + node] = own.rs[k];
             }
             if constexpr (S::EC) {
-                const double beta = own.rho / own.p;
-                sq[QB * NN + node] = beta;
-                sq[(QB + 1) * NN + node] = log(own.rho);
-                sq[(QB + 2) * NN + node] = log(beta);
+                sq[QB * NN + node] = own.rho / own.p;
             }
             bool ok = own.rho > 0.0 && own.p > 0.0 && isfinite(own.rhoE) && isfinite(own.p);
             if constexpr (MIX) {
@@ -194,120 +230,126 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
             if (!ok) atomicOr(P.flags, FLAG_NONPHYS);
         }
     }
-    // affine element geometry
-    double Jaf[DIM * DIM];
-    double Jel = 1.0;
-    if constexpr (!CURV) {
-        const double *g = P.geo + (size_t)(valid ? e : 0) * GA;
-#pragma unroll
-        for (int k = 0; k < DIM * DIM; ++k) Jaf[k] = g[k];
-        Jel = g[DIM * DIM];
-    }
-    const int ebase = (valid ? e : 0) * 2 * DIM;
     __syncthreads();
+    const double Jel = CURV ? 1.0 : sJa[DIM * DIM];
 
     double acc[NV];  // surface terms and alpha-weighted FV terms
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
 
+    // Work items (face nodes, volume pairs, neighbour viscous fluxes) of all
+    // elements of the workgroup are spread over all its threads.
+    int cursor = 0;
+
     // ---- interface / boundary Riemann fluxes: one work item per face node
+    {
+        const Spread sp = spread_phase(tid, NT, P.epb * NSF, cursor);
+        cursor = sp.cursor;
 #pragma unroll
-    for (int r = 0; r < (NSF + NN - 1) / NN; ++r) {
-        const int it = r * NN + node;
-        if (valid && it < NSF) {
-            const int f = it / NF;
-            const int q = it - f * NF;
-            const int d = f >> 1, side = f & 1;
-            const int nd = line_node<N1, DIM>(d, side ? N : 0, q);
-            St<DIM, MIX> own, ext;
-            lds_state<DIM, MIX>(su, sq, NN, nd, gamma, own);
-            double nrm[DIM];
-            if constexpr (CURV) {
+        for (int r = 0; r < (NSF + NN - 1) / NN; ++r) {
+            const int it = r * NT + sp.t;
+            if (tid < NT && it < nloc * NSF) {
+                const int ei = it / NSF;
+                const int fi = it - ei * NSF;
+                const int f = fi / NF;
+                const int q = fi - f * NF;
+                const int d = f >> 1, side = f & 1;
+                const double *esu = smem + ei * S::SLOT;
+                const double *esq = esu + S::SU;
+                const double *eg = esu + OFF_G;
+                double *ebuf = smem + ei * S::SLOT + OFF_B;
+                const int nd = line_node<N1, DIM>(d, side ? N : 0, q);
+                St<DIM, MIX> own, ext;
+                lds_state<DIM, MIX>(esu, esq, NN, nd, gamma, own);
+                double nrm[DIM];
+                if constexpr (CURV) {
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) nrm[c] = sJa[(d * DIM + c) * NN + nd];
-            } else {
-                jaf_row<DIM>(Jaf, d, nrm);
-            }
-            const int nb = P.nbr[ebase + f];
-            double F[NV];
-            if (MORT && nb <= kMortBase) {
-                // non-conforming face: sub-face fluxes from k_mortar
-                constexpr int NSUB = DIM == 3 ? 4 : 2;
-                const int code = kMortBase - nb;
-                const int m = code >> 3, role = code & 7;
-                const double *mf = P.mflux + (size_t)m * NSUB * NV * NF;
-                if (role < NSUB) {
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) F[v] = mf[(role * NV + v) * NF + q];
+                    for (int c = 0; c < DIM; ++c) nrm[c] = eg[(d * DIM + c) * NN + nd];
                 } else {
-                    // large side: 2^(dim-1) sum_s (P_a x P_b) F*_s
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) F[v] = 0.0;
-                    const int qa = q % N1, qb = q / N1;
-#pragma unroll 1
-                    for (int sb = 0; sb < NSUB; ++sb) {
-                        const int a = sb & 1, bsel = sb >> 1;
-#pragma unroll 1
-                        for (int qq = 0; qq < NF; ++qq) {
-                            const int ja = qq % N1, jb = qq / N1;
-                            double w = P.Pm[a][qa * N1 + ja];
-                            if (DIM == 3) w *= P.Pm[bsel][qb * N1 + jb];
-#pragma unroll
-                            for (int v = 0; v < NV; ++v) F[v] = fma(w, mf[(sb * NV + v) * NF + qq], F[v]);
-                        }
-                    }
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) F[v] *= (double)NSUB;
+                    for (int c = 0; c < DIM; ++c) nrm[c] = eg[d * DIM + c];
                 }
+                const int nb = P.nbr[(e0 + ei) * 2 * DIM + f];
+                double F[NV];
+                if (MORT && nb <= kMortBase) {
+                    // non-conforming face: sub-face fluxes from k_mortar
+                    constexpr int NSUB = DIM == 3 ? 4 : 2;
+                    const int code = kMortBase - nb;
+                    const int m = code >> 3, role = code & 7;
+                    const double *mf = P.mflux + (size_t)m * NSUB * NV * NF;
+                    if (role < NSUB) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) buf[v * NSF + it] = F[v];
-                continue;
-            }
-            if (nb >= 0) {
-                const int nbn = line_node<N1, DIM>(d, side ? 0 : N, q);
-                const size_t gj = (size_t)nb * NN + nbn;
-                double ue[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) ue[v] = P.u[v * stride + gj];
-                const double Te = MIX ? P.T[gj] : 0.0;
-                make_state<DIM, MIX>(ue, Te, gamma, P.M, ext);
-                if (side == 0) {
-                    if constexpr (CURV) {
-#pragma unroll
-                        for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(d * DIM + c) * stride + gj];
+                        for (int v = 0; v < NV; ++v) F[v] = mf[(role * NV + v) * NF + q];
                     } else {
+                        // large side: 2^(dim-1) sum_s (P_a x P_b) F*_s
 #pragma unroll
-                        for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(size_t)nb * GA + d * DIM + c];
+                        for (int v = 0; v < NV; ++v) F[v] = 0.0;
+                        const int qa = q % N1, qb = q / N1;
+#pragma unroll 1
+                        for (int sb = 0; sb < NSUB; ++sb) {
+                            const int a = sb & 1, bsel = sb >> 1;
+#pragma unroll 1
+                            for (int qq = 0; qq < NF; ++qq) {
+                                const int ja = qq % N1, jb = qq / N1;
+                                double w = P.Pm[a][qa * N1 + ja];
+                                if (DIM == 3) w *= P.Pm[bsel][qb * N1 + jb];
+#pragma unroll
+                                for (int v = 0; v < NV; ++v) F[v] = fma(w, mf[(sb * NV + v) * NF + qq], F[v]);
+                            }
+                        }
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) F[v] *= (double)NSUB;
                     }
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) ebuf[v * NSF + fi] = F[v];
+                    continue;
                 }
-            } else {
-                const int bc = -1 - nb;
-                const int kind = P.bc_kind[bc];
-                if (kind == 0) {
+                if (nb >= 0) {
+                    const int nbn = line_node<N1, DIM>(d, side ? 0 : N, q);
+                    const size_t gj = (size_t)nb * NN + nbn;
                     double ue[NV];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) ue[v] = P.bc_state[bc * NV + v];
-                    make_state<DIM, MIX>(ue, MIX ? P.bc_T[bc] : 0.0, gamma, P.M, ext);
-                } else if (kind == 1) {
-                    ext = own;
+                    for (int v = 0; v < NV; ++v) ue[v] = P.u[v * stride + gj];
+                    const double Te = MIX ? P.T[gj] : 0.0;
+                    make_state<DIM, MIX>(ue, Te, gamma, P.M, ext);
+                    if (side == 0) {
+                        if constexpr (CURV) {
+#pragma unroll
+                            for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(d * DIM + c) * stride + gj];
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(size_t)nb * GA + d * DIM + c];
+                        }
+                    }
                 } else {
-                    // slip wall: mirror the velocity about the face (T and p unchanged)
-                    const double inn = rcp(dotn<DIM>(nrm, nrm));
-                    const double vn = dotn<DIM>(own.v, nrm) * inn;
-                    ext = own;
+                    const int bc = -1 - nb;
+                    const int kind = P.bc_kind[bc];
+                    if (kind == 0) {
+                        double ue[NV];
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) ext.v[c] = own.v[c] - 2.0 * vn * nrm[c];
+                        for (int v = 0; v < NV; ++v) ue[v] = P.bc_state[bc * NV + v];
+                        make_state<DIM, MIX>(ue, MIX ? P.bc_T[bc] : 0.0, gamma, P.M, ext);
+                    } else if (kind == 1) {
+                        ext = own;
+                    } else {
+                        // slip wall: mirror the velocity about the face (T and p unchanged)
+                        const double inn = rcp(dotn<DIM>(nrm, nrm));
+                        const double vn = dotn<DIM>(own.v, nrm) * inn;
+                        ext = own;
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) ext.v[c] = own.v[c] - 2.0 * vn * nrm[c];
+                    }
                 }
-            }
-            if constexpr (SF == 0) {
-                if (side) rusanov<DIM, MIX>(own, ext, nrm, F);
-                else rusanov<DIM, MIX>(ext, own, nrm, F);
-            } else {
-                if (side) ranocha_state<DIM, MIX>(own, ext, nrm, gamma, F);
-                else ranocha_state<DIM, MIX>(ext, own, nrm, gamma, F);
-            }
+                if constexpr (SF == 0) {
+                    if (side) rusanov<DIM, MIX>(own, ext, nrm, F);
+                    else rusanov<DIM, MIX>(ext, own, nrm, F);
+                } else {
+                    if (side) ranocha_state<DIM, MIX>(own, ext, nrm, gamma, F);
+                    else ranocha_state<DIM, MIX>(ext, own, nrm, gamma, F);
+                }
 #pragma unroll
-            for (int v = 0; v < NV; ++v) buf[v * NSF + it] = F[v];
+                for (int v = 0; v < NV; ++v) ebuf[v * NSF + fi] = F[v];
+            }
         }
     }
     __syncthreads();
@@ -336,40 +378,47 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     const double gm1_inv = 1.0 / (gamma - 1.0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
+        const Spread sp = spread_phase(tid, NT, P.epb * PD, cursor);
+        cursor = sp.cursor;
 #pragma unroll
         for (int r = 0; r < (PD + NN - 1) / NN; ++r) {
-            const int p = r * NN + node;
-            if (valid && p < PD) {
+            const int it = r * NT + sp.t;
+            if (tid < NT && it < nloc * PD) {
+                const int ei = it / PD;
+                const int p = it - ei * PD;
                 const int l = p / NPL;
-                int a, b;
-                pair_of<N1>(p - l * NPL, a, b);
+                const int k = p - l * NPL;
+                const int a = (int)((PairTab<N1>::A >> (4 * k)) & 15u);
+                const int b = (int)((PairTab<N1>::B >> (4 * k)) & 15u);
+                const double *esu = smem + ei * S::SLOT;
+                const double *esq = esu + S::SU;
+                const double *eg = esu + OFF_G;
+                double *ebuf = smem + ei * S::SLOT + OFF_B;
                 const int na = line_node<N1, DIM>(d, a, l);
                 const int nb = line_node<N1, DIM>(d, b, l);
                 double nbar[DIM];
 #pragma unroll
                 for (int c = 0; c < DIM; ++c)
-                    nbar[c] = CURV ? 0.5 * (sJa[(d * DIM + c) * NN + na] + sJa[(d * DIM + c) * NN + nb])
-                                   : Jaf[d * DIM + c];
+                    nbar[c] = CURV ? 0.5 * (eg[(d * DIM + c) * NN + na] + eg[(d * DIM + c) * NN + nb])
+                                   : eg[d * DIM + c];
                 double F[NV];
                 if constexpr (S::EC) {
                     double vA[DIM], vB[DIM];
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) {
-                        vA[c] = sq[(1 + c) * NN + na];
-                        vB[c] = sq[(1 + c) * NN + nb];
+                        vA[c] = esq[(1 + c) * NN + na];
+                        vB[c] = esq[(1 + c) * NN + nb];
                     }
-                    ranocha_prims<DIM>(sq[na], vA, sq[(1 + DIM) * NN + na], sq[QB * NN + na],
-                                       sq[(QB + 1) * NN + na], sq[(QB + 2) * NN + na], sq[nb], vB,
-                                       sq[(1 + DIM) * NN + nb], sq[QB * NN + nb], sq[(QB + 1) * NN + nb],
-                                       sq[(QB + 2) * NN + nb], nbar, gm1_inv, F);
+                    ranocha_prims<DIM>(esq[na], vA, esq[(1 + DIM) * NN + na], esq[QB * NN + na], esq[nb], vB,
+                                       esq[(1 + DIM) * NN + nb], esq[QB * NN + nb], nbar, gm1_inv, F);
                 } else {
                     St<DIM, MIX> A, B;
-                    lds_state<DIM, MIX>(su, sq, NN, na, gamma, A);
-                    lds_state<DIM, MIX>(su, sq, NN, nb, gamma, B);
+                    lds_state<DIM, MIX>(esu, esq, NN, na, gamma, A);
+                    lds_state<DIM, MIX>(esu, esq, NN, nb, gamma, B);
                     ducros_state<DIM, MIX>(A, B, nbar, F);
                 }
 #pragma unroll
-                for (int v = 0; v < NV; ++v) buf[v * PD + p] = F[v];
+                for (int v = 0; v < NV; ++v) ebuf[v * PD + p] = F[v];
             }
         }
         __syncthreads();
@@ -387,7 +436,6 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
         }
         __syncthreads();
     }
-
     // ---- first-order subcell finite volumes (elements with alpha > 0)
     const double alpha = (P.alpha != nullptr && valid) ? P.alpha[e] : 0.0;
     if (__syncthreads_or(alpha > 0.0)) {
@@ -408,7 +456,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                         for (int c = 0; c < DIM; ++c) nrm[c] = ns[c];
                     } else {
 #pragma unroll
-                        for (int c = 0; c < DIM; ++c) nrm[c] = Jaf[d * DIM + c];
+                        for (int c = 0; c < DIM; ++c) nrm[c] = sJa[d * DIM + c];
                     }
                     St<DIM, MIX> A, B;
                     lds_state<DIM, MIX>(su, sq, NN, nL, gamma, A);
@@ -449,17 +497,21 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
         double vis[NW];
 #pragma unroll
         for (int k = 0; k < NW; ++k) vis[k] = 0.0;
+        const Spread sp = spread_phase(tid, NT, P.epb * NSF, cursor);
 #pragma unroll
         for (int r = 0; r < (NSF + NN - 1) / NN; ++r) {
-            const int it = r * NN + node;
-            if (valid && it < NSF) {
-                const int f = it / NF;
-                const int q = it - f * NF;
-                const int nb = P.nbr[ebase + f];
+            const int it = r * NT + sp.t;
+            if (tid < NT && it < nloc * NSF) {
+                const int ei = it / NSF;
+                const int fi = it - ei * NSF;
+                const int f = fi / NF;
+                const int q = fi - f * NF;
+                const int nb = P.nbr[(e0 + ei) * 2 * DIM + f];
                 const double *fn = P.grad + ((size_t)nb * 2 * DIM + (f ^ 1)) * NW * NF + q;
                 const double sc = (f & 1) ? 0.5 / P.B.w[N] : -0.5 / P.B.w[0];
+                double *ebuf = smem + ei * S::SLOT + OFF_B;
 #pragma unroll
-                for (int k = 0; k < NW; ++k) buf[k * NSF + it] = sc * fn[k * NF];
+                for (int k = 0; k < NW; ++k) ebuf[k * NSF + fi] = sc * fn[k * NF];
             }
         }
         __syncthreads();

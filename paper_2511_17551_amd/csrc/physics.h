@@ -46,7 +46,7 @@ __device__ __forceinline__ double rcp(double x) {
 // P = 2 + 2z/3 + 2z^2/5 + 2z^3/7; here 1/P is itself expanded,
 // 2/P = 1 - z/3 - 4z^2/45 - 44z^3/945 + O(z^4) (remainder < 1e-17 relative),
 // which saves a reciprocal.
-__device__ __forceinline__ double ln_mean(double x, double y, double lx, double ly) {
+__device__ __forceinline__ double ln_mean(double x, double y) {
     const double s = x + y;
     const double d = y - x;
     if (d * d < 1e-4 * (s * s)) {
@@ -55,11 +55,11 @@ __device__ __forceinline__ double ln_mean(double x, double y, double lx, double 
         const double h = 0.5 * s;
         return fma(-h * z, 1.0 / 3.0 + z * (4.0 / 45.0 + z * (44.0 / 945.0)), h);
     }
-    return d * rcp(ly - lx);
+    return d * rcp(log(y * rcp(x)));
 }
 
 // Reciprocal of the logarithmic mean, ln(y/x)/(y - x) (same branches).
-__device__ __forceinline__ double inv_ln_mean(double x, double y, double lx, double ly) {
+__device__ __forceinline__ double inv_ln_mean(double x, double y) {
     const double s = x + y;
     const double d = y - x;
     if (d * d < 1e-4 * (s * s)) {
@@ -69,7 +69,7 @@ __device__ __forceinline__ double inv_ln_mean(double x, double y, double lx, dou
         const double P = 2.0 + z * (2.0 / 3.0 + z * (2.0 / 5.0 + z * (2.0 / 7.0)));
         return P * rs;
     }
-    return (ly - lx) * rcp(d);
+    return log(y * rcp(x)) * rcp(d);
 }
 
 // ---------------------------------------------------------------- mixture
@@ -217,12 +217,11 @@ __device__ __forceinline__ void rusanov(const St<DIM, MIX> &L, const St<DIM, MIX
 
 // Ranocha flux from primitive values (perfect gas).
 template <int DIM>
-__device__ __forceinline__ void ranocha_prims(double rL, const double *vL, double pL, double bL,
-                                              double lrL, double lbL, double rR, const double *vR,
-                                              double pR, double bR, double lrR, double lbR,
-                                              const double *n, double gm1_inv, double *F) {
-    const double rho_hat = ln_mean(rL, rR, lrL, lrR);
-    const double ibeta_hat = inv_ln_mean(bL, bR, lbL, lbR);
+__device__ __forceinline__ void ranocha_prims(double rL, const double *vL, double pL, double bL, double rR,
+                                              const double *vR, double pR, double bR, const double *n,
+                                              double gm1_inv, double *F) {
+    const double rho_hat = ln_mean(rL, rR);
+    const double ibeta_hat = inv_ln_mean(bL, bR);
     double vbar[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) vbar[c] = 0.5 * (vL[c] + vR[c]);
@@ -239,8 +238,7 @@ template <int DIM, bool MIX>
 __device__ __forceinline__ void ranocha_state(const St<DIM, MIX> &L, const St<DIM, MIX> &R,
                                               const double *n, double gamma, double *F) {
     const double bL = L.rho / L.p, bR = R.rho / R.p;
-    ranocha_prims<DIM>(L.rho, L.v, L.p, bL, log(L.rho), log(bL), R.rho, R.v, R.p, bR, log(R.rho),
-                       log(bR), n, 1.0 / (gamma - 1.0), F);
+    ranocha_prims<DIM>(L.rho, L.v, L.p, bL, R.rho, R.v, R.p, bR, n, 1.0 / (gamma - 1.0), F);
 }
 
 // Ducros split-form flux: {{rho_s}} {{v}}.n, {{m}} {{v}}.n + {{p}} n, ({{rhoE}} + {{p}}) {{v}}.n
