@@ -113,12 +113,8 @@ struct RhsShape {
     static constexpr int B1 = PD * NV;
     static constexpr int B2 = NFV * NV;
     static constexpr int B3 = NSF * NV;
-    static constexpr int B4 = 0;
-    static constexpr int B5 = EQ == 1 ? NSF * NW : 0;
     static constexpr int M12 = B1 > B2 ? B1 : B2;
-    static constexpr int M34 = B3 > B4 ? B3 : B4;
-    static constexpr int M345 = M34 > B5 ? M34 : B5;
-    static constexpr int BUF = M12 > M345 ? M12 : M345;
+    static constexpr int BUF = M12 > B3 ? M12 : B3;
     static constexpr int GEO = CURV ? (DIM * DIM + 1) * NN : 0;
     static constexpr int GEOA = CURV ? 0 : DIM * DIM + 1;  // affine: Ja rows, J
     static constexpr int SLOT = SU + NQ * NN + GEO + GEOA + BUF;
@@ -304,12 +300,20 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                     for (int v = 0; v < NV; ++v) ebuf[v * NSF + fi] = F[v];
                     continue;
                 }
+                double ftn[NW];  // neighbour's contravariant viscous face flux (BR1)
+#pragma unroll
+                for (int k = 0; k < NW; ++k) ftn[k] = 0.0;
                 if (nb >= 0) {
                     const int nbn = line_node<N1, DIM>(d, side ? 0 : N, q);
                     const size_t gj = (size_t)nb * NN + nbn;
                     double ue[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) ue[v] = P.u[v * stride + gj];
+                    if constexpr (EQ == 1) {
+                        const double *fn = P.grad + ((size_t)nb * 2 * DIM + (f ^ 1)) * NW * NF + q;
+#pragma unroll
+                        for (int k = 0; k < NW; ++k) ftn[k] = fn[k * NF];
+                    }
                     const double Te = MIX ? P.T[gj] : 0.0;
                     make_state<DIM, MIX>(ue, Te, gamma, P.M, ext);
                     if (side == 0) {
@@ -346,6 +350,14 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                 } else {
                     if (side) ranocha_state<DIM, MIX>(own, ext, nrm, gamma, F);
                     else ranocha_state<DIM, MIX>(ext, own, nrm, gamma, F);
+                }
+                if constexpr (EQ == 1) {
+                    // BR1 interface flux {{F_v}}: the element's own half is in
+                    // the gradient kernel's output, the neighbour's half enters
+                    // with the inviscid flux (F* - F_v/2 on the momentum and
+                    // energy rows; periodic meshes only, so nb >= 0 here).
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) F[1 + k] -= 0.5 * ftn[k];
                 }
 #pragma unroll
                 for (int v = 0; v < NV; ++v) ebuf[v * NSF + fi] = F[v];
@@ -490,46 +502,13 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     for (int v = 0; v < NV; ++v) du[v] = -fma(1.0 - alpha, dg[v], acc[v]) * iJ;
 
     // ---- BR1 viscous divergence (perfect-gas Navier-Stokes, affine elements).
-    // k_grad wrote the element-local part (P.vpart) and every element's face
-    // contravariant viscous fluxes (P.grad); what remains are the neighbours'
-    // halves of the averaged interface fluxes, +-Ft_nbr / (2 w).
+    // The gradient kernel wrote the element-local part (volume divergence and
+    // the element's own halves of the interface fluxes); the neighbours'
+    // halves came in with the face fluxes above.
     if constexpr (EQ == 1) {
-        double vis[NW];
-#pragma unroll
-        for (int k = 0; k < NW; ++k) vis[k] = 0.0;
-        const Spread sp = spread_phase(tid, NT, P.epb * NSF, cursor);
-#pragma unroll
-        for (int r = 0; r < (NSF + NN - 1) / NN; ++r) {
-            const int it = r * NT + sp.t;
-            if (tid < NT && it < nloc * NSF) {
-                const int ei = it / NSF;
-                const int fi = it - ei * NSF;
-                const int f = fi / NF;
-                const int q = fi - f * NF;
-                const int nb = P.nbr[(e0 + ei) * 2 * DIM + f];
-                const double *fn = P.grad + ((size_t)nb * 2 * DIM + (f ^ 1)) * NW * NF + q;
-                const double sc = (f & 1) ? 0.5 / P.B.w[N] : -0.5 / P.B.w[0];
-                double *ebuf = smem + ei * S::SLOT + OFF_B;
-#pragma unroll
-                for (int k = 0; k < NW; ++k) ebuf[k * NSF + fi] = sc * fn[k * NF];
-            }
-        }
-        __syncthreads();
         if (valid) {
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) {
-                const int a = node_pos<N1>(node, d);
-                const int l = node_line<N1, DIM>(node, d);
-                if (a == N) {
-#pragma unroll
-                    for (int k = 0; k < NW; ++k) vis[k] += buf[k * NSF + (2 * d + 1) * NF + l];
-                } else if (a == 0) {
-#pragma unroll
-                    for (int k = 0; k < NW; ++k) vis[k] += buf[k * NSF + (2 * d) * NF + l];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < NW; ++k) du[1 + k] += fma(vis[k], iJ, P.vpart[(size_t)k * stride + gi]);
+            for (int k = 0; k < NW; ++k) du[1 + k] += P.vpart[(size_t)k * stride + gi];
         }
     }
 
