@@ -41,7 +41,8 @@ void rhs_launch(const RhsParams &P, int mode, int blocks, int threads, size_t ld
     hipLaunchKernelGGL((k_rhs<DIM, N, EQ, VF, SF, CURV, MORT>), dim3(blocks), dim3(threads), lds, s, P, mode);
 }
 template <int DIM, int N>
-void grad_launch(const RhsParams &P, int blocks, int threads, size_t lds, hipStream_t s) {
+void grad_launch(const RhsParams &P, int blocks, int threads, hipStream_t s) {
+    const size_t lds = (size_t)P.epb * GradShape<DIM, N>::SLOT * sizeof(double);
     hipLaunchKernelGGL((k_grad<DIM, N>), dim3(blocks), dim3(threads), lds, s, P);
 }
 template <int DIM, int N, bool MIX>
@@ -313,10 +314,9 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
         RhsParams G = P;
         G.out = ctx->vpart.p;
         G.out2 = ctx->grad.p;
-        const size_t lds = (size_t)epb * (c.dim + 1) * ctx->nn * sizeof(double);
-        if (c.dim == 3 && c.N == 3) grad_launch<3, 3>(G, blocks, th, lds, s);
-        else if (c.dim == 3 && c.N == 4) grad_launch<3, 4>(G, blocks, th, lds, s);
-        else if (c.dim == 2 && c.N == 3) grad_launch<2, 3>(G, blocks, th, lds, s);
+        if (c.dim == 3 && c.N == 3) grad_launch<3, 3>(G, blocks, th, s);
+        else if (c.dim == 3 && c.N == 4) grad_launch<3, 4>(G, blocks, th, s);
+        else if (c.dim == 2 && c.N == 3) grad_launch<2, 3>(G, blocks, th, s);
         else return set_err(ctx, DGX_E_INVAL, "NS gradients not built for this dim/N");
         tape_mark(tp, "k_grad", s);
     }

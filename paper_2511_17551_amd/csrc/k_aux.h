@@ -21,23 +21,36 @@ namespace dgx {
 // Affine elements (Ja^d constant); on a conforming face of two affine
 // elements Ja^d of both sides is the area vector of the shared face.
 template <int DIM, int N>
+struct GradShape {
+    static constexpr int N1 = N + 1;
+    static constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+    static constexpr int NF = NN / N1;
+    static constexpr int NW = DIM + 1;
+    static constexpr int NSF = 2 * DIM * NF;
+    // own W (and later Ft^d), neighbours' face traces of W
+    static constexpr int SLOT = NW * NN + NW * NSF;
+};
+
+template <int DIM, int N>
 __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
-    constexpr int N1 = N + 1;
-    constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
-    constexpr int NF = NN / N1;
+    using S = GradShape<DIM, N>;
+    constexpr int N1 = N + 1, NN = S::NN, NF = S::NF, NW = S::NW, NSF = S::NSF;
     constexpr int NV = DIM + 2;
-    constexpr int NW = DIM + 1;
     constexpr int GA = DIM * DIM + 1;
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
+    const int NT = P.epb * NN;
+    const int e0 = blockIdx.x * P.epb;
+    const int nloc = min(P.epb, P.nelem - e0);
     int el = tid / NN;
     const int node = tid - el * NN;
-    const int e = blockIdx.x * P.epb + el;
-    const bool valid = (el < P.epb) && (e < P.nelem);
+    const bool valid = el < nloc;
+    const int e = e0 + (valid ? el : 0);
     if (el >= P.epb) el = 0;
-    double *sw = smem + el * NW * NN;
+    double *sw = smem + el * S::SLOT;
+    double *sn = sw + NW * NN;
     const unsigned stride = (unsigned)P.nelem * NN;
-    const unsigned gi = (unsigned)(valid ? e : 0) * NN + node;
+    const unsigned gi = (unsigned)e * NN + node;
 
     auto prim = [&](const double *u, double *W) {
         const double ir = rcp(u[0]);
@@ -50,6 +63,32 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
         const double p = (P.gamma - 1.0) * (u[1 + DIM] - 0.5 * u[0] * v2);
         W[DIM] = p * ir / P.R;
     };
+
+    // Neighbour face traces: one item per face node of every element of the
+    // workgroup, spread over all threads; all loads are issued up front.
+    constexpr int RF = (NSF + NN - 1) / NN;
+    const Spread spf = spread_phase(tid, NT, P.epb * NSF, 0);
+    double un[RF][NV];
+    int slot[RF];
+#pragma unroll
+    for (int r = 0; r < RF; ++r) {
+        const int it = r * NT + spf.t;
+        slot[r] = -1;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) un[r][v] = 1.0;
+        if (tid < NT && it < nloc * NSF) {
+            const int ei = it / NSF;
+            const int fi = it - ei * NSF;
+            const int f = fi / NF;
+            const int q = fi - f * NF;
+            const int d = f >> 1, side = f & 1;
+            const int nb = P.nbr[(e0 + ei) * 2 * DIM + f];
+            const unsigned gj = (unsigned)nb * NN + line_node<N1, DIM>(d, side ? 0 : N, q);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) un[r][v] = (P.u + (size_t)v * stride)[gj];
+            slot[r] = ei * S::SLOT + NW * NN + fi;
+        }
+    }
     double Wo[NW];
     if (valid) {
         double uo[NV];
@@ -62,8 +101,20 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) Wo[w] = 0.0;
     }
+#pragma unroll
+    for (int r = 0; r < RF; ++r) {
+        if (slot[r] >= 0) {
+            double Wn[NW];
+            prim(un[r], Wn);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) smem[slot[r] + w * NSF] = Wn[w];
+        }
+    }
     __syncthreads();
-    const double *g = P.geo + (size_t)(valid ? e : 0) * GA;
+    // with a multiple of 64 nodes per element every wave holds one element:
+    // its metric terms then live in scalar registers
+    const int eu = (NN % 64 == 0) ? __builtin_amdgcn_readfirstlane(e) : e;
+    const double *g = P.geo + (size_t)eu * GA;
     double Ja[DIM * DIM];
 #pragma unroll
     for (int k = 0; k < DIM * DIM; ++k) Ja[k] = g[k];
@@ -90,16 +141,11 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
             }
             if (a == 0 || a == N) {
                 const int side = (a == N) ? 1 : 0;
-                const int nb = P.nbr[e * 2 * DIM + 2 * d + side];
-                const unsigned gj = (unsigned)nb * NN + line_node<N1, DIM>(d, side ? 0 : N, l);
-                double un[NV], Wn[NW];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) un[v] = (P.u + (size_t)v * stride)[gj];
-                prim(un, Wn);
+                const int fi = (2 * d + side) * NF + l;
                 const double sc = side ? 1.0 / P.B.w[N] : -1.0 / P.B.w[0];
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
-                    const double ws = 0.5 * (Wo[w] + Wn[w]);
+                    const double ws = 0.5 * (Wo[w] + sn[w * NSF + fi]);
                     dW[w] = fma(sc, ws - Wo[w], dW[w]);
                 }
             }

@@ -148,6 +148,8 @@ __device__ __forceinline__ void lds_state(const double *su, const double *sq, in
 #pragma unroll
         for (int k = 0; k < kNS; ++k) s.rs[k] = su[k * NN + n];
     } else {
+        // perfect gas: recomputed (one LDS array less keeps five 4-element
+        // workgroups per CU); bitwise equal to the value make_state gives
         s.c = sqrt(gamma * s.p * rcp(s.rho));
         s.rs[0] = 0.0;
     }
@@ -160,7 +162,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     constexpr int NPL = S::NPL, PD = S::PD, NFV = S::NFV, NSF = S::NSF;
     constexpr bool MIX = S::MIX;
     constexpr int GA = DIM * DIM + 1;
-    constexpr int QB = DIM + 3 + (MIX ? 1 : 0);  // first EC slot in sq
+    constexpr int QB = DIM + 3 + (MIX ? 1 : 0);  // EC slot in sq
     constexpr int OFF_G = S::SU + NQ * NN;        // element geometry within a slot
     constexpr int OFF_B = OFF_G + S::GEO + S::GEOA;
     extern __shared__ double smem[];
@@ -182,6 +184,23 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     const size_t stride = (size_t)P.nelem * NN;
     const size_t gi = (size_t)e * NN + node;
     const double gamma = P.gamma;
+
+    // Work items (face nodes, volume pairs) of all elements of the workgroup
+    // are spread over all its threads.  The face phase's neighbour indices
+    // are fetched first so that their latency overlaps the staging.
+    constexpr int RF = (NSF + NN - 1) / NN;
+    const Spread spf = spread_phase(tid, NT, P.epb * NSF, 0);
+    int cursor = spf.cursor;
+    int nbf[RF];
+#pragma unroll
+    for (int r = 0; r < RF; ++r) {
+        const int it = r * NT + spf.t;
+        nbf[r] = 0;
+        if (tid < NT && it < nloc * NSF) {
+            const int ei = it / NSF;
+            nbf[r] = P.nbr[(e0 + ei) * 2 * DIM + (it - ei * NSF) / NF];
+        }
+    }
 
     // ---- stage the element: primitives (+ species, metric terms)
     {
@@ -233,17 +252,11 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
 
-    // Work items (face nodes, volume pairs, neighbour viscous fluxes) of all
-    // elements of the workgroup are spread over all its threads.
-    int cursor = 0;
-
     // ---- interface / boundary Riemann fluxes: one work item per face node
     {
-        const Spread sp = spread_phase(tid, NT, P.epb * NSF, cursor);
-        cursor = sp.cursor;
 #pragma unroll
-        for (int r = 0; r < (NSF + NN - 1) / NN; ++r) {
-            const int it = r * NT + sp.t;
+        for (int r = 0; r < RF; ++r) {
+            const int it = r * NT + spf.t;
             if (tid < NT && it < nloc * NSF) {
                 const int ei = it / NSF;
                 const int fi = it - ei * NSF;
@@ -265,7 +278,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) nrm[c] = eg[d * DIM + c];
                 }
-                const int nb = P.nbr[(e0 + ei) * 2 * DIM + f];
+                const int nb = nbf[r];
                 double F[NV];
                 if (MORT && nb <= kMortBase) {
                     // non-conforming face: sub-face fluxes from k_mortar
