@@ -202,6 +202,25 @@ int dgx_max_dt(dgx_ctx *ctx, const double *u, double cfl, double *dt_host, void 
 int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double *p,
                int guess_mode, dgx_newton_stats *stats, void *stream);
 
+/* Per-node stiff chemistry, split from the transport (Governing Equations,
+ * Eq. source_term; rates of Appendix, Chemical Kinetics): one backward-Euler
+ * step over dt >= 0 of the species sources at fixed density, momentum and
+ * total energy, in place on the species rows of u (device [nvar][nelem][nn]
+ * of the mesh).  Needs a mixture context created with a reaction table
+ * (DGX_EQ_EULER_MIX with cfg->reactions, or DGX_EQ_REACT_MIX).  Newton with
+ * the analytic Jacobian along the fixed-energy manifold; every iterate's T
+ * comes from the T(e) solve warm-started at the previous one (first: the
+ * incoming state's T); steps are limited so that rho_s >= 0 and the thermal
+ * energy rho e - sum rho_s e0_s stays positive; a node stops when its full
+ * Newton step is below tol * rho, after at most maxit iterations.  The
+ * library's per-node temperature is left at the new state's T.  Enqueues on
+ * stream; with stats (host) it synchronises and fills the iteration
+ * statistics (DGX_E_NOCONV if a node failed), with stats == NULL failures are
+ * reported by dgx_check.  With a DGX_EQ_EULER_MIX context, dt/2 chemistry,
+ * dgx_ssprk3_step over dt and dt/2 chemistry form a Strang splitting. */
+int dgx_chem_step(dgx_ctx *ctx, double *u, double dt, double tol, int maxit, dgx_newton_stats *stats,
+                  void *stream);
+
 /* Shock-indicator blending factor of the last dgx_rhs call (device pointer
  * to [nelem] doubles owned by the library; NULL if shock capturing is off). */
 const double *dgx_last_alpha(const dgx_ctx *ctx);

@@ -15,6 +15,7 @@
 #include "../../include/dgx.h"
 #include "host_geometry.h"
 #include "k_aux.h"
+#include "k_chem.h"
 #include "surrogate.h"
 
 using namespace dgx;
@@ -406,8 +407,8 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
     if (mix && (!cfg->species || cfg->species->nspecies != 5)) return DGX_E_INVAL;
     if (mix && cfg->volume_flux == DGX_VF_RANOCHA) return DGX_E_INVAL;
     if (mix && cfg->surface_flux != DGX_SF_RUSANOV) return DGX_E_INVAL;
-    if (cfg->equation == DGX_EQ_REACT_MIX &&
-        (!cfg->reactions || cfg->reactions->nreactions < 1 || cfg->reactions->nreactions > kMaxR))
+    if (cfg->equation == DGX_EQ_REACT_MIX && !cfg->reactions) return DGX_E_INVAL;
+    if (mix && cfg->reactions && (cfg->reactions->nreactions < 1 || cfg->reactions->nreactions > kMaxR))
         return DGX_E_INVAL;
     if (cfg->equation == DGX_EQ_NS && (cfg->mu < 0.0 || cfg->Pr <= 0.0)) return DGX_E_INVAL;
     if (!mix && !(cfg->gamma > 1.0)) return DGX_E_INVAL;
@@ -437,7 +438,9 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
             ctx->mix.mol[s] = ctx->sp.molecule[s] ? 1 : 0;
         }
     }
-    if (cfg->equation == DGX_EQ_REACT_MIX) {
+    if (mix && cfg->reactions) {
+        // reaction table: sources in the right-hand side (DGX_EQ_REACT_MIX)
+        // and the split stiff-chemistry step (dgx_chem_step)
         const dgx_reactions *r = cfg->reactions;
         KinC &K = ctx->kin;
         K.nr = r->nreactions;
@@ -662,7 +665,7 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         if ((rc = dalloc(ctx, ctx->grad, (size_t)E * 2 * dim * (dim + 1) * ctx->nf))) return rc;
         if ((rc = dalloc(ctx, ctx->vpart, (size_t)(dim + 1) * E * nn))) return rc;
     }
-    if (ctx->cfg.equation == DGX_EQ_REACT_MIX) {
+    if (ctx->kin.nr > 0) {
         if ((rc = dalloc(ctx, ctx->kin_d, 1))) return rc;
         HIPCHK(hipMemcpy(ctx->kin_d.p, &ctx->kin, sizeof(KinC), hipMemcpyHostToDevice));
     }
@@ -766,6 +769,42 @@ int dgx_max_dt(dgx_ctx *ctx, const double *u, double cfl, double *dt_host, void 
     return DGX_OK;
 }
 
+// Per-node iteration counts in ctx->iters (-1: not converged) -> stats.
+// Synchronises the stream.
+static int collect_stats(dgx_ctx *ctx, int64_t count, int maxit, dgx_newton_stats *stats, hipStream_t s) {
+    std::vector<int> h(count);
+    HIPCHK(hipMemcpyAsync(h.data(), ctx->iters.p, count * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int64_t tot = 0, bad = 0, first = -1;
+    int mx = 0;
+    double wsum = 0.0;
+    int64_t nw = 0;
+    for (int64_t i = 0; i < count; i += 64) {
+        int wm = 0;
+        for (int64_t j = i; j < std::min(count, i + 64); ++j) {
+            int it = h[j];
+            if (it < 0) {
+                ++bad;
+                if (first < 0) first = j;
+                it = maxit;
+            }
+            tot += it;
+            mx = std::max(mx, it);
+            wm = std::max(wm, it);
+        }
+        wsum += wm;
+        ++nw;
+    }
+    stats->nodes = count;
+    stats->iters_total = tot;
+    stats->iters_max = mx;
+    stats->iters_wave_max_mean = nw ? wsum / nw : 0.0;
+    stats->nonconverged = bad;
+    stats->first_bad = first;
+    if (bad) return set_err(ctx, DGX_E_NOCONV, std::to_string(bad) + " nodes did not converge");
+    return DGX_OK;
+}
+
 int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double *p, int guess_mode,
                dgx_newton_stats *stats, void *stream) {
     if (!ctx) return DGX_E_INVAL;
@@ -800,37 +839,35 @@ int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double
                            ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, iters, ctx->flags.p);
     if (hipGetLastError() != hipSuccess) return set_err(ctx, DGX_E_DEVICE, "thermo launch failed");
     if (!stats) return DGX_OK;
-    std::vector<int> h(count);
-    HIPCHK(hipMemcpyAsync(h.data(), ctx->iters.p, count * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    int64_t tot = 0, bad = 0, first = -1;
-    int mx = 0;
-    double wsum = 0.0;
-    int64_t nw = 0;
-    for (int64_t i = 0; i < count; i += 64) {
-        int wm = 0;
-        for (int64_t j = i; j < std::min(count, i + 64); ++j) {
-            int it = h[j];
-            if (it < 0) {
-                ++bad;
-                if (first < 0) first = j;
-                it = ctx->cfg.newton_maxit;
-            }
-            tot += it;
-            mx = std::max(mx, it);
-            wm = std::max(wm, it);
-        }
-        wsum += wm;
-        ++nw;
-    }
-    stats->nodes = count;
-    stats->iters_total = tot;
-    stats->iters_max = mx;
-    stats->iters_wave_max_mean = nw ? wsum / nw : 0.0;
-    stats->nonconverged = bad;
-    stats->first_bad = first;
-    if (bad) return set_err(ctx, DGX_E_NOCONV, std::to_string(bad) + " nodes did not converge");
-    return DGX_OK;
+    return collect_stats(ctx, count, ctx->cfg.newton_maxit, stats, s);
+}
+
+int dgx_chem_step(dgx_ctx *ctx, double *u, double dt, double tol, int maxit, dgx_newton_stats *stats,
+                  void *stream) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!is_mix(ctx) || ctx->kin.nr < 1) return set_err(ctx, DGX_E_INVAL, "chemistry needs a mixture with reactions");
+    if (!u) return set_err(ctx, DGX_E_INVAL, "null pointer");
+    if (!(dt >= 0.0) || !(tol > 0.0) || maxit < 1) return set_err(ctx, DGX_E_INVAL, "bad dt, tol or maxit");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t count = (int64_t)ctx->nelem * ctx->nn;
+    if (stats && (rc = dalloc(ctx, ctx->iters, (size_t)count))) return rc;
+    // temperature of the incoming state: the warm start of the inner solves
+    if ((rc = enqueue_thermo_mesh(ctx, u, s))) return set_err(ctx, rc, "thermo launch failed");
+    int *iters = stats ? ctx->iters.p : nullptr;
+    const int tb = 256;
+    const int blocks = (int)((count + tb - 1) / tb);
+    const double ttol = 1e-14;
+    const int tmaxit = 100;
+    if (ctx->cfg.dim == 2)
+        hipLaunchKernelGGL(k_chem<2>, dim3(blocks), dim3(tb), 0, s, u, count, dt, ctx->kin_d.p, ctx->mix, ctx->T.p, tol,
+                           maxit, ttol, tmaxit, iters, ctx->flags.p);
+    else
+        hipLaunchKernelGGL(k_chem<3>, dim3(blocks), dim3(tb), 0, s, u, count, dt, ctx->kin_d.p, ctx->mix, ctx->T.p, tol,
+                           maxit, ttol, tmaxit, iters, ctx->flags.p);
+    if (hipGetLastError() != hipSuccess) return set_err(ctx, DGX_E_DEVICE, "chemistry launch failed");
+    if (!stats) return DGX_OK;
+    return collect_stats(ctx, count, maxit, stats, s);
 }
 
 const double *dgx_last_alpha(const dgx_ctx *ctx) {

@@ -1,0 +1,118 @@
+"""Per-node backward-Euler chemistry on the GPU (dgx_chem_step) against the
+oracle: one step at mild, stiff and near-equilibrium step sizes on the hot
+cylinder state (species densities node by node, conservation of mass and
+atoms, momentum and energy untouched, the temperature left in the library),
+and Strang-split reacting steps: half a chemistry step, one frozen-mixture
+SSPRK3 step with the positivity limiter, half a chemistry step."""
+import numpy as np
+import pytest
+
+from paper_2511_17551_amd import workloads as W
+from oracle.dgsem import Operator
+from oracle.thermo import Mixture
+from oracle.kinetics import Kinetics
+from oracle.chemistry import backward_euler
+from tests.helpers import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+NATOM = np.array([2, 0, 1, 1, 0])
+OATOM = np.array([0, 2, 1, 0, 1])
+
+
+@pytest.fixture(scope="module")
+def dgx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2511_17551_amd import dgx as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def thermo_fns():
+    mix = Mixture(W.Species())
+    return (lambda rs, T: mix.rho_e(rs, T)), (lambda rs, T: mix.rho_cv(rs, T))
+
+
+def frozen_case(thermo_fns, nr, nth):
+    """The hot cylinder state with frozen transport; the reaction table is
+    used by the chemistry step only."""
+    c = W.case_c4(*thermo_fns, nr=nr, nth=nth, hot=True)
+    c.cfg = dict(c.cfg, eq=W.EQ_EULER_MIX)
+    return c
+
+
+def oracle_chem(c, u, dt):
+    sp = c.species
+    mix = Mixture(sp)
+    kin = Kinetics(sp, c.reactions)
+    flat = u.reshape(u.shape[0], -1)
+    rs0 = flat[:5]
+    rho = rs0.sum(0)
+    m = flat[5:7]
+    rhoe = flat[7] - 0.5 * (m * m).sum(0) / rho
+    T0, _ = mix.solve_T(rs0, rhoe, c.cfg["T_guess"])
+    rs, T, it = backward_euler(mix, kin, rs0, rhoe, dt, T0)
+    out = flat.copy()
+    out[:5] = rs
+    return out.reshape(u.shape), T, it
+
+
+@pytest.mark.parametrize("dt", [1e-12, 1e-9, 1e-6])
+def test_chem_step_matches_oracle(dgx, thermo_fns, dt):
+    import torch
+    c = frozen_case(thermo_fns, 8, 16)
+    print("case", c.name, "dt", dt, flush=True)
+    ref, Tref, it = oracle_chem(c, c.u0, dt)
+    s = dgx.Solver(c)
+    u = to_dev(c.u0)
+    st = dgx.dgx_chem_step(s.ctx, u, dt)
+    s.check()
+    got = to_host(u)
+    T = torch.empty(c.u0.shape[1] * c.u0.shape[2], dtype=torch.float64, device="cuda")
+    dgx.dgx_thermo(s.ctx, u, T)
+    Tg = to_host(T)
+    s.close()
+    rho = c.u0[:5].sum(0)
+    err = np.max(np.abs(got[:5] - ref[:5]) / rho[None])
+    moved = np.max(np.abs(ref[:5] - c.u0[:5]) / rho[None])
+    print("chem dt %.0e: max |drho_s|/rho gpu-oracle %.3e, change %.3e, iters gpu max %d mean %.2f, oracle max %d"
+          % (dt, err, moved, st["iters_max"], st["iters_total"] / st["nodes"], it.max()))
+    assert st["nonconverged"] == 0
+    assert err < 1e-11
+    assert moved > 1e-6
+    assert np.array_equal(got[5:], c.u0[5:])
+    assert np.max(np.abs(got[:5].sum(0) - rho) / rho) < 1e-13
+    W_ = c.species.W[:, None, None]
+    for atoms in (NATOM, OATOM):
+        a0 = (atoms[:, None, None] * c.u0[:5] / W_).sum(0)
+        a1 = (atoms[:, None, None] * got[:5] / W_).sum(0)
+        assert np.max(np.abs(a1 - a0) / a0) < 1e-12
+    assert np.all(got[:5] >= 0.0)
+    assert np.max(np.abs(Tg - Tref) / Tref) < 1e-10
+
+
+def test_strang_split_steps(dgx, thermo_fns):
+    from oracle import ssprk
+    from oracle.positivity import limit
+    c = frozen_case(thermo_fns, 8, 16)
+    print("case", c.name, "strang 3 steps", flush=True)
+    op = Operator(c.cfg, c.mesh, species=c.species)
+    wq = np.outer(op.b.w, op.b.w).reshape(-1)
+    lim = lambda v: limit(v, op.J, wq, 2, c.species.e0)[0]
+    s = dgx.Solver(c)
+    u = to_dev(c.u0)
+    dt = dgx.dgx_max_dt(s.ctx, u, 0.3)
+    ref = c.u0
+    for _ in range(3):
+        ref = oracle_chem(c, ref, 0.5 * dt)[0]
+        ref, _ = ssprk.run(lambda v, t: op.rhs(v, t), ref, 0.0, dt, 1, limiter=lim)
+        ref = oracle_chem(c, ref, 0.5 * dt)[0]
+        dgx.dgx_chem_step(s.ctx, u, 0.5 * dt)
+        s.ssprk3(u, dt, 1)
+        dgx.dgx_chem_step(s.ctx, u, 0.5 * dt)
+    s.check()
+    got = to_host(u)
+    s.close()
+    print("strang 3 steps dt %.3e rel err %.3e, species change %.3e"
+          % (dt, rel_err(got, ref), np.abs(ref[:5] - c.u0[:5]).max() / c.u0[:5].sum(0).max()))
+    assert rel_err(got, ref) < 1e-9
