@@ -12,6 +12,7 @@ Prints one JSON line (see the keys below).  The oracle (NumPy, one thread)
 is timed on the same 32^3 state for the cpu_baseline entry.
 """
 import argparse
+import hashlib
 import json
 
 import numpy as np
@@ -72,12 +73,41 @@ def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_rhs_traffic.json")
+
+
+def kernel_source_hash():
+    """SHA-1 of the sources the right-hand-side kernel is compiled from."""
+    h = hashlib.sha1()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_17551_amd", "csrc")
+    for f in ("k_rhs.h", "physics.h", "dgx_internal.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per k_rhs launch (FETCH_SIZE + WRITE_SIZE per dispatch, each
+    divided by its copy-kernel calibration factor) from the committed counter
+    summary, or None when it was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha1") != kernel_source_hash():
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=6, reps=5):
     """Per-node T(e): surrogate-guided vs plain Newton on solver-generated states.
 
-    States: a frozen-chemistry run of the Mach-8 cylinder O-grid (64 x 128,
-    N = 3, positivity limiter, CFL 0.2), snapshots every 20 SSPRK3 steps ->
-    16 x 131072 = 2,097,152 states.  Labels: the plain solve's converged T.
+    States: a reacting run of the Mach-8 cylinder O-grid (64 x 128, N = 3,
+    positivity limiter, CFL 0.2), each step Strang-split into half a
+    backward-Euler chemistry step, one frozen-mixture SSPRK3 step and half a
+    chemistry step; snapshots every 20 steps -> 16 x 131072 = 2,097,152
+    states.  Labels: the plain solve's converged T.  The chemistry step itself
+    is timed on the last state.
     The surrogate is trained on the same set (Adam, batch 4096), then both
     solves are timed (HIP events, same stream, same 1e-10 tolerance).
     """
@@ -87,14 +117,35 @@ def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=6, reps=5)
     c = W.case_c4(energy, cv)
     dgx.dgx_destroy(pctx)
     c.cfg["eq"] = W.EQ_EULER_MIX
-    c.reactions = None
     s = dgx.Solver(c)
     u = torch.from_numpy(c.u0).to("cuda")
     dt = dgx.dgx_max_dt(s.ctx, u, 0.2)
     snaps = []
     for _ in range(snapshots):
-        s.ssprk3(u, dt, steps_per_snap)
+        for _ in range(steps_per_snap):
+            dgx.dgx_chem_step(s.ctx, u, 0.5 * dt, stats=False)
+            s.ssprk3(u, dt, 1)
+            dgx.dgx_chem_step(s.ctx, u, 0.5 * dt, stats=False)
         snaps.append(u.reshape(u.shape[0], -1).clone())
+    s.check()
+    # the chemistry step on the last state (copies, so the state set stays put)
+    uc = u.clone()
+    chem_stats = dgx.dgx_chem_step(s.ctx, uc, 0.5 * dt)
+    e0, e1 = _events(torch)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        uc.copy_(u)
+        dgx.dgx_chem_step(s.ctx, uc, 0.5 * dt, stats=False)
+    e1.record()
+    torch.cuda.synchronize()
+    chem_ms = e0.elapsed_time(e1) / reps
+    e0.record()
+    for _ in range(reps):
+        uc.copy_(u)
+    e1.record()
+    torch.cuda.synchronize()
+    chem_ms -= e0.elapsed_time(e1) / reps
     s.check()
     states = torch.cat(snaps, 1).contiguous()
     del snaps
@@ -109,7 +160,6 @@ def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=6, reps=5)
     st_sur = dgx.dgx_thermo(s.ctx, states, Ts, nstates=n, guess=dgx.GUESS_SURROGATE)
     maxrel = float(((Ts - T).abs() / T).max())
     Tg = torch.empty_like(T)
-    e0, e1 = _events(torch)
     res = {}
     for name, guess in (("plain", dgx.GUESS_FREESTREAM), ("surrogate", dgx.GUESS_SURROGATE)):
         dgx.dgx_thermo(s.ctx, states, Ts, nstates=n, guess=guess, stats=False)
@@ -163,7 +213,11 @@ def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=6, reps=5)
                                wave_max_mean_plain=round(sp_sub["iters_wave_max_mean"], 3),
                                wave_max_mean_surrogate=round(ss_sub["iters_wave_max_mean"], 3)),
                 train_epochs=epochs, train_s=round(train_s, 2), loss_first=float(losses[0]),
-                loss_last=float(losses[-1]), tol=1e-10)
+                loss_last=float(losses[-1]), tol=1e-10,
+                chemistry=dict(nodes=int(chem_stats["nodes"]), dt=0.5 * dt, ms=round(chem_ms, 4),
+                               iters_mean=round(chem_stats["iters_total"] / chem_stats["nodes"], 3),
+                               iters_max=int(chem_stats["iters_max"]),
+                               wave_max_mean=round(chem_stats["iters_wave_max_mean"], 3)))
 
 
 def batch_leg(torch, W, dgx, reps=10):
@@ -229,7 +283,7 @@ def main():
     ap.add_argument("--no-thermo", action="store_true", help="skip the surrogate vs plain T(e) leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched AMR + cases leg")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain 84 MB device copy (counter calibration)")
+                    help="also run a plain 1 GiB read + 1 GiB write kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
@@ -248,11 +302,14 @@ def main():
     dt = dgx.dgx_max_dt(solver.ctx, u, 0.5)
     epb, tune_ms = dgx.dgx_autotune(solver.ctx, u, reps=10)
     if args.copy_probe:
-        tmp = torch.empty_like(u)
+        # counter calibration: an elementwise kernel that reads and writes
+        # 1 GiB each (larger than the 256 MB Infinity Cache), five times
+        cx = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        cy = torch.empty_like(cx)
         for _ in range(5):
-            tmp.copy_(u)
+            torch.mul(cx, 1.0, out=cy)
         torch.cuda.synchronize()
-        del tmp
+        del cx, cy
     solver.ssprk3(u, dt, max(args.warmup, 1))
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -277,7 +334,7 @@ def main():
     gb = grad_bytes_per_launch(nelem, nn, nvar, 3, 4)
     achieved = rb / (k_rhs_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(),
                 kernel="k_rhs", kernel_ms=round(k_rhs_ms, 5), bytes_per_launch=rb,
                 other_kernels={k: round(v, 5) for k, v in kt.items() if k != "k_rhs"},
                 k_grad_GBs=round(gb / (kt.get("k_grad", float("nan")) * 1e-3) / 1e9, 1))

@@ -38,7 +38,9 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
     constexpr int NV = DIM + 2;
     constexpr int GA = DIM * DIM + 1;
     extern __shared__ double smem[];
+    __shared__ double sD[N1 * N1];  // read with per-lane indices
     const int tid = threadIdx.x;
+    if (tid < N1 * N1) sD[tid] = P.B.D[tid];
     const int NT = P.epb * NN;
     const int e0 = blockIdx.x * P.epb;
     const int nloc = min(P.epb, P.nelem - e0);
@@ -134,7 +136,7 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
             for (int w = 0; w < NW; ++w) dW[w] = 0.0;
 #pragma unroll
             for (int j = 0; j < N1; ++j) {
-                const double Dj = P.B.D[a * N1 + j];
+                const double Dj = sD[a * N1 + j];
                 const int nj = line_node<N1, DIM>(d, j, l);
 #pragma unroll
                 for (int w = 0; w < NW; ++w) dW[w] = fma(Dj, sw[w * NN + nj], dW[w]);
@@ -204,7 +206,7 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
             const int l = node_line<N1, DIM>(node, d);
 #pragma unroll
             for (int j = 0; j < N1; ++j) {
-                const double Dj = P.B.D[a * N1 + j];
+                const double Dj = sD[a * N1 + j];
                 const int nj = line_node<N1, DIM>(d, j, l);
 #pragma unroll
                 for (int k = 0; k < NW; ++k) vis[k] = fma(Dj, sw[k * NN + nj], vis[k]);
@@ -499,7 +501,7 @@ __global__ void k_maxrate(RhsParams P, unsigned long long *out) {
             double n[DIM];
             for (int c = 0; c < DIM; ++c)
                 n[c] = CURV ? P.geo[(d * DIM + c) * stride + i] : P.geo[(size_t)e * GA + d * DIM + c];
-            rate += fabs(dotn<DIM>(s.v, n)) + s.c * sqrt(dotn<DIM>(n, n));
+            rate += fabs(dotn<DIM>(s.v, n)) + s.c * wave_sqrt(dotn<DIM>(n, n));
         }
         rate /= fabs(J);
     }

@@ -150,7 +150,7 @@ __device__ __forceinline__ void lds_state(const double *su, const double *sq, in
     } else {
         // perfect gas: recomputed (one LDS array less keeps five 4-element
         // workgroups per CU); bitwise equal to the value make_state gives
-        s.c = sqrt(gamma * s.p * rcp(s.rho));
+        s.c = wave_sqrt(gamma * s.p * rcp(s.rho));
         s.rs[0] = 0.0;
     }
 }
@@ -166,8 +166,14 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     constexpr int OFF_G = S::SU + NQ * NN;        // element geometry within a slot
     constexpr int OFF_B = OFF_G + S::GEO + S::GEOA;
     extern __shared__ double smem[];
+    // 2 D (pair-flux coefficients) and the LGL weights: read with per-lane
+    // indices, so they live in LDS rather than in the kernel arguments
+    __shared__ double sDc[N1 * N1];
+    __shared__ double sW[N1];
 
     const int tid = threadIdx.x;
+    if (tid < N1 * N1) sDc[tid] = 2.0 * P.B.D[tid];
+    if (tid < N1) sW[tid] = P.B.w[tid];
     const int NT = P.epb * NN;  // threads that own a node
     const int e0 = blockIdx.x * P.epb;
     const int nloc = min(P.epb, P.nelem - e0);
@@ -186,8 +192,9 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     const double gamma = P.gamma;
 
     // Work items (face nodes, volume pairs) of all elements of the workgroup
-    // are spread over all its threads.  The face phase's neighbour indices
-    // are fetched first so that their latency overlaps the staging.
+    // are spread over all its threads.  The face phase's neighbour indices,
+    // and then the neighbour data of its conforming faces, are fetched first
+    // so that their latency overlaps the staging.
     constexpr int RF = (NSF + NN - 1) / NN;
     const Spread spf = spread_phase(tid, NT, P.epb * NSF, 0);
     int cursor = spf.cursor;
@@ -202,6 +209,48 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
         }
     }
 
+    double une[RF][NV];   // neighbour state at the face node
+    double ftr[RF][NW];   // neighbour's contravariant viscous face flux (BR1)
+    double nrr[RF][DIM];  // xi_d = -1 faces: the neighbour's normal
+    double Tr[RF];        // neighbour temperature (mixtures)
+    // the first round's neighbour data is loaded before the staging, later
+    // rounds' right before use (register pressure)
+    auto load_nbr = [&](int r) {
+        const int it = r * NT + spf.t;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) une[r][v] = 1.0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) ftr[r][k] = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) nrr[r][c] = 0.0;
+        Tr[r] = 1.0;
+        const int nb = nbf[r];
+        if (tid < NT && it < nloc * NSF && nb >= 0) {
+            const int ei = it / NSF;
+            const int f = (it - ei * NSF) / NF;
+            const int q = it - ei * NSF - f * NF;
+            const int d = f >> 1, side = f & 1;
+            const size_t gj = (size_t)nb * NN + line_node<N1, DIM>(d, side ? 0 : N, q);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) une[r][v] = P.u[v * stride + gj];
+            if constexpr (EQ == 1) {
+                const double *fn = P.grad + ((size_t)nb * 2 * DIM + (f ^ 1)) * NW * NF + q;
+#pragma unroll
+                for (int k = 0; k < NW; ++k) ftr[r][k] = fn[k * NF];
+            }
+            if constexpr (MIX) Tr[r] = P.T[gj];
+            if (side == 0) {
+                if constexpr (CURV) {
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) nrr[r][c] = P.geo[(d * DIM + c) * stride + gj];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) nrr[r][c] = P.geo[(size_t)nb * GA + d * DIM + c];
+                }
+            }
+        }
+    };
+
     // ---- stage the element: primitives (+ species, metric terms)
     {
         double uo[NV];
@@ -209,6 +258,9 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
         if (valid) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) uo[v] = P.u[v * stride + gi];
+        }
+        load_nbr(0);
+        if (valid) {
             if constexpr (CURV) {
 #pragma unroll
                 for (int k = 0; k < DIM * DIM; ++k) sJa[k * NN + node] = P.geo[k * stride + gi];
@@ -256,6 +308,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     {
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
+            if (r > 0) load_nbr(r);
             const int it = r * NT + spf.t;
             if (tid < NT && it < nloc * NSF) {
                 const int ei = it / NSF;
@@ -313,30 +366,11 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                     for (int v = 0; v < NV; ++v) ebuf[v * NSF + fi] = F[v];
                     continue;
                 }
-                double ftn[NW];  // neighbour's contravariant viscous face flux (BR1)
-#pragma unroll
-                for (int k = 0; k < NW; ++k) ftn[k] = 0.0;
                 if (nb >= 0) {
-                    const int nbn = line_node<N1, DIM>(d, side ? 0 : N, q);
-                    const size_t gj = (size_t)nb * NN + nbn;
-                    double ue[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) ue[v] = P.u[v * stride + gj];
-                    if constexpr (EQ == 1) {
-                        const double *fn = P.grad + ((size_t)nb * 2 * DIM + (f ^ 1)) * NW * NF + q;
-#pragma unroll
-                        for (int k = 0; k < NW; ++k) ftn[k] = fn[k * NF];
-                    }
-                    const double Te = MIX ? P.T[gj] : 0.0;
-                    make_state<DIM, MIX>(ue, Te, gamma, P.M, ext);
+                    make_state<DIM, MIX>(une[r], MIX ? Tr[r] : 0.0, gamma, P.M, ext);
                     if (side == 0) {
-                        if constexpr (CURV) {
 #pragma unroll
-                            for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(d * DIM + c) * stride + gj];
-                        } else {
-#pragma unroll
-                            for (int c = 0; c < DIM; ++c) nrm[c] = P.geo[(size_t)nb * GA + d * DIM + c];
-                        }
+                        for (int c = 0; c < DIM; ++c) nrm[c] = nrr[r][c];
                     }
                 } else {
                     const int bc = -1 - nb;
@@ -370,7 +404,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                     // with the inviscid flux (F* - F_v/2 on the momentum and
                     // energy rows; periodic meshes only, so nb >= 0 here).
 #pragma unroll
-                    for (int k = 0; k < NW; ++k) F[1 + k] -= 0.5 * ftn[k];
+                    for (int k = 0; k < NW; ++k) F[1 + k] -= 0.5 * ftr[r][k];
                 }
 #pragma unroll
                 for (int v = 0; v < NV; ++v) ebuf[v * NSF + fi] = F[v];
@@ -451,10 +485,12 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
             const int a = node_pos<N1>(node, d);
             const int l = node_line<N1, DIM>(node, d);
 #pragma unroll
-            for (int b = 0; b < N1; ++b) {
-                if (b == a) continue;
-                const int k = l * NPL + (a < b ? pair_index<N1>(a, b) : pair_index<N1>(b, a));
-                const double coef = 2.0 * P.B.D[a * N1 + b];
+            for (int j = 1; j < N1; ++j) {
+                // the other nodes b != a of the line, without branches
+                const int b = a + j - (a + j >= N1 ? N1 : 0);
+                const int lo = a < b ? a : b, hi = a < b ? b : a;
+                const int k = l * NPL + pair_index<N1>(lo, hi);
+                const double coef = sDc[a * N1 + b];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) dg[v] = fma(coef, buf[v * PD + k], dg[v]);
             }
@@ -463,7 +499,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     }
     // ---- first-order subcell finite volumes (elements with alpha > 0)
     const double alpha = (P.alpha != nullptr && valid) ? P.alpha[e] : 0.0;
-    if (__syncthreads_or(alpha > 0.0)) {
+    if (P.alpha != nullptr && __syncthreads_or(alpha > 0.0)) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
 #pragma unroll
@@ -496,7 +532,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
             if (valid && alpha > 0.0) {
                 const int a = node_pos<N1>(node, d);
                 const int l = node_line<N1, DIM>(node, d);
-                const double aw = alpha / P.B.w[a];
+                const double aw = alpha / sW[a];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     const double hi = a < N ? buf[v * NFV + l * N + a] : 0.0;
