@@ -269,9 +269,10 @@ int dgx_check(dgx_ctx *ctx, void *stream);
 int dgx_species_energy(const dgx_ctx *ctx, double T, double *e, double *cv);
 
 /* Kernel timing for profiling: enqueue `reps` evaluations of the
- * right-hand side in the fused stage form used by dgx_ssprk3_step
- * (out = 3/4 u + 1/4 (u + dt du), into library scratch; u is not modified),
- * bracketing every kernel with HIP events on `stream`.  ms_out[k] receives
+ * right-hand side in the fused form of the second SSPRK3 stage
+ * (out = 3/4 u0 + 1/4 (u + dt du), u0 a library copy of u in its own
+ * buffer, out into library scratch; u is not modified), bracketing every
+ * kernel with HIP events on `stream`.  ms_out[k] receives
  * the average duration of kernel k in launch order, names_out (may be NULL)
  * a comma-separated list of the kernel names (buffer of names_len bytes);
  * *nk the number of kernels (<= 8).  Synchronises. */

@@ -430,6 +430,58 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     }
     __syncthreads();
 
+    // ---- first-order subcell finite volumes (elements with alpha > 0)
+    const double alpha = (P.alpha != nullptr && valid) ? P.alpha[e] : 0.0;
+    if (P.alpha != nullptr && __syncthreads_or(alpha > 0.0)) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+            for (int r = 0; r < (NFV + NN - 1) / NN; ++r) {
+                const int p = r * NN + node;
+                if (valid && alpha > 0.0 && p < NFV) {
+                    const int l = p / N;
+                    const int m = p - l * N + 1;
+                    const int nL = line_node<N1, DIM>(d, m - 1, l);
+                    const int nR = line_node<N1, DIM>(d, m, l);
+                    double nrm[DIM];
+                    if constexpr (CURV) {
+                        const double *ns = P.nsub + ((((size_t)e * DIM + d) * NF + l) * N + (m - 1)) * DIM;
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) nrm[c] = ns[c];
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) nrm[c] = sJa[d * DIM + c];
+                    }
+                    St<DIM, MIX> A, B;
+                    lds_state<DIM, MIX>(su, sq, NN, nL, gamma, A);
+                    lds_state<DIM, MIX>(su, sq, NN, nR, gamma, B);
+                    double F[NV];
+                    rusanov<DIM, MIX>(A, B, nrm, F);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) buf[v * NFV + p] = F[v];
+                }
+            }
+            __syncthreads();
+            if (valid && alpha > 0.0) {
+                const int a = node_pos<N1>(node, d);
+                const int l = node_line<N1, DIM>(node, d);
+                const double aw = alpha / sW[a];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double hi = a < N ? buf[v * NFV + l * N + a] : 0.0;
+                    const double lo = a > 0 ? buf[v * NFV + l * N + a - 1] : 0.0;
+                    acc[v] = fma(aw, hi - lo, acc[v]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // the epilogue's own-node loads (u, u0 of the stage form, the local
+    // viscous part) are issued before the last gather, once the pair fluxes
+    // no longer hold registers, so that their latency overlaps it
+    double eu[NV], eu0[NV], evp[NW];
+
     // ---- high-order volume term: symmetric two-point fluxes along lines
     double dg[NV];
 #pragma unroll
@@ -480,6 +532,17 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                 for (int v = 0; v < NV; ++v) ebuf[v * PD + p] = F[v];
             }
         }
+        if (d == DIM - 1) {
+            const bool st = valid && mode != 0;
+            const bool s0 = st && P.sa != 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                eu[v] = st ? P.u[v * stride + gi] : 0.0;
+                eu0[v] = s0 ? P.u0[v * stride + gi] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < NW; ++k) evp[k] = (EQ == 1 && valid) ? P.vpart[(size_t)k * stride + gi] : 0.0;
+        }
         __syncthreads();
         if (valid) {
             const int a = node_pos<N1>(node, d);
@@ -497,53 +560,6 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
         }
         __syncthreads();
     }
-    // ---- first-order subcell finite volumes (elements with alpha > 0)
-    const double alpha = (P.alpha != nullptr && valid) ? P.alpha[e] : 0.0;
-    if (P.alpha != nullptr && __syncthreads_or(alpha > 0.0)) {
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-#pragma unroll
-            for (int r = 0; r < (NFV + NN - 1) / NN; ++r) {
-                const int p = r * NN + node;
-                if (valid && alpha > 0.0 && p < NFV) {
-                    const int l = p / N;
-                    const int m = p - l * N + 1;
-                    const int nL = line_node<N1, DIM>(d, m - 1, l);
-                    const int nR = line_node<N1, DIM>(d, m, l);
-                    double nrm[DIM];
-                    if constexpr (CURV) {
-                        const double *ns = P.nsub + ((((size_t)e * DIM + d) * NF + l) * N + (m - 1)) * DIM;
-#pragma unroll
-                        for (int c = 0; c < DIM; ++c) nrm[c] = ns[c];
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < DIM; ++c) nrm[c] = sJa[d * DIM + c];
-                    }
-                    St<DIM, MIX> A, B;
-                    lds_state<DIM, MIX>(su, sq, NN, nL, gamma, A);
-                    lds_state<DIM, MIX>(su, sq, NN, nR, gamma, B);
-                    double F[NV];
-                    rusanov<DIM, MIX>(A, B, nrm, F);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) buf[v * NFV + p] = F[v];
-                }
-            }
-            __syncthreads();
-            if (valid && alpha > 0.0) {
-                const int a = node_pos<N1>(node, d);
-                const int l = node_line<N1, DIM>(node, d);
-                const double aw = alpha / sW[a];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const double hi = a < N ? buf[v * NFV + l * N + a] : 0.0;
-                    const double lo = a > 0 ? buf[v * NFV + l * N + a - 1] : 0.0;
-                    acc[v] = fma(aw, hi - lo, acc[v]);
-                }
-            }
-            __syncthreads();
-        }
-    }
-
     const double Jn = CURV ? (valid ? sJ[node] : 1.0) : Jel;
     const double iJ = 1.0 / Jn;
     double du[NV];
@@ -557,7 +573,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     if constexpr (EQ == 1) {
         if (valid) {
 #pragma unroll
-            for (int k = 0; k < NW; ++k) du[1 + k] += P.vpart[(size_t)k * stride + gi];
+            for (int k = 0; k < NW; ++k) du[1 + k] += evp[k];
         }
     }
 
@@ -608,9 +624,8 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double us = P.u[v * stride + gi];
-                const double base = P.sa != 0.0 ? P.sa * P.u0[v * stride + gi] : 0.0;
-                P.out[v * stride + gi] = base + P.sb * (us + P.dt * du[v]);
+                const double base = P.sa != 0.0 ? P.sa * eu0[v] : 0.0;
+                P.out[v * stride + gi] = base + P.sb * (eu[v] + P.dt * du[v]);
             }
         }
     }
