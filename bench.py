@@ -285,6 +285,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-thermo", action="store_true", help="skip the surrogate vs plain T(e) leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched AMR + cases leg")
+    ap.add_argument("--epb", type=int, default=0,
+                    help="elements per workgroup to use instead of autotuning (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write kernel (counter calibration)")
     args = ap.parse_args()
@@ -303,14 +305,20 @@ def main():
     solver = dgx.Solver(case)
     u = torch.from_numpy(case.u0).to("cuda")
     dt = dgx.dgx_max_dt(solver.ctx, u, 0.5)
-    epb, tune_ms = dgx.dgx_autotune(solver.ctx, u, reps=10)
+    if args.epb > 0:
+        dgx.dgx_set_launch(solver.ctx, args.epb)
+        epb, tune_ms = args.epb, {}
+    else:
+        epb, tune_ms = dgx.dgx_autotune(solver.ctx, u, reps=10)
     if args.copy_probe:
-        # counter calibration: an elementwise kernel that reads and writes
-        # 1 GiB each (larger than the 256 MB Infinity Cache), five times
+        # counter calibration: kernels of known traffic on 1 GiB buffers
+        # (larger than the 256 MB Infinity Cache)
         cx = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         cy = torch.empty_like(cx)
-        for _ in range(5):
-            torch.mul(cx, 1.0, out=cy)
+        for _ in range(3):
+            torch.mul(cx, 1.0, out=cy)   # elementwise kernel
+            cy.copy_(cx)                 # runtime copy kernel
+            cx.sum()                     # reduction (reads only)
         torch.cuda.synchronize()
         del cx, cy
     solver.ssprk3(u, dt, max(args.warmup, 1))
