@@ -94,6 +94,17 @@ __device__ __forceinline__ Spread spread_phase(int tid, int NT, int K_per_block,
     return {t, next};
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin (block b to XCD b mod 8),
+// and each XCD has its own L2.  This renumbering gives every XCD one
+// contiguous range of element groups, so that face neighbours (in particular
+// the neighbours of a group's end elements) are staged under the same L2.
+// A bijection of [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int X = 8;
+    const int q = nb / X, r = nb - q * X, x = b % X, i = b / X;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 template <int DIM, int N, int EQ, int VF, bool CURV>
 struct RhsShape {
     static constexpr int N1 = N + 1;
@@ -175,7 +186,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     if (tid < N1 * N1) sDc[tid] = 2.0 * P.B.D[tid];
     if (tid < N1) sW[tid] = P.B.w[tid];
     const int NT = P.epb * NN;  // threads that own a node
-    const int e0 = blockIdx.x * P.epb;
+    const int e0 = xcd_block(blockIdx.x, gridDim.x) * P.epb;
     const int nloc = min(P.epb, P.nelem - e0);
     int el = tid / NN;
     const int node = tid - el * NN;
