@@ -223,6 +223,58 @@ def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=6, reps=5)
                                wave_max_mean=round(chem_stats["iters_wave_max_mean"], 3)))
 
 
+def c3_bytes_per_launch(nelem, nn, nvar, dim, stage_base=True):
+    """Algorithmic HBM bytes of one fused k_rhs launch on curved mixture
+    elements: per node the state (nvar) and its temperature read, the stage
+    base u0 (nvar) read, the next stage (nvar) written, the nodal metric terms
+    Ja (dim x dim) and J read; per element the blending factor and 2*dim int32
+    neighbour indices.  (Subcell normals, read by shocked elements only, are
+    not counted.)"""
+    per_node = nvar + 1 + (nvar if stage_base else 0) + nvar + dim * dim + 1
+    return nelem * nn * per_node * 8 + nelem * (8 + 2 * dim * 4)
+
+
+def c3_leg(torch, W, dgx, reps=20):
+    """The curvilinear 24^3 N = 4 frozen 5-species Mach-3 shock case:
+    back-to-back right-hand sides on the shock state (each: T(e) Newton per
+    node, modal indicator, fused RHS with subcell FV in the shocked elements),
+    GDOF-RHS/s and the k_rhs roofline of its stage-form launch."""
+    probe = W.case_c4(lambda rs, T: 0 * T, lambda rs, T: 1 + 0 * T, nr=4, nth=8)
+    pctx = dgx.dgx_create(probe.cfg, probe.species, probe.reactions)
+    energy, cv = dgx.mixture_energy_fns(pctx)
+    c = W.case_c3(energy, cv)
+    dgx.dgx_destroy(pctx)   # the energy functions use it: only after the case is built
+    nvar, nelem, nn = c.u0.shape
+    s = dgx.Solver(c)
+    u = torch.from_numpy(c.u0).to("cuda")
+    du = torch.empty_like(u)
+    epb, tune = dgx.dgx_autotune(s.ctx, u, reps=5)
+    for _ in range(2):
+        dgx.dgx_rhs(s.ctx, u, 0.0, du)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        dgx.dgx_rhs(s.ctx, u, 0.0, du)
+    e1.record()
+    torch.cuda.synchronize()
+    s.check()
+    ms_rhs = e0.elapsed_time(e1) / reps
+    alpha = dgx.dgx_last_alpha(s.ctx, nelem)
+    shocked = int((alpha > 0).sum()) if alpha is not None else 0
+    kt = dgx.dgx_kernel_times(s.ctx, u, reps=10)
+    s.close()
+    rb = c3_bytes_per_launch(nelem, nn, nvar, 3)
+    k_ms = kt["k_rhs"]
+    achieved = rb / (k_ms * 1e-3) / 1e9
+    return dict(workload="curved24_N4_air5_mach3_shock_rhs", elements=nelem, N=4, nodes=nelem * nn,
+                dof=int(c.u0.size), value=round(c.u0.size / (ms_rhs * 1e-3) / 1e9, 3),
+                unit="GDOF-RHS/s", ms_per_rhs=round(ms_rhs, 5), elements_per_workgroup=epb,
+                shocked_elements=shocked, kernel_ms={k: round(v, 5) for k, v in kt.items()},
+                roofline=dict(bound="hbm", kernel="k_rhs", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                              unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), bytes_per_launch=rb))
+
+
 def batch_leg(torch, W, dgx, reps=10):
     """The AMR density wave + 16 vortex-tube cases: one launch per stage for
     everything vs one context / launch sequence per case."""
@@ -283,6 +335,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the curved N=4 mixture shock leg")
     ap.add_argument("--no-thermo", action="store_true", help="skip the surrogate vs plain T(e) leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched AMR + cases leg")
     ap.add_argument("--epb", type=int, default=0,
@@ -364,6 +417,8 @@ def main():
         out["thermo"] = thermo_leg(torch, W, dgx)
     if not args.no_batch:
         out["batch"] = batch_leg(torch, W, dgx)
+    if not args.no_c3:
+        out["c3"] = c3_leg(torch, W, dgx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out))

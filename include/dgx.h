@@ -114,7 +114,10 @@ typedef struct dgx_config {
     double force_alpha;    /* >= 0: use this alpha everywhere (testing) */
     double newton_tol;     /* relative step tolerance of T(e) */
     int newton_maxit;
-    double T_guess;        /* freestream guess of T(e) */
+    double T_guess;        /* freestream guess of T(e); the right-hand side's
+                              per-node solves start from the node's previous
+                              temperature (T_guess before the first solve, and
+                              again if Newton fails from it) */
     int positivity;        /* 1 = Zhang-Shu positivity limiter after every SSPRK3 stage */
     const dgx_species *species;      /* mixture equations, else NULL */
     const dgx_reactions *reactions;  /* DGX_EQ_REACT_MIX, else NULL  */

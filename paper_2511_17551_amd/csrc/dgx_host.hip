@@ -253,11 +253,11 @@ int enqueue_thermo_mesh(dgx_ctx *ctx, const double *u, hipStream_t s) {
     if (ctx->cfg.dim == 2)
         hipLaunchKernelGGL(k_thermo<2>, dim3(blocks), dim3(th), 0, s, u, count, (const double *)nullptr,
                            ctx->cfg.T_guess, ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, ctx->T.p,
-                           (double *)nullptr, (int *)nullptr, ctx->flags.p);
+                           (double *)nullptr, (int *)nullptr, ctx->flags.p, 1);
     else
         hipLaunchKernelGGL(k_thermo<3>, dim3(blocks), dim3(th), 0, s, u, count, (const double *)nullptr,
                            ctx->cfg.T_guess, ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, ctx->T.p,
-                           (double *)nullptr, (int *)nullptr, ctx->flags.p);
+                           (double *)nullptr, (int *)nullptr, ctx->flags.p, 1);
     return hipGetLastError() == hipSuccess ? DGX_OK : DGX_E_DEVICE;
 }
 
@@ -296,7 +296,7 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
         const IndEntry *ie = find_ind(ctx);
         if (!ie) return set_err(ctx, DGX_E_INVAL, "no indicator kernel for this configuration");
         ie->fn(P, c.ind_var, c.alpha_max, c.alpha_min, ctx->alpha.p, ctx->alpha_raw.p, blocks, th,
-               (size_t)epb * 2 * ctx->nn * sizeof(double), s);
+               (size_t)epb * 3 * ctx->nn * sizeof(double), s);
         if (c.alpha_smooth) {
             const int tb = 256;
             if (c.dim == 2)
@@ -652,7 +652,13 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         HIPCHK(hipMemcpy(ctx->bc_T.p, bT.data(), m->nbc * sizeof(double), hipMemcpyHostToDevice));
     }
     // scratch
-    if (is_mix(ctx) && (rc = dalloc(ctx, ctx->T, (size_t)E * nn))) return rc;
+    if (is_mix(ctx)) {
+        // per-node temperature, the warm start of the right-hand side's
+        // T(e) solves: the freestream guess until the first solve
+        if ((rc = dalloc(ctx, ctx->T, (size_t)E * nn))) return rc;
+        std::vector<double> t0((size_t)E * nn, ctx->cfg.T_guess);
+        HIPCHK(hipMemcpy(ctx->T.p, t0.data(), t0.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     if ((rc = dalloc(ctx, ctx->alpha, E))) return rc;
     if ((rc = dalloc(ctx, ctx->alpha_tmp, E))) return rc;
     if ((rc = dalloc(ctx, ctx->alpha_raw, E))) return rc;
@@ -833,10 +839,10 @@ int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double
     const int blocks = (int)((count + tb - 1) / tb);
     if (ctx->cfg.dim == 2)
         hipLaunchKernelGGL(k_thermo<2>, dim3(blocks), dim3(tb), 0, s, u, count, tg, ctx->cfg.T_guess,
-                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, iters, ctx->flags.p);
+                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, iters, ctx->flags.p, 0);
     else
         hipLaunchKernelGGL(k_thermo<3>, dim3(blocks), dim3(tb), 0, s, u, count, tg, ctx->cfg.T_guess,
-                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, iters, ctx->flags.p);
+                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, iters, ctx->flags.p, 0);
     if (hipGetLastError() != hipSuccess) return set_err(ctx, DGX_E_DEVICE, "thermo launch failed");
     if (!stats) return DGX_OK;
     return collect_stats(ctx, count, ctx->cfg.newton_maxit, stats, s);

@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(256) k_thermo(const double *__restrict__ u, in
                                                 const double *__restrict__ Tguess, double T0,
                                                 double tol, int maxit, MixC M, double *__restrict__ T,
                                                 double *__restrict__ pout, int *__restrict__ iters,
-                                                unsigned *flags) {
+                                                unsigned *flags, int warm) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     double rs[kNS];
@@ -253,9 +253,15 @@ __global__ void __launch_bounds__(256) k_thermo(const double *__restrict__ u, in
         m2 = fma(m, m, m2);
     }
     const double rhoe = u[(kNS + DIM) * count + i] - 0.5 * m2 / rho;
-    double t = Tguess ? Tguess[i] : T0;
+    // guess: the given one, or with warm != 0 the node's previous T (the
+    // right-hand side's solves), else T0; a failed warm start retries from T0
+    double t = Tguess ? Tguess[i] : (warm ? T[i] : T0);
     if (!(t > 0.0) || !isfinite(t)) t = T0;
-    const int it = mix_newton(M, rs, rhoe, t, tol, maxit);
+    int it = mix_newton(M, rs, rhoe, t, tol, maxit);
+    if (warm && (it < 0 || !isfinite(t) || !(t > 0.0))) {
+        t = T0;
+        it = mix_newton(M, rs, rhoe, t, tol, maxit);
+    }
     T[i] = t;
     if (pout) pout[i] = mix_rR(M, rs) * t;
     if (iters) iters[i] = it;
@@ -273,14 +279,17 @@ __global__ void __launch_bounds__(512) k_indicator(RhsParams P, int ind_var, dou
     constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
     constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
     extern __shared__ double smem[];
+    __shared__ double sV[N1 * N1];  // V^-1, read with per-lane indices
     const int tid = threadIdx.x;
+    if (tid < N1 * N1) sV[tid] = P.B.Vinv[tid];
     int el = tid / NN;
     const int node = tid - el * NN;
     const int e = blockIdx.x * P.epb + el;
     const bool valid = (el < P.epb) && (e < P.nelem);
     if (el >= P.epb) el = 0;
-    double *x = smem + el * 2 * NN;
+    double *x = smem + el * 3 * NN;
     double *y = x + NN;
+    double *z = y + NN;
     const size_t stride = (size_t)P.nelem * NN;
     const size_t gi = (size_t)(valid ? e : 0) * NN + node;
     if (valid) {
@@ -299,29 +308,36 @@ __global__ void __launch_bounds__(512) k_indicator(RhsParams P, int ind_var, dou
             const int a = node_pos<N1>(node, d);
             const int l = node_line<N1, DIM>(node, d);
 #pragma unroll
-            for (int j = 0; j < N1; ++j) m = fma(P.B.Vinv[a * N1 + j], x[line_node<N1, DIM>(d, j, l)], m);
+            for (int j = 0; j < N1; ++j) m = fma(sV[a * N1 + j], x[line_node<N1, DIM>(d, j, l)], m);
         }
         __syncthreads();
         if (valid) x[node] = m;
         __syncthreads();
     }
+    // modal energies: all modes, modes of degree <= N-1, <= N-2 (degree = the
+    // largest one-dimensional index), summed over the element in a fixed tree
     if (valid) {
-        // largest mode index of this coefficient
         int mx = 0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) mx = max(mx, node_pos<N1>(node, d));
-        y[node] = (double)mx;
+        const double m2 = x[node] * x[node];
+        x[node] = m2;
+        y[node] = mx <= N - 1 ? m2 : 0.0;
+        z[node] = mx <= N - 2 ? m2 : 0.0;
     }
     __syncthreads();
-    if (valid && node == 0) {
-        double eall = 0.0, e1 = 0.0, e2 = 0.0;
-        for (int n = 0; n < NN; ++n) {
-            const double m2 = x[n] * x[n];
-            const int mx = (int)y[n];
-            eall += m2;
-            if (mx <= N - 1) e1 += m2;
-            if (mx <= N - 2) e2 += m2;
+    constexpr int P2 = NN <= 16 ? 16 : NN <= 32 ? 32 : NN <= 64 ? 64 : 128;
+#pragma unroll
+    for (int h = P2 / 2; h > 0; h >>= 1) {
+        if (valid && node < h && node + h < NN) {
+            x[node] += x[node + h];
+            y[node] += y[node + h];
+            z[node] += z[node + h];
         }
+        __syncthreads();
+    }
+    if (valid && node == 0) {
+        const double eall = x[0], e1 = y[0], e2 = z[0];
         const double E = fmax((eall - e1) / eall, (e1 - e2) / e1);
         const double thr = 0.5 * pow(10.0, -1.8 * pow((double)N1, 0.25));
         const double s = log((1.0 - 1e-4) / 1e-4);

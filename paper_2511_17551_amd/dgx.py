@@ -157,6 +157,9 @@ class _Keep:
     """Holds ctypes objects alive while the C side copies them."""
 
 
+_LIVE = set()   # contexts created and not yet destroyed (host-side guard)
+
+
 def dgx_create(cfg: dict, species=None, reactions=None):
     keep = _Keep()
     c = dgx_config()
@@ -187,6 +190,7 @@ def dgx_create(cfg: dict, species=None, reactions=None):
     rc = lib.dgx_create(C.byref(c), C.byref(h))
     if rc != DGX_OK:
         raise DgxError(rc, "dgx_create rejected the configuration")
+    _LIVE.add(h.value)
     return h
 
 
@@ -351,6 +355,7 @@ def dgx_last_error(ctx):
 
 
 def dgx_destroy(ctx):
+    _LIVE.discard(ctx.value if isinstance(ctx, C.c_void_p) else ctx)
     lib.dgx_destroy(ctx)
 
 
@@ -398,6 +403,8 @@ def mixture_energy_fns(ctx):
     (used to build mixture states when the oracle is not involved)."""
     def make(which):
         def fn(rs, T):
+            if (ctx.value if isinstance(ctx, C.c_void_p) else ctx) not in _LIVE:
+                raise RuntimeError("mixture energy functions used after their context was destroyed")
             T = np.asarray(T, float)
             shape = np.broadcast_shapes(rs.shape[1:], T.shape)
             Tb = np.broadcast_to(T, shape)
