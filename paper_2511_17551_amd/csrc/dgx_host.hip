@@ -121,7 +121,7 @@ struct dgx_ctx {
     bool curved = false;
     bool mesh_ok = false;
     int nbc = 0;
-    DevBuf<double> geo, Jn, nsub, bc_state, bc_T, T, alpha, alpha_tmp, alpha_raw, grad, vpart, u1, u2, dtbuf;
+    DevBuf<double> geo, Jn, nsub, bc_state, bc_T, T, csnd, alpha, alpha_tmp, alpha_raw, grad, vpart, u1, u2, dtbuf;
     DevBuf<int> nbr, bc_kind, mort, iters;
     DevBuf<double> tg;
     DevBuf<double> mflux;
@@ -218,6 +218,7 @@ RhsParams base_params(dgx_ctx *ctx) {
     P.Jn = ctx->Jn.p;
     P.nsub = ctx->nsub.p;
     P.T = ctx->T.p;
+    P.csnd = ctx->csnd.p;
     P.grad = ctx->grad.p;
     P.vpart = ctx->vpart.p;
     P.bc_kind = ctx->bc_kind.p;
@@ -253,11 +254,11 @@ int enqueue_thermo_mesh(dgx_ctx *ctx, const double *u, hipStream_t s) {
     if (ctx->cfg.dim == 2)
         hipLaunchKernelGGL(k_thermo<2>, dim3(blocks), dim3(th), 0, s, u, count, (const double *)nullptr,
                            ctx->cfg.T_guess, ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, ctx->T.p,
-                           (double *)nullptr, (int *)nullptr, ctx->flags.p, 1);
+                           (double *)nullptr, ctx->csnd.p, (int *)nullptr, ctx->flags.p, 1);
     else
         hipLaunchKernelGGL(k_thermo<3>, dim3(blocks), dim3(th), 0, s, u, count, (const double *)nullptr,
                            ctx->cfg.T_guess, ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, ctx->T.p,
-                           (double *)nullptr, (int *)nullptr, ctx->flags.p, 1);
+                           (double *)nullptr, ctx->csnd.p, (int *)nullptr, ctx->flags.p, 1);
     return hipGetLastError() == hipSuccess ? DGX_OK : DGX_E_DEVICE;
 }
 
@@ -656,6 +657,7 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         // per-node temperature, the warm start of the right-hand side's
         // T(e) solves: the freestream guess until the first solve
         if ((rc = dalloc(ctx, ctx->T, (size_t)E * nn))) return rc;
+        if ((rc = dalloc(ctx, ctx->csnd, (size_t)E * nn))) return rc;
         std::vector<double> t0((size_t)E * nn, ctx->cfg.T_guess);
         HIPCHK(hipMemcpy(ctx->T.p, t0.data(), t0.size() * sizeof(double), hipMemcpyHostToDevice));
     }
@@ -839,10 +841,12 @@ int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double
     const int blocks = (int)((count + tb - 1) / tb);
     if (ctx->cfg.dim == 2)
         hipLaunchKernelGGL(k_thermo<2>, dim3(blocks), dim3(tb), 0, s, u, count, tg, ctx->cfg.T_guess,
-                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, iters, ctx->flags.p, 0);
+                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, (double *)nullptr, iters,
+                           ctx->flags.p, 0);
     else
         hipLaunchKernelGGL(k_thermo<3>, dim3(blocks), dim3(tb), 0, s, u, count, tg, ctx->cfg.T_guess,
-                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, iters, ctx->flags.p, 0);
+                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, (double *)nullptr, iters,
+                           ctx->flags.p, 0);
     if (hipGetLastError() != hipSuccess) return set_err(ctx, DGX_E_DEVICE, "thermo launch failed");
     if (!stats) return DGX_OK;
     return collect_stats(ctx, count, ctx->cfg.newton_maxit, stats, s);
@@ -1075,7 +1079,7 @@ void dgx_destroy(dgx_ctx *ctx) {
     (void)hipDeviceSynchronize();
     clear_graph(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    DevBuf<double> *bufs[] = {&ctx->geo,   &ctx->Jn,        &ctx->nsub,      &ctx->bc_state, &ctx->bc_T, &ctx->T,
+    DevBuf<double> *bufs[] = {&ctx->geo,   &ctx->Jn,        &ctx->nsub,      &ctx->bc_state, &ctx->bc_T, &ctx->T, &ctx->csnd,
                               &ctx->alpha, &ctx->alpha_tmp, &ctx->alpha_raw, &ctx->grad,     &ctx->u1,   &ctx->u2,
                               &ctx->dtbuf, &ctx->vpart};
     for (auto *b : bufs) b->release();

@@ -57,6 +57,7 @@ struct RhsParams {
     const double *nsub;     // curved + shock: [E][dim][nf][N][dim] subcell normals
     const double *alpha;    // [E] or null
     const double *T;        // mixture temperature [E][nn]
+    const double *csnd;     // mixture frozen sound speed [E][nn], from the T(e) solve
     const double *grad;     // NS: neighbours' face viscous fluxes [E][2 dim][dim+1][nf]
     const double *vpart;    // NS: element-local viscous divergence [dim+1][E][nn]
     double *out2;           // second output (k_grad: face viscous fluxes)

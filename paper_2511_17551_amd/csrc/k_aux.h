@@ -235,8 +235,8 @@ template <int DIM>
 __global__ void __launch_bounds__(256) k_thermo(const double *__restrict__ u, int64_t count,
                                                 const double *__restrict__ Tguess, double T0,
                                                 double tol, int maxit, MixC M, double *__restrict__ T,
-                                                double *__restrict__ pout, int *__restrict__ iters,
-                                                unsigned *flags, int warm) {
+                                                double *__restrict__ pout, double *__restrict__ cout,
+                                                int *__restrict__ iters, unsigned *flags, int warm) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     double rs[kNS];
@@ -264,6 +264,7 @@ __global__ void __launch_bounds__(256) k_thermo(const double *__restrict__ u, in
     }
     T[i] = t;
     if (pout) pout[i] = mix_rR(M, rs) * t;
+    if (cout) cout[i] = mix_sound(M, rs, rho, t);
     if (iters) iters[i] = it;
     if (it < 0 || !isfinite(t) || !(t > 0.0)) atomicOr(flags, FLAG_NOCONV);
 }
@@ -511,7 +512,7 @@ __global__ void k_maxrate(RhsParams P, unsigned long long *out) {
         double uo[NV];
         for (int v = 0; v < NV; ++v) uo[v] = P.u[v * stride + i];
         St<DIM, MIX> s;
-        make_state<DIM, MIX>(uo, MIX ? P.T[i] : 0.0, P.gamma, P.M, s);
+        make_state<DIM, MIX>(uo, MIX ? P.T[i] : 0.0, P.gamma, P.M, s, MIX ? P.csnd + i : nullptr);
         const double J = CURV ? P.Jn[i] : P.geo[(size_t)e * GA + DIM * DIM];
         for (int d = 0; d < DIM; ++d) {
             double n[DIM];

@@ -224,6 +224,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     double ftr[RF][NW];   // neighbour's contravariant viscous face flux (BR1)
     double nrr[RF][DIM];  // xi_d = -1 faces: the neighbour's normal
     double Tr[RF];        // neighbour temperature (mixtures)
+    double cr[RF];        // neighbour frozen sound speed (mixtures)
     // the first round's neighbour data is loaded before the staging, later
     // rounds' right before use (register pressure)
     auto load_nbr = [&](int r) {
@@ -235,6 +236,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) nrr[r][c] = 0.0;
         Tr[r] = 1.0;
+        cr[r] = 1.0;
         const int nb = nbf[r];
         if (tid < NT && it < nloc * NSF && nb >= 0) {
             const int ei = it / NSF;
@@ -249,7 +251,10 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
 #pragma unroll
                 for (int k = 0; k < NW; ++k) ftr[r][k] = fn[k * NF];
             }
-            if constexpr (MIX) Tr[r] = P.T[gj];
+            if constexpr (MIX) {
+                Tr[r] = P.T[gj];
+                cr[r] = P.csnd[gj];
+            }
             if (side == 0) {
                 if constexpr (CURV) {
 #pragma unroll
@@ -285,7 +290,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
             for (int v = 0; v < NV; ++v) uo[v] = 1.0;
         }
         St<DIM, MIX> own;
-        make_state<DIM, MIX>(uo, Tn, gamma, P.M, own);
+        make_state<DIM, MIX>(uo, Tn, gamma, P.M, own, MIX && valid ? P.csnd + gi : nullptr);
         if (valid) {
             sq[node] = own.rho;
 #pragma unroll
@@ -378,7 +383,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                     continue;
                 }
                 if (nb >= 0) {
-                    make_state<DIM, MIX>(une[r], MIX ? Tr[r] : 0.0, gamma, P.M, ext);
+                    make_state<DIM, MIX>(une[r], MIX ? Tr[r] : 0.0, gamma, P.M, ext, MIX ? &cr[r] : nullptr);
                     if (side == 0) {
 #pragma unroll
                         for (int c = 0; c < DIM; ++c) nrm[c] = nrr[r][c];

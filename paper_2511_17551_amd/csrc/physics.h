@@ -154,8 +154,9 @@ __device__ __forceinline__ double mix_sound(const MixC &M, const double *rs, dou
 
 // State of a node from its conserved vector (and T for a mixture).
 template <int DIM, bool MIX>
+// (mixtures: c is the given frozen sound speed when cgiven is not null)
 __device__ __forceinline__ void make_state(const double *u, double T, double gamma, const MixC &M,
-                                           St<DIM, MIX> &s) {
+                                           St<DIM, MIX> &s, const double *cgiven = nullptr) {
     if constexpr (MIX) {
         double rho = 0.0;
 #pragma unroll
@@ -170,7 +171,7 @@ __device__ __forceinline__ void make_state(const double *u, double T, double gam
         s.rhoE = u[kNS + DIM];
         const double rR = mix_rR(M, s.rs);
         s.p = rR * T;
-        s.c = mix_sound(M, s.rs, rho, T);
+        s.c = cgiven ? *cgiven : mix_sound(M, s.rs, rho, T);
     } else {
         s.rho = u[0];
         const double ir = rcp(u[0]);
