@@ -114,7 +114,8 @@ def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=6, reps=5)
     pctx = dgx.dgx_create(probe.cfg, probe.species, probe.reactions)
     energy, cv = dgx.mixture_energy_fns(pctx)
     c = W.case_c4(energy, cv)
-    dgx.dgx_destroy(pctx)
+    hot = W.case_c4(energy, cv, hot=True)
+    dgx.dgx_destroy(pctx)   # the energy functions use it: only after the cases are built
     c.cfg["eq"] = W.EQ_EULER_MIX
     s = dgx.Solver(c)
     u = torch.from_numpy(c.u0).to("cuda")
@@ -125,7 +126,6 @@ def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=6, reps=5)
         snaps.append(u.reshape(u.shape[0], -1).clone())
     s.check()
     # the chemistry step on the hot cylinder state (fresh copies each time)
-    hot = W.case_c4(energy, cv, hot=True)
     hot.cfg["eq"] = W.EQ_EULER_MIX
     sh = dgx.Solver(hot)
     uh = torch.from_numpy(hot.u0).to("cuda")
