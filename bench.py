@@ -362,7 +362,7 @@ def main():
         dgx.dgx_set_launch(solver.ctx, args.epb)
         epb, tune_ms = args.epb, {}
     else:
-        epb, tune_ms = dgx.dgx_autotune(solver.ctx, u, reps=10)
+        epb, tune_ms = dgx.dgx_autotune(solver.ctx, u, reps=20)
     if args.copy_probe:
         # counter calibration: kernels of known traffic on 1 GiB buffers
         # (larger than the 256 MB Infinity Cache)

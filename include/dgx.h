@@ -283,15 +283,17 @@ int dgx_kernel_times(dgx_ctx *ctx, const double *u, int reps, double *ms_out, in
                      char *names_out, size_t names_len, void *stream);
 
 /* Autotuner: for each elements-per-workgroup candidate in {1, 2, 4, 8}
- * that fits (<= 512 threads, <= 64 KB LDS), time `reps` SSPRK3 steps as
- * dgx_ssprk3_step runs them (three fused stages, u0 in its own buffer, the
- * positivity limiter when configured; into library scratch with dt = 0, so
- * u is read, not modified) with HIP events on `stream`, and keep the
- * fastest.  The winner is cached process-wide under the key
+ * that fits (<= 512 threads, <= 64 KB LDS) and each workgroup numbering
+ * (round-robin over the 8 XCDs, or XCD-contiguous element ranges), time
+ * `reps` SSPRK3 steps as dgx_ssprk3_step runs them (three fused stages, u0
+ * in its own buffer, the positivity limiter when configured; into library
+ * scratch with dt = 0, so u is read, not modified) with HIP events on
+ * `stream`, and keep the fastest pair.  The winner is cached process-wide under the key
  * (dim, N, equation, fluxes, geometry kind, element count) and reused by
  * later dgx_set_mesh calls with the same key.  *epb_out (may be NULL)
- * receives the choice, ms_out (may be NULL, [4]) the candidates' average
- * milliseconds per right-hand side (-1 = not run).  Synchronises. */
+ * receives the elements-per-workgroup choice, ms_out (may be NULL, [4]) each
+ * candidate's best average milliseconds per right-hand side over the two
+ * numberings (-1 = not run).  Synchronises. */
 int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *ms_out, void *stream);
 
 /* Force the elements per workgroup (1, 2, 4 or 8; must fit as above). */

@@ -71,6 +71,7 @@ struct RhsParams {
     double Pm[2][25];       // L2 projection back from the halves
     double gamma, R, mu, kappa;
     int epb;                // elements per block
+    int xcd;                // nonzero: XCD-contiguous workgroup numbering (k_rhs, k_grad)
     unsigned *flags;
     BasisC B;
     MixC M;

@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
     const int tid = threadIdx.x;
     if (tid < N1 * N1) sD[tid] = P.B.D[tid];
     const int NT = P.epb * NN;
-    const int e0 = xcd_block(blockIdx.x, gridDim.x) * P.epb;
+    const int e0 = (P.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x) * P.epb;
     const int nloc = min(P.epb, P.nelem - e0);
     int el = tid / NN;
     const int node = tid - el * NN;

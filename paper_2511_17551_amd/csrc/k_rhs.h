@@ -98,7 +98,9 @@ __device__ __forceinline__ Spread spread_phase(int tid, int NT, int K_per_block,
 // and each XCD has its own L2.  This renumbering gives every XCD one
 // contiguous range of element groups, so that face neighbours (in particular
 // the neighbours of a group's end elements) are staged under the same L2.
-// A bijection of [0, nb).
+// It pays while the state fits the shared Infinity Cache; beyond that the
+// round-robin order, one window sweeping the state, keeps the neighbours'
+// data fresh there instead (the autotuner decides).  A bijection of [0, nb).
 __device__ __forceinline__ int xcd_block(int b, int nb) {
     constexpr int X = 8;
     const int q = nb / X, r = nb - q * X, x = b % X, i = b / X;
@@ -186,7 +188,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     if (tid < N1 * N1) sDc[tid] = 2.0 * P.B.D[tid];
     if (tid < N1) sW[tid] = P.B.w[tid];
     const int NT = P.epb * NN;  // threads that own a node
-    const int e0 = xcd_block(blockIdx.x, gridDim.x) * P.epb;
+    const int e0 = (P.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x) * P.epb;
     const int nloc = min(P.epb, P.nelem - e0);
     int el = tid / NN;
     const int node = tid - el * NN;
