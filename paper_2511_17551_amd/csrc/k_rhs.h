@@ -123,14 +123,26 @@ struct RhsShape {
     static constexpr int PD = NF * NPL;      // pairs per direction
     static constexpr int NFV = NF * N;       // interior subcell interfaces per direction
     static constexpr int NSF = 2 * DIM * NF; // face nodes
-    static constexpr int B1 = PD * NV;
+    // large element types handle their pair and face work items in two
+    // chunks, which halves the flux buffer (LDS bounds their occupancy)
+    static constexpr int NCH = PD * NV > 1200 ? 2 : 1;
+    static constexpr int PDC = (PD + NCH - 1) / NCH;    // pairs per chunk
+    static constexpr int NSFC = (NSF + NCH - 1) / NCH;  // face nodes per chunk
+    static constexpr int B1 = PDC * NV;
     static constexpr int B2 = NFV * NV;
-    static constexpr int B3 = NSF * NV;
+    static constexpr int B3 = NSFC * NV;
     static constexpr int M12 = B1 > B2 ? B1 : B2;
     static constexpr int BUF = M12 > B3 ? M12 : B3;
-    static constexpr int GEO = CURV ? (DIM * DIM + 1) * NN : 0;
+    // curved: one metric row per node (the current direction); J and the
+    // face normals are read from memory
+    static constexpr int GEO = CURV ? DIM * NN : 0;
     static constexpr int GEOA = CURV ? 0 : DIM * DIM + 1;  // affine: Ja rows, J
     static constexpr int SLOT = SU + NQ * NN + GEO + GEOA + BUF;
+    // curved mixture elements keep their own state in registers from the
+    // staging to the stage update (their working set exceeds the Infinity
+    // Cache, so re-reading it costs HBM traffic; they have VGPRs to spare at
+    // their LDS-bound occupancy)
+    static constexpr bool KEEPU = MIX && CURV;
 };
 
 // nrm = Jaf[d][:] for a runtime direction d without dynamic indexing of a
@@ -173,11 +185,14 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     using S = RhsShape<DIM, N, EQ, VF, CURV>;
     constexpr int N1 = S::N1, NN = S::NN, NF = S::NF, NV = S::NV, NQ = S::NQ, NW = S::NW;
     constexpr int NPL = S::NPL, PD = S::PD, NFV = S::NFV, NSF = S::NSF;
+    constexpr int NCH = S::NCH, PDC = S::PDC, NSFC = S::NSFC;
     constexpr bool MIX = S::MIX;
     constexpr int GA = DIM * DIM + 1;
     constexpr int QB = DIM + 3 + (MIX ? 1 : 0);  // EC slot in sq
     constexpr int OFF_G = S::SU + NQ * NN;        // element geometry within a slot
     constexpr int OFF_B = OFF_G + S::GEO + S::GEOA;
+    constexpr int RFC = (NSFC + NN - 1) / NN;     // face rounds per chunk
+    constexpr int RF = NCH * RFC;                 // face rounds
     extern __shared__ double smem[];
     // 2 D (pair-flux coefficients) and the LGL weights: read with per-lane
     // indices, so they live in LDS rather than in the kernel arguments
@@ -197,78 +212,100 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     if (el >= P.epb) el = 0;
     double *su = smem + el * S::SLOT;
     double *sq = su + S::SU;
-    double *sJa = su + OFF_G;
-    double *sJ = sJa + DIM * DIM * NN;
+    double *sJa = su + OFF_G;  // curved: the current direction's metric row; affine: Ja, J
     double *buf = su + OFF_B;
     const size_t stride = (size_t)P.nelem * NN;
     const size_t gi = (size_t)e * NN + node;
     const double gamma = P.gamma;
 
     // Work items (face nodes, volume pairs) of all elements of the workgroup
-    // are spread over all its threads.  The face phase's neighbour indices,
-    // and then the neighbour data of its conforming faces, are fetched first
-    // so that their latency overlaps the staging.
-    constexpr int RF = (NSF + NN - 1) / NN;
-    const Spread spf = spread_phase(tid, NT, P.epb * NSF, 0);
-    int cursor = spf.cursor;
+    // are spread over all its threads; large element types handle them in
+    // NCH chunks so that one chunk's fluxes fit the LDS buffer.  The face
+    // phase's neighbour indices, and then the neighbour data of its first
+    // round, are fetched first so that their latency overlaps the staging.
+    Spread spf[NCH];
+    int cursor = 0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        spf[c] = spread_phase(tid, NT, P.epb * NSFC, cursor);
+        cursor = spf[c].cursor;
+    }
+    // face round g = chunk * RFC + r: item of this thread (element ei, face
+    // node fi), or false
+    auto face_item = [&](int g, int &ei, int &fi) -> bool {
+        const int c = g / RFC, r = g - c * RFC;
+        const int it = r * NT + spf[c].t;
+        if (tid >= NT || it >= nloc * NSFC) return false;
+        ei = it / NSFC;
+        fi = c * NSFC + (it - ei * NSFC);
+        return fi < NSF;
+    };
     int nbf[RF];
 #pragma unroll
-    for (int r = 0; r < RF; ++r) {
-        const int it = r * NT + spf.t;
-        nbf[r] = 0;
-        if (tid < NT && it < nloc * NSF) {
-            const int ei = it / NSF;
-            nbf[r] = P.nbr[(e0 + ei) * 2 * DIM + (it - ei * NSF) / NF];
-        }
+    for (int g = 0; g < RF; ++g) {
+        int ei, fi;
+        nbf[g] = 0;
+        if (face_item(g, ei, fi)) nbf[g] = P.nbr[(e0 + ei) * 2 * DIM + fi / NF];
     }
 
     double une[RF][NV];   // neighbour state at the face node
     double ftr[RF][NW];   // neighbour's contravariant viscous face flux (BR1)
-    double nrr[RF][DIM];  // xi_d = -1 faces: the neighbour's normal
+    double nrr[RF][DIM];  // the face normal when it comes from memory
     double Tr[RF];        // neighbour temperature (mixtures)
     double cr[RF];        // neighbour frozen sound speed (mixtures)
-    // the first round's neighbour data is loaded before the staging, later
-    // rounds' right before use (register pressure)
-    auto load_nbr = [&](int r) {
-        const int it = r * NT + spf.t;
+    // The first round's data is loaded before the staging, later rounds'
+    // right before use (register pressure).  Face normals come from the
+    // element whose xi_d = +1 face it is: on affine elements the own one
+    // sits in LDS, the neighbour's is loaded; on curved elements both are
+    // nodal and loaded.
+    auto load_nbr = [&](int g) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) une[r][v] = 1.0;
+        for (int v = 0; v < NV; ++v) une[g][v] = 1.0;
 #pragma unroll
-        for (int k = 0; k < NW; ++k) ftr[r][k] = 0.0;
+        for (int k = 0; k < NW; ++k) ftr[g][k] = 0.0;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) nrr[r][c] = 0.0;
-        Tr[r] = 1.0;
-        cr[r] = 1.0;
-        const int nb = nbf[r];
-        if (tid < NT && it < nloc * NSF && nb >= 0) {
-            const int ei = it / NSF;
-            const int f = (it - ei * NSF) / NF;
-            const int q = it - ei * NSF - f * NF;
-            const int d = f >> 1, side = f & 1;
+        for (int c = 0; c < DIM; ++c) nrr[g][c] = 0.0;
+        Tr[g] = 1.0;
+        cr[g] = 1.0;
+        int ei, fi;
+        if (!face_item(g, ei, fi)) return;
+        const int nb = nbf[g];
+        const int f = fi / NF;
+        const int q = fi - f * NF;
+        const int d = f >> 1, side = f & 1;
+        if (nb >= 0) {
             const size_t gj = (size_t)nb * NN + line_node<N1, DIM>(d, side ? 0 : N, q);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) une[r][v] = P.u[v * stride + gj];
+            for (int v = 0; v < NV; ++v) une[g][v] = P.u[v * stride + gj];
             if constexpr (EQ == 1) {
                 const double *fn = P.grad + ((size_t)nb * 2 * DIM + (f ^ 1)) * NW * NF + q;
 #pragma unroll
-                for (int k = 0; k < NW; ++k) ftr[r][k] = fn[k * NF];
+                for (int k = 0; k < NW; ++k) ftr[g][k] = fn[k * NF];
             }
             if constexpr (MIX) {
-                Tr[r] = P.T[gj];
-                cr[r] = P.csnd[gj];
+                Tr[g] = P.T[gj];
+                cr[g] = P.csnd[gj];
             }
             if (side == 0) {
                 if constexpr (CURV) {
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) nrr[r][c] = P.geo[(d * DIM + c) * stride + gj];
+                    for (int c = 0; c < DIM; ++c) nrr[g][c] = P.geo[(d * DIM + c) * stride + gj];
                 } else {
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) nrr[r][c] = P.geo[(size_t)nb * GA + d * DIM + c];
+                    for (int c = 0; c < DIM; ++c) nrr[g][c] = P.geo[(size_t)nb * GA + d * DIM + c];
                 }
+            }
+        }
+        if constexpr (CURV) {
+            if (nb < 0 || side == 1) {
+                const size_t go = (size_t)(e0 + ei) * NN + line_node<N1, DIM>(d, side ? N : 0, q);
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) nrr[g][c] = P.geo[(d * DIM + c) * stride + go];
             }
         }
     };
 
+    double ku[S::KEEPU ? NV : 1];  // the own state, kept for the stage update
     // ---- stage the element: primitives (+ species, metric terms)
     {
         double uo[NV];
@@ -281,8 +318,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
         if (valid) {
             if constexpr (CURV) {
 #pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) sJa[k * NN + node] = P.geo[k * stride + gi];
-                sJ[node] = P.Jn[gi];
+                for (int c = 0; c < DIM; ++c) sJa[c * NN + node] = P.geo[c * stride + gi];  // direction 0
             } else {
                 if (node < GA) sJa[node] = P.geo[(size_t)e * GA + node];
             }
@@ -290,6 +326,10 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v) uo[v] = 1.0;
+        }
+        if constexpr (S::KEEPU) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ku[v] = uo[v];
         }
         St<DIM, MIX> own;
         make_state<DIM, MIX>(uo, Tn, gamma, P.M, own, MIX && valid ? P.csnd + gi : nullptr);
@@ -316,23 +356,23 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
         }
     }
     __syncthreads();
-    const double Jel = CURV ? 1.0 : sJa[DIM * DIM];
 
     double acc[NV];  // surface terms and alpha-weighted FV terms
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
 
     // ---- interface / boundary Riemann fluxes: one work item per face node
-    {
 #pragma unroll
-        for (int r = 0; r < RF; ++r) {
-            if (r > 0) load_nbr(r);
-            const int it = r * NT + spf.t;
-            if (tid < NT && it < nloc * NSF) {
-                const int ei = it / NSF;
-                const int fi = it - ei * NSF;
+    for (int ch = 0; ch < NCH; ++ch) {
+#pragma unroll
+        for (int rr = 0; rr < RFC; ++rr) {
+            const int g = ch * RFC + rr;
+            if (g > 0) load_nbr(g);
+            int ei, fi;
+            if (face_item(g, ei, fi)) {
                 const int f = fi / NF;
                 const int q = fi - f * NF;
+                const int jb = fi - ch * NSFC;  // slot in this chunk's buffer
                 const int d = f >> 1, side = f & 1;
                 const double *esu = smem + ei * S::SLOT;
                 const double *esq = esu + S::SU;
@@ -344,12 +384,12 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                 double nrm[DIM];
                 if constexpr (CURV) {
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) nrm[c] = eg[(d * DIM + c) * NN + nd];
+                    for (int c = 0; c < DIM; ++c) nrm[c] = nrr[g][c];
                 } else {
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) nrm[c] = eg[d * DIM + c];
                 }
-                const int nb = nbf[r];
+                const int nb = nbf[g];
                 double F[NV];
                 if (MORT && nb <= kMortBase) {
                     // non-conforming face: sub-face fluxes from k_mortar
@@ -370,9 +410,9 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                             const int a = sb & 1, bsel = sb >> 1;
 #pragma unroll 1
                             for (int qq = 0; qq < NF; ++qq) {
-                                const int ja = qq % N1, jb = qq / N1;
+                                const int ja = qq % N1, jb2 = qq / N1;
                                 double w = P.Pm[a][qa * N1 + ja];
-                                if (DIM == 3) w *= P.Pm[bsel][qb * N1 + jb];
+                                if (DIM == 3) w *= P.Pm[bsel][qb * N1 + jb2];
 #pragma unroll
                                 for (int v = 0; v < NV; ++v) F[v] = fma(w, mf[(sb * NV + v) * NF + qq], F[v]);
                             }
@@ -381,14 +421,14 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                         for (int v = 0; v < NV; ++v) F[v] *= (double)NSUB;
                     }
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) ebuf[v * NSF + fi] = F[v];
+                    for (int v = 0; v < NV; ++v) ebuf[v * NSFC + jb] = F[v];
                     continue;
                 }
                 if (nb >= 0) {
-                    make_state<DIM, MIX>(une[r], MIX ? Tr[r] : 0.0, gamma, P.M, ext, MIX ? &cr[r] : nullptr);
+                    make_state<DIM, MIX>(une[g], MIX ? Tr[g] : 0.0, gamma, P.M, ext, MIX ? &cr[g] : nullptr);
                     if (side == 0) {
 #pragma unroll
-                        for (int c = 0; c < DIM; ++c) nrm[c] = nrr[r][c];
+                        for (int c = 0; c < DIM; ++c) nrm[c] = nrr[g][c];
                     }
                 } else {
                     const int bc = -1 - nb;
@@ -422,31 +462,30 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                     // with the inviscid flux (F* - F_v/2 on the momentum and
                     // energy rows; periodic meshes only, so nb >= 0 here).
 #pragma unroll
-                    for (int k = 0; k < NW; ++k) F[1 + k] -= 0.5 * ftr[r][k];
+                    for (int k = 0; k < NW; ++k) F[1 + k] -= 0.5 * ftr[g][k];
                 }
 #pragma unroll
-                for (int v = 0; v < NV; ++v) ebuf[v * NSF + fi] = F[v];
+                for (int v = 0; v < NV; ++v) ebuf[v * NSFC + jb] = F[v];
             }
         }
-    }
-    __syncthreads();
-    if (valid) {
+        __syncthreads();
+        if (valid) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            const int a = node_pos<N1>(node, d);
-            const int l = node_line<N1, DIM>(node, d);
-            if (a == N) {
-                const double sc = 1.0 / P.B.w[N];
+            for (int d = 0; d < DIM; ++d) {
+                const int a = node_pos<N1>(node, d);
+                const int l = node_line<N1, DIM>(node, d);
+                if (a == N || a == 0) {
+                    const int fi = (2 * d + (a == N ? 1 : 0)) * NF + l;
+                    if (NCH == 1 || (fi >= ch * NSFC && fi < (ch + 1) * NSFC)) {
+                        const double sc = a == N ? 1.0 / sW[N] : -1.0 / sW[0];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) acc[v] = fma(sc, buf[v * NSF + (2 * d + 1) * NF + l], acc[v]);
-            } else if (a == 0) {
-                const double sc = -1.0 / P.B.w[0];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) acc[v] = fma(sc, buf[v * NSF + (2 * d) * NF + l], acc[v]);
+                        for (int v = 0; v < NV; ++v) acc[v] = fma(sc, buf[v * NSFC + fi - ch * NSFC], acc[v]);
+                    }
+                }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---- first-order subcell finite volumes (elements with alpha > 0)
     const double alpha = (P.alpha != nullptr && valid) ? P.alpha[e] : 0.0;
@@ -496,9 +535,10 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     }
 
     // the epilogue's own-node loads (u, u0 of the stage form, the local
-    // viscous part) are issued before the last gather, once the pair fluxes
-    // no longer hold registers, so that their latency overlaps it
+    // viscous part, curved J) are issued before the last gather, once the
+    // pair fluxes no longer hold registers, so that their latency overlaps it
     double eu[NV], eu0[NV], evp[NW];
+    double Jc = 1.0;  // curved: J of the node
 
     // ---- high-order volume term: symmetric two-point fluxes along lines
     double dg[NV];
@@ -507,79 +547,101 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     const double gm1_inv = 1.0 / (gamma - 1.0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        const Spread sp = spread_phase(tid, NT, P.epb * PD, cursor);
-        cursor = sp.cursor;
+        // curved elements: the next direction's metric row, loaded now and
+        // stored once this direction's pair fluxes are done
+        double jnext[DIM];
+        if constexpr (CURV) {
 #pragma unroll
-        for (int r = 0; r < (PD + NN - 1) / NN; ++r) {
-            const int it = r * NT + sp.t;
-            if (tid < NT && it < nloc * PD) {
-                const int ei = it / PD;
-                const int p = it - ei * PD;
-                const int l = p / NPL;
-                const int k = p - l * NPL;
-                const int a = (int)((PairTab<N1>::A >> (4 * k)) & 15u);
-                const int b = (int)((PairTab<N1>::B >> (4 * k)) & 15u);
-                const double *esu = smem + ei * S::SLOT;
-                const double *esq = esu + S::SU;
-                const double *eg = esu + OFF_G;
-                double *ebuf = smem + ei * S::SLOT + OFF_B;
-                const int na = line_node<N1, DIM>(d, a, l);
-                const int nb = line_node<N1, DIM>(d, b, l);
-                double nbar[DIM];
+            for (int c = 0; c < DIM; ++c)
+                jnext[c] = (valid && d + 1 < DIM) ? P.geo[((d + 1) * DIM + c) * stride + gi] : 0.0;
+        }
 #pragma unroll
-                for (int c = 0; c < DIM; ++c)
-                    nbar[c] = CURV ? 0.5 * (eg[(d * DIM + c) * NN + na] + eg[(d * DIM + c) * NN + nb])
-                                   : eg[d * DIM + c];
-                double F[NV];
-                if constexpr (S::EC) {
-                    double vA[DIM], vB[DIM];
+        for (int ch = 0; ch < NCH; ++ch) {
+            const Spread sp = spread_phase(tid, NT, P.epb * PDC, cursor);
+            cursor = sp.cursor;
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) {
-                        vA[c] = esq[(1 + c) * NN + na];
-                        vB[c] = esq[(1 + c) * NN + nb];
+            for (int r = 0; r < (PDC + NN - 1) / NN; ++r) {
+                const int it = r * NT + sp.t;
+                if (tid < NT && it < nloc * PDC) {
+                    const int ei = it / PDC;
+                    const int jb = it - ei * PDC;      // slot in this chunk's buffer
+                    const int p = ch * PDC + jb;       // pair index within the direction
+                    if (NCH > 1 && p >= PD) continue;
+                    const int l = p / NPL;
+                    const int k = p - l * NPL;
+                    const int a = (int)((PairTab<N1>::A >> (4 * k)) & 15u);
+                    const int b = (int)((PairTab<N1>::B >> (4 * k)) & 15u);
+                    const double *esu = smem + ei * S::SLOT;
+                    const double *esq = esu + S::SU;
+                    const double *eg = esu + OFF_G;
+                    double *ebuf = smem + ei * S::SLOT + OFF_B;
+                    const int na = line_node<N1, DIM>(d, a, l);
+                    const int nb = line_node<N1, DIM>(d, b, l);
+                    double nbar[DIM];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c)
+                        nbar[c] = CURV ? 0.5 * (eg[c * NN + na] + eg[c * NN + nb]) : eg[d * DIM + c];
+                    double F[NV];
+                    if constexpr (S::EC) {
+                        double vA[DIM], vB[DIM];
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) {
+                            vA[c] = esq[(1 + c) * NN + na];
+                            vB[c] = esq[(1 + c) * NN + nb];
+                        }
+                        ranocha_prims<DIM>(esq[na], vA, esq[(1 + DIM) * NN + na], esq[QB * NN + na], esq[nb], vB,
+                                           esq[(1 + DIM) * NN + nb], esq[QB * NN + nb], nbar, gm1_inv, F);
+                    } else {
+                        St<DIM, MIX> A, B;
+                        lds_state<DIM, MIX>(esu, esq, NN, na, gamma, A);
+                        lds_state<DIM, MIX>(esu, esq, NN, nb, gamma, B);
+                        ducros_state<DIM, MIX>(A, B, nbar, F);
                     }
-                    ranocha_prims<DIM>(esq[na], vA, esq[(1 + DIM) * NN + na], esq[QB * NN + na], esq[nb], vB,
-                                       esq[(1 + DIM) * NN + nb], esq[QB * NN + nb], nbar, gm1_inv, F);
-                } else {
-                    St<DIM, MIX> A, B;
-                    lds_state<DIM, MIX>(esu, esq, NN, na, gamma, A);
-                    lds_state<DIM, MIX>(esu, esq, NN, nb, gamma, B);
-                    ducros_state<DIM, MIX>(A, B, nbar, F);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) ebuf[v * PDC + jb] = F[v];
+                }
+            }
+            if (d == DIM - 1 && ch == NCH - 1) {
+                const bool st = valid && mode != 0;
+                const bool s0 = st && P.sa != 0.0;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    if constexpr (S::KEEPU) eu[v] = ku[v];
+                    else eu[v] = st ? P.u[v * stride + gi] : 0.0;
+                    eu0[v] = s0 ? P.u0[v * stride + gi] : 0.0;
                 }
 #pragma unroll
-                for (int v = 0; v < NV; ++v) ebuf[v * PD + p] = F[v];
+                for (int k = 0; k < NW; ++k) evp[k] = (EQ == 1 && valid) ? P.vpart[(size_t)k * stride + gi] : 0.0;
+                if constexpr (CURV) Jc = valid ? P.Jn[gi] : 1.0;
             }
-        }
-        if (d == DIM - 1) {
-            const bool st = valid && mode != 0;
-            const bool s0 = st && P.sa != 0.0;
+            __syncthreads();
+            if constexpr (CURV) {
+                // every pair of this direction has read the row: replace it
+                if (ch == NCH - 1 && d + 1 < DIM && valid) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                eu[v] = st ? P.u[v * stride + gi] : 0.0;
-                eu0[v] = s0 ? P.u0[v * stride + gi] : 0.0;
+                    for (int c = 0; c < DIM; ++c) sJa[c * NN + node] = jnext[c];
+                }
             }
+            if (valid) {
+                const int a = node_pos<N1>(node, d);
+                const int l = node_line<N1, DIM>(node, d);
 #pragma unroll
-            for (int k = 0; k < NW; ++k) evp[k] = (EQ == 1 && valid) ? P.vpart[(size_t)k * stride + gi] : 0.0;
-        }
-        __syncthreads();
-        if (valid) {
-            const int a = node_pos<N1>(node, d);
-            const int l = node_line<N1, DIM>(node, d);
+                for (int j = 1; j < N1; ++j) {
+                    // the other nodes b != a of the line, without branches
+                    const int b = a + j - (a + j >= N1 ? N1 : 0);
+                    const int lo = a < b ? a : b, hi = a < b ? b : a;
+                    const int k = l * NPL + pair_index<N1>(lo, hi);
+                    if (NCH == 1 || (k >= ch * PDC && k < (ch + 1) * PDC)) {
+                        const double coef = sDc[a * N1 + b];
 #pragma unroll
-            for (int j = 1; j < N1; ++j) {
-                // the other nodes b != a of the line, without branches
-                const int b = a + j - (a + j >= N1 ? N1 : 0);
-                const int lo = a < b ? a : b, hi = a < b ? b : a;
-                const int k = l * NPL + pair_index<N1>(lo, hi);
-                const double coef = sDc[a * N1 + b];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) dg[v] = fma(coef, buf[v * PD + k], dg[v]);
+                        for (int v = 0; v < NV; ++v) dg[v] = fma(coef, buf[v * PDC + k - ch * PDC], dg[v]);
+                    }
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
-    const double Jn = CURV ? (valid ? sJ[node] : 1.0) : Jel;
-    const double iJ = 1.0 / Jn;
+    const double iJ = 1.0 / (CURV ? Jc : sJa[DIM * DIM]);
     double du[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) du[v] = -fma(1.0 - alpha, dg[v], acc[v]) * iJ;
