@@ -117,7 +117,9 @@ typedef struct dgx_config {
     double T_guess;        /* freestream guess of T(e); the right-hand side's
                               per-node solves start from the node's previous
                               temperature (T_guess before the first solve, and
-                              again if Newton fails from it) */
+                              again if Newton fails from it), so a mixture
+                              right-hand side depends on that history at the
+                              level of the Newton tolerance's rounding */
     int positivity;        /* 1 = Zhang-Shu positivity limiter after every SSPRK3 stage */
     const dgx_species *species;      /* mixture equations, else NULL */
     const dgx_reactions *reactions;  /* DGX_EQ_REACT_MIX, else NULL  */
@@ -296,8 +298,11 @@ int dgx_kernel_times(dgx_ctx *ctx, const double *u, int reps, double *ms_out, in
  * numberings (-1 = not run).  Synchronises. */
 int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *ms_out, void *stream);
 
-/* Force the elements per workgroup (1, 2, 4 or 8; must fit as above). */
-int dgx_set_launch(dgx_ctx *ctx, int epb);
+/* Force the launch shape: elements per workgroup (1, 2, 4 or 8; must fit as
+ * above) and the workgroup numbering (order: 0 round-robin over the XCDs,
+ * 1 XCD-contiguous element ranges, -1 keep the current one).  The results do
+ * not depend on either (bitwise). */
+int dgx_set_launch(dgx_ctx *ctx, int epb, int order);
 
 /* Text of the last error on this context (never NULL). */
 const char *dgx_last_error(const dgx_ctx *ctx);

@@ -1007,12 +1007,15 @@ int dgx_kernel_times(dgx_ctx *ctx, const double *u, int reps, double *ms_out, in
     return rc;
 }
 
-int dgx_set_launch(dgx_ctx *ctx, int epb) {
+int dgx_set_launch(dgx_ctx *ctx, int epb, int order) {
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!epb_fits(ctx, epb)) return set_err(ctx, DGX_E_INVAL, "elements per workgroup does not fit");
-    if (epb != ctx->epb) clear_graph(ctx);
+    if (order < -1 || order > 1) return set_err(ctx, DGX_E_INVAL, "workgroup order must be -1, 0 or 1");
+    const int xcd = order < 0 ? ctx->xcd : order;
+    if (epb != ctx->epb || xcd != ctx->xcd) clear_graph(ctx);
     ctx->epb = epb;
+    ctx->xcd = xcd;
     return DGX_OK;
 }
 

@@ -93,7 +93,7 @@ def _load():
         "dgx_kernel_times": ([vp, vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_char_p,
                               C.c_size_t, vp], C.c_int),
         "dgx_autotune": ([vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), vp], C.c_int),
-        "dgx_set_launch": ([vp, C.c_int], C.c_int),
+        "dgx_set_launch": ([vp, C.c_int, C.c_int], C.c_int),
         "dgx_last_error": ([vp], C.c_char_p),
         "dgx_destroy": ([vp], None),
     }
@@ -346,8 +346,10 @@ def dgx_autotune(ctx, u, reps=10, stream=None):
     return epb.value, {c: ms[i] for i, c in enumerate((1, 2, 4, 8)) if ms[i] >= 0}
 
 
-def dgx_set_launch(ctx, epb):
-    _raise(ctx, lib.dgx_set_launch(ctx, int(epb)))
+def dgx_set_launch(ctx, epb, order=-1):
+    """Elements per workgroup and workgroup numbering (0 round-robin over the
+    XCDs, 1 XCD-contiguous, -1 keep)."""
+    _raise(ctx, lib.dgx_set_launch(ctx, int(epb), int(order)))
 
 
 def dgx_last_error(ctx):
