@@ -99,7 +99,7 @@ def recorded_traffic():
     return float(rec["traffic_bytes_per_launch"])
 
 
-def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=6, reps=5):
+def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=16, reps=5):
     """Per-node T(e): surrogate-guided vs plain Newton on solver-generated states.
 
     States: a frozen-chemistry run of the Mach-8 cylinder O-grid (64 x 128,

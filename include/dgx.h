@@ -239,8 +239,9 @@ int dgx_surrogate_set(dgx_ctx *ctx, const float *params_host, size_t n);
 int dgx_surrogate_get(dgx_ctx *ctx, float *params_host, size_t n);
 
 /* Train the surrogate on device states (packed [nvar][count], count >= 256)
- * with labels T (device [count]): epochs of Adam (lr, beta1 0.9, beta2 0.999,
- * eps 1e-8) over minibatches of `batch` in a seeded order.  The loss of each
+ * with labels T (device [count]): epochs of Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8; learning rate decaying from lr to 0 along a cosine over the
+ * call's steps) over minibatches of `batch` in a seeded order.  The loss of each
  * epoch is written to loss_host[epoch] if not NULL.  Synchronises. */
 int dgx_surrogate_train(dgx_ctx *ctx, const double *states, const double *T, int64_t count,
                         int epochs, int batch, float lr, uint64_t seed, float *loss_host,

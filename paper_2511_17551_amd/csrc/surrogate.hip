@@ -35,10 +35,10 @@ constexpr int oW1 = 0, ob1 = oW1 + H * kSurIn, oW2 = ob1 + H, ob2 = oW2 + H * H,
               ob3 = oW3 + H * H, oW4 = ob3 + H, ob4 = oW4 + H, oNorm = ob4 + 1;
 static_assert(oNorm == kSurParams, "parameter layout");
 
+// FP32 -> BF16, round to nearest even: the conversion instruction of gfx950
+// (v_cvt_pk_bf16_f32, which also packs pairs)
 __device__ __forceinline__ unsigned short to_bf16(float f) {
-    unsigned b = __float_as_uint(f);
-    b += 0x7FFFu + ((b >> 16) & 1u);
-    return (unsigned short)(b >> 16);
+    return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 __device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
@@ -51,11 +51,12 @@ __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
     return v;
 }
 
-// tanh(x) = 1 - 2 / (exp(2x) + 1) with the hardware exp/reciprocal (FP32,
-// a few ulp; the activations are rounded to BF16 right after).
+// tanh(x) = 1 - 2 / (exp(2x) + 1) with the hardware exp and reciprocal
+// estimates (v_exp_f32, v_rcp_f32: FP32, about one ulp each; the activations
+// are rounded to BF16 right after, or feed the FP32 output layer).
 __device__ __forceinline__ float tanh_fast(float x) {
     const float t = __expf(2.0f * x);
-    return 1.0f - 2.0f * __frcp_rn(t + 1.0f);
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(t + 1.0f);
 }
 
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
@@ -198,51 +199,70 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float *__restrict__ P
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // two independent 16-sample tiles per pass: the matrix unit works on
+        // one while the vector ALU evaluates the other's tanh
 #pragma unroll 1
-        for (int tt = 0; tt < 4; ++tt) {
-            const int64_t n = s0 + 16 * tt + r;
-            float v[4];
+        for (int tt = 0; tt < 4; tt += 2) {
+            bf16x4 xb[2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = 4 * g + j;
-                v[j] = k < 6 ? sx[w][16 * tt + r][k] : 0.0f;
-            }
-            const bf16x4 xb = pack4(v[0], v[1], v[2], v[3]);
-            bf16x4 hb[4], hc[4];
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-                acc = mfma(W1f[mt], xb, acc);
-                float h[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) h[j] = tanh_fast(acc[j] + sbias[0][16 * mt + 4 * g + j]);
-                hb[mt] = pack4(h[0], h[1], h[2], h[3]);
-            }
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kc = 0; kc < 4; ++kc) acc = mfma(W2f[mt][kc], hb[kc], acc);
-                float h[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) h[j] = tanh_fast(acc[j] + sbias[1][16 * mt + 4 * g + j]);
-                hc[mt] = pack4(h[0], h[1], h[2], h[3]);
-            }
-            float yp = 0.0f;
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kc = 0; kc < 4; ++kc) acc = mfma(W3f[mt][kc], hc[kc], acc);
+            for (int t2 = 0; t2 < 2; ++t2) {
+                float v[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int k = 16 * mt + 4 * g + j;
-                    yp = fmaf(sbias[3][k], tanh_fast(acc[j] + sbias[2][k]), yp);
+                    const int k = 4 * g + j;
+                    v[j] = k < 6 ? sx[w][16 * (tt + t2) + r][k] : 0.0f;
+                }
+                xb[t2] = pack4(v[0], v[1], v[2], v[3]);
+            }
+            bf16x4 hb[2][4], hc[2][4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+                for (int t2 = 0; t2 < 2; ++t2) {
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                    acc = mfma(W1f[mt], xb[t2], acc);
+                    float h[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) h[j] = tanh_fast(acc[j] + sbias[0][16 * mt + 4 * g + j]);
+                    hb[t2][mt] = pack4(h[0], h[1], h[2], h[3]);
                 }
             }
-            yp += __shfl_xor(yp, 16);
-            yp += __shfl_xor(yp, 32);
-            if (g == 0 && n < count) Tg[n] = (double)(yp + b4) * (double)nrm[13] + (double)nrm[12];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+                for (int t2 = 0; t2 < 2; ++t2) {
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) acc = mfma(W2f[mt][kc], hb[t2][kc], acc);
+                    float h[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) h[j] = tanh_fast(acc[j] + sbias[1][16 * mt + 4 * g + j]);
+                    hc[t2][mt] = pack4(h[0], h[1], h[2], h[3]);
+                }
+            }
+            float yp[2] = {0.0f, 0.0f};
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+                for (int t2 = 0; t2 < 2; ++t2) {
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) acc = mfma(W3f[mt][kc], hc[t2][kc], acc);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int k = 16 * mt + 4 * g + j;
+                        yp[t2] = fmaf(sbias[3][k], tanh_fast(acc[j] + sbias[2][k]), yp[t2]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int t2 = 0; t2 < 2; ++t2) {
+                float y = yp[t2];
+                y += __shfl_xor(y, 16);
+                y += __shfl_xor(y, 32);
+                const int64_t n = s0 + 16 * (tt + t2) + r;
+                if (g == 0 && n < count) Tg[n] = (double)(y + b4) * (double)nrm[13] + (double)nrm[12];
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -568,6 +588,10 @@ int surrogate_train(Surrogate &S, int dim, const double *states, const double *T
     for (int64_t i = 0; i < count; ++i) order[i] = (int)i;
     std::mt19937_64 rng(seed);
     int rc = 0;
+    // cosine learning-rate decay over this call's steps, lr -> 0
+    const int64_t per_epoch = (count + batch - 1) / batch;
+    const double total = (double)epochs * (double)per_epoch;
+    int64_t t = 0;
     for (int ep = 0; ep < epochs && !rc; ++ep) {
         std::shuffle(order.begin(), order.end(), rng);
         if (hipMemcpyAsync(idx, order.data(), count * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -582,8 +606,10 @@ int surrogate_train(Surrogate &S, int dim, const double *states, const double *T
             ++S.step;
             const float c1 = 1.0f - std::pow(0.9f, (float)S.step);
             const float c2 = 1.0f - std::pow(0.999f, (float)S.step);
+            const float lr_t = (float)(0.5 * lr * (1.0 + std::cos(3.14159265358979323846 * (double)t / total)));
+            ++t;
             hipLaunchKernelGGL(k_adam, dim3((kSurParams + 255) / 256), dim3(256), 0, s, S.params, S.grads, S.adam_m,
-                               S.adam_v, lr, c1, c2);
+                               S.adam_v, lr_t, c1, c2);
         }
         float l = 0.0f;
         if (!rc && (hipMemcpyAsync(&l, ld, sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
