@@ -275,6 +275,40 @@ def c3_leg(torch, W, dgx, reps=20):
                               unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), bytes_per_launch=rb))
 
 
+def c4_leg(torch, W, dgx, reps=20):
+    """The 2D reacting 5-species cylinder (64 x 128 O-grid, N = 3, 17
+    Arrhenius reactions): back-to-back right-hand sides on the hot, partly
+    dissociated state (each: T(e) Newton per node, modal indicator, fused RHS
+    with the species sources)."""
+    probe = W.case_c4(lambda rs, T: 0 * T, lambda rs, T: 1 + 0 * T, nr=4, nth=8)
+    pctx = dgx.dgx_create(probe.cfg, probe.species, probe.reactions)
+    energy, cv = dgx.mixture_energy_fns(pctx)
+    c = W.case_c4(energy, cv, hot=True)
+    dgx.dgx_destroy(pctx)   # the energy functions use it: only after the case is built
+    nvar, nelem, nn = c.u0.shape
+    s = dgx.Solver(c)
+    u = torch.from_numpy(c.u0).to("cuda")
+    du = torch.empty_like(u)
+    epb, _ = dgx.dgx_autotune(s.ctx, u, reps=5)
+    for _ in range(2):
+        dgx.dgx_rhs(s.ctx, u, 0.0, du)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        dgx.dgx_rhs(s.ctx, u, 0.0, du)
+    e1.record()
+    torch.cuda.synchronize()
+    s.check()
+    ms_rhs = e0.elapsed_time(e1) / reps
+    kt = dgx.dgx_kernel_times(s.ctx, u, reps=10)
+    s.close()
+    return dict(workload="cylinder64x128_N3_air5_17reactions_hot_rhs", elements=nelem, N=3, nodes=nelem * nn,
+                dof=int(c.u0.size), value=round(c.u0.size / (ms_rhs * 1e-3) / 1e9, 3), unit="GDOF-RHS/s",
+                ms_per_rhs=round(ms_rhs, 5), elements_per_workgroup=epb,
+                kernel_ms={k: round(v, 5) for k, v in kt.items()})
+
+
 def batch_leg(torch, W, dgx, reps=10):
     """The AMR density wave + 16 vortex-tube cases: one launch per stage for
     everything vs one context / launch sequence per case."""
@@ -335,7 +369,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-c3", action="store_true", help="skip the curved N=4 mixture shock leg")
+    ap.add_argument("--no-c3", action="store_true", help="skip the mixture legs (curved N=4 shock, reacting cylinder)")
     ap.add_argument("--no-thermo", action="store_true", help="skip the surrogate vs plain T(e) leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched AMR + cases leg")
     ap.add_argument("--epb", type=int, default=0,
@@ -419,6 +453,7 @@ def main():
         out["batch"] = batch_leg(torch, W, dgx)
     if not args.no_c3:
         out["c3"] = c3_leg(torch, W, dgx)
+        out["c4"] = c4_leg(torch, W, dgx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out))
