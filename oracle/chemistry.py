@@ -1,5 +1,5 @@
-"""Per-node stiff chemistry: one backward-Euler step of the species sources
-at fixed internal energy (oracle).
+"""Per-node stiff chemistry: backward-Euler steps of the species sources at
+fixed internal energy (oracle).
 
 Test infrastructure only: the library does not import this module.
 
@@ -8,46 +8,69 @@ transport terms split off); Appendix, Chemical Kinetics (the rates).  The
 paper integrates the sources inside its explicit schemes and warns that the
 iterative thermochemistry is the overhead risk of a reacting step
 (Introduction); it gives no implicit treatment.  Reading: the stiff sources
-are integrated per node by operator splitting, one backward-Euler step over
-dt on the species densities while rho, momentum and total energy stay
-fixed (so rho e = rho E - |m|^2 / (2 rho) is fixed as well):
+are integrated per node by operator splitting, backward Euler on the species
+densities while rho, momentum and total energy stay fixed (so
+rho e = rho E - |m|^2 / (2 rho) is fixed as well).  One backward-Euler step
+over h from rho_s^a solves
 
-    G(rho_s) = rho_s - rho_s^n - dt * omega_s(rho_s, T(rho_s, rho e)) = 0.
+    G(rho_s) = rho_s - rho_s^a - h * omega_s(rho_s, T(rho_s, rho e)) = 0.
 
 The reactions conserve mass, so sum_s omega_s = 0 and the step keeps
 rho = sum_s rho_s.  The root is found by Newton's method with a
 central-difference Jacobian (columns scaled to the node's density), a step
 restricted so that no density becomes negative and the thermal energy
 rho e - sum_s rho_s e0_s stays positive (else no temperature exists), and
-the stop max_s |delta_s| <= tol * rho on the full Newton step.  The Jacobian only steers the iteration; the
-root is what both implementations must agree on.
+the stop max_s |delta_s| <= tol * rho on the full Newton step.  The Jacobian
+only steers the iteration; the root is what both implementations must agree
+on.
+
+Substeps.  A mode that grows (atom-impact dissociation makes [X] grow at a
+rate k [X2]) turns the step's Jacobian singular as h times the growth rate
+reaches 1; beyond that the root near rho^a is gone and the Newton step
+points out of the admissible set, so the positivity limit shrinks it to
+nothing.  Such a Newton iteration is declared failed when the limit cuts the
+step to below STALL of its length on two consecutive iterations (or after
+maxit iterations), and the node then covers the step with backward-Euler
+substeps of dt / 2^k: a failed substep is retried at half the size, and
+after a successful one the node returns to the next larger size when its
+position in the step is a multiple of it.  Positions are kept as integers in
+units of dt / 2^KMAX; a node that fails at the smallest size does not
+converge.  Where the single step converges (the usual case) the result is
+that step's root.
 """
 import numpy as np
 
+KMAX = 20      # smallest substep dt / 2^20
+STALL = 1e-3   # a step cut below this fraction twice in a row has failed
+
 
 def residual(mix, kin, rs, rs0, rhoe, dt, Tg):
-    """G(rs) and the temperature it used, per node (rs: (ns, n))."""
+    """G(rs) and the temperature it used, per node (rs: (ns, n); dt scalar or
+    per node)."""
     T, _ = mix.solve_T(rs, rhoe, Tg, tol=1e-14, maxit=100)
     return rs - rs0 - dt * kin.omega_dot(rs, T), T
 
 
-def backward_euler(mix, kin, rs0, rhoe, dt, T0, tol=1e-13, maxit=100):
-    """One implicit step for every node.  rs0: (ns, n); rhoe, T0: (n,).
+def newton(mix, kin, rs0, rhoe, dt, T0, tol=1e-13, maxit=50):
+    """Damped Newton for one backward-Euler step per node (dt: (n,)).
 
-    Returns (rs, T, iterations).  Raises if a node does not converge.
+    Returns (rs, T, iterations, converged); nodes that stall or run out of
+    iterations are reported as not converged (their rs is meaningless).
     """
     ns, n = rs0.shape
     rs = rs0.copy()
     rho = rs0.sum(0)
     T = np.array(np.broadcast_to(T0, (n,)), float)
     it = np.zeros(n, np.int64)
+    low = np.zeros(n, np.int64)
+    ok = np.zeros(n, bool)
     active = np.ones(n, bool)
     for _ in range(maxit):
         if not active.any():
             break
         idx = np.flatnonzero(active)
-        ra, r0, ea, Ta, rhoa = rs[:, idx], rs0[:, idx], rhoe[idx], T[idx], rho[idx]
-        G, Ta = residual(mix, kin, ra, r0, ea, dt, Ta)
+        ra, r0, ea, Ta, rhoa, dta = rs[:, idx], rs0[:, idx], rhoe[idx], T[idx], rho[idx], dt[idx]
+        G, Ta = residual(mix, kin, ra, r0, ea, dta, Ta)
         # central-difference Jacobian, column k: dG/drho_k
         h = 1e-7 * rhoa
         Jm = np.empty((len(idx), ns, ns))
@@ -56,8 +79,8 @@ def backward_euler(mix, kin, rs0, rhoe, dt, T0, tol=1e-13, maxit=100):
             dn = ra.copy()
             up[k] += h
             dn[k] -= h
-            Gp, _ = residual(mix, kin, up, r0, ea, dt, Ta)
-            Gm, _ = residual(mix, kin, dn, r0, ea, dt, Ta)
+            Gp, _ = residual(mix, kin, up, r0, ea, dta, Ta)
+            Gm, _ = residual(mix, kin, dn, r0, ea, dta, Ta)
             Jm[:, :, k] = ((Gp - Gm) / (2.0 * h)).T
         delta = -np.linalg.solve(Jm, G.T[:, :, None])[:, :, 0].T
         # keep every density non-negative, and keep a positive thermal
@@ -76,8 +99,45 @@ def backward_euler(mix, kin, rs0, rhoe, dt, T0, tol=1e-13, maxit=100):
         it[idx] += 1
         # converged when the full (undamped) Newton step is below tolerance
         done = np.max(np.abs(delta), axis=0) <= tol * rhoa
-        active[idx[done]] = False
-    if active.any():
-        raise RuntimeError("backward-Euler chemistry did not converge")
-    T, _ = mix.solve_T(rs, rhoe, T, tol=1e-14, maxit=100)
-    return rs, T, it
+        low[idx] = np.where(theta < STALL, low[idx] + 1, 0)
+        stalled = ~done & (low[idx] >= 2)
+        ok[idx[done]] = True
+        active[idx[done | stalled]] = False
+    T[ok], _ = mix.solve_T(rs[:, ok], rhoe[ok], T[ok], tol=1e-14, maxit=100)
+    return rs, T, it, ok
+
+
+def backward_euler(mix, kin, rs0, rhoe, dt, T0, tol=1e-13, maxit=50):
+    """Chemistry over dt for every node.  rs0: (ns, n); rhoe, T0: (n,).
+
+    Returns (rs, T, iterations, substeps): the Newton iterations summed over
+    a node's substeps and its number of substeps (1 where the single step
+    converged).  Raises if a node fails at the smallest substep.
+    """
+    ns, n = rs0.shape
+    unit = 1 << KMAX
+    pos = np.zeros(n, np.int64)
+    lev = np.zeros(n, np.int64)
+    rs = rs0.copy()
+    T = np.array(np.broadcast_to(T0, (n,)), float)
+    its = np.zeros(n, np.int64)
+    nsub = np.zeros(n, np.int64)
+    while True:
+        act = np.flatnonzero(pos < unit)
+        if len(act) == 0:
+            break
+        if np.any(lev[act] > KMAX):
+            raise RuntimeError("backward-Euler chemistry did not converge")
+        h = dt * np.ldexp(1.0, -lev[act].astype(np.int32))
+        r1, T1, it, ok = newton(mix, kin, rs[:, act], rhoe[act], h, T[act], tol, maxit)
+        its[act] += it
+        good = act[ok]
+        rs[:, good] = r1[:, ok]
+        T[good] = T1[ok]
+        pos[good] += unit >> lev[good]
+        nsub[good] += 1
+        # back to the next larger substep once the position is a multiple of it
+        up = (lev[good] > 0) & (pos[good] % (unit >> np.maximum(lev[good] - 1, 0)) == 0)
+        lev[good[up]] -= 1
+        lev[act[~ok]] += 1
+    return rs, T, its, nsub

@@ -56,17 +56,26 @@ class Kinetics:
         dn = self.dnu.sum(1).reshape((-1,) + (1,) * np.ndim(T))
         return -dG / (sp.Ru * T) + dn * np.log(sp.p_ref / (sp.Ru * T))
 
-    def kf(self, T):
+    def ln_kf(self, T):
+        """ln k_f = ln A + b ln T - theta_a / T (Eq. forward_rate)."""
         rx = self.rx
         sh = (-1,) + (1,) * np.ndim(T)
-        return rx.A.reshape(sh) * T ** rx.b.reshape(sh) * np.exp(-rx.theta_a.reshape(sh) / T)
+        return np.log(rx.A).reshape(sh) + rx.b.reshape(sh) * np.log(T) - rx.theta_a.reshape(sh) / T
+
+    def kf(self, T):
+        return np.exp(self.ln_kf(T))
+
+    def kb(self, T):
+        """k_b = k_f / K_c (Eq. backward), formed as exp(ln k_f - ln K_c): at low
+        T both factors underflow while their ratio stays finite."""
+        return np.exp(self.ln_kf(T) - self.ln_Kc(T))
 
     def rates(self, rs, T):
         """Molar rates of progress R_r (mol m^-3 s^-1), shape (nr,) + T.shape."""
         rx = self.rx
         conc = rs / self.sp.W.reshape((-1,) + (1,) * np.ndim(T))
         kf = self.kf(T)
-        kb = kf / np.exp(self.ln_Kc(T))
+        kb = self.kb(T)
         out = []
         for r in range(rx.nreactions):
             fwd = np.ones_like(T)

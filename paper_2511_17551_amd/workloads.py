@@ -198,9 +198,16 @@ def park17_reactions(seed: int = 4) -> Reactions:
     """17 reactions with the Park 5-species structure, partner made explicit.
 
     X2 + M <=> X + Y + M for X2 in {N2, O2, NO} and each M in the 5
-    species, then N2 + O <=> NO + N and NO + O <=> O2 + N.  Coefficients are
-    seeded: log10 A ~ U[15, 22] (cm^3/mol/s), b ~ U[-1.6, 0],
-    theta_a ~ U[5e4, 1.2e5] K.
+    species, then N2 + O <=> NO + N and NO + O <=> O2 + N, each written in
+    its endothermic direction.  Coefficients are seeded so that they span
+    the Park data: b ~ U[-1.6, 0]; A such that log10(A * 5000^b) ~ U[12, 17]
+    (cm^3/mol/s, the range of A T^b of those reactions at 5000 K, all below
+    the gas-kinetic collision rate); and the activation temperature is the
+    reaction heat over R_u plus U[0, 4000] K, as theta_a of a dissociation is
+    its dissociation energy over k_B and the exchange reactions sit a few
+    hundred kelvin above their heat.  The last keeps k_b = k_f / K_c bounded
+    as T falls (an activation temperature away from the heat makes k_b grow
+    or vanish like exp(|dtheta|/T)).
     """
     N2, O2, NO, N, O = range(5)
     nu, nup = [], []
@@ -226,9 +233,10 @@ def park17_reactions(seed: int = 4) -> Reactions:
         nup.append(p)
     rng = np.random.default_rng(seed)
     nr = len(nu)
-    logA = rng.uniform(15.0, 22.0, nr)
     b = rng.uniform(-1.6, 0.0, nr)
-    th = rng.uniform(5.0e4, 1.2e5, nr)
+    logA = rng.uniform(12.0, 17.0, nr) - b * math.log10(5000.0)
+    heat = (np.asarray(nup) - np.asarray(nu)) @ Species().hf_molar / Species().Ru
+    th = heat + rng.uniform(0.0, 4.0e3, nr)
     return Reactions(A=10.0 ** logA * 1e-6, b=b, theta_a=th,
                      nu=np.asarray(nu, np.int32), nup=np.asarray(nup, np.int32))
 
