@@ -17,10 +17,12 @@ over h from rho_s^a solves
 
 The reactions conserve mass, so sum_s omega_s = 0 and the step keeps
 rho = sum_s rho_s.  The root is found by Newton's method with a
-central-difference Jacobian (columns scaled to the node's density), a step
+central-difference Jacobian (steps of 1e-7 rho, cut where the thermal energy
+could not pay for the perturbed formation energy), a step
 restricted so that no density becomes negative and the thermal energy
 rho e - sum_s rho_s e0_s stays positive (else no temperature exists), and
-the stop max_s |delta_s| <= tol * rho on the full Newton step.  The Jacobian
+the stop max_s |delta_s| <= tol * rho on the full Newton step.  An iterate
+whose temperature solve fails ends the iteration as failed.  The Jacobian
 only steers the iteration; the root is what both implementations must agree
 on.
 
@@ -44,11 +46,13 @@ KMAX = 20      # smallest substep dt / 2^20
 STALL = 1e-3   # a step cut below this fraction twice in a row has failed
 
 
-def residual(mix, kin, rs, rs0, rhoe, dt, Tg):
+def residual(mix, kin, rs, rs0, rhoe, dt, Tg, strict=True):
     """G(rs) and the temperature it used, per node (rs: (ns, n); dt scalar or
-    per node)."""
-    T, _ = mix.solve_T(rs, rhoe, Tg, tol=1e-14, maxit=100)
-    return rs - rs0 - dt * kin.omega_dot(rs, T), T
+    per node).  A node whose T(e) solve fails raises, or with strict=False
+    gets NaN."""
+    T, _ = mix.solve_T(rs, rhoe, Tg, tol=1e-14, maxit=100, strict=strict)
+    with np.errstate(invalid="ignore"):
+        return rs - rs0 - dt * kin.omega_dot(rs, T), T
 
 
 def newton(mix, kin, rs0, rhoe, dt, T0, tol=1e-13, maxit=50):
@@ -70,18 +74,28 @@ def newton(mix, kin, rs0, rhoe, dt, T0, tol=1e-13, maxit=50):
             break
         idx = np.flatnonzero(active)
         ra, r0, ea, Ta, rhoa, dta = rs[:, idx], rs0[:, idx], rhoe[idx], T[idx], rho[idx], dt[idx]
-        G, Ta = residual(mix, kin, ra, r0, ea, dta, Ta)
-        # central-difference Jacobian, column k: dG/drho_k
-        h = 1e-7 * rhoa
+        G, Ta = residual(mix, kin, ra, r0, ea, dta, Ta, strict=False)
+        # central-difference Jacobian, column k: dG/drho_k; the perturbation
+        # is 1e-7 rho, cut to a quarter of the thermal energy over e0_k so
+        # that the perturbed state still has a temperature
+        thermal0 = ea - (ra * mix.e0[:, None]).sum(0)
         Jm = np.empty((len(idx), ns, ns))
         for k in range(ns):
+            h = 1e-7 * rhoa
+            if mix.e0[k] > 0.0:
+                h = np.minimum(h, 0.25 * thermal0 / mix.e0[k])
             up = ra.copy()
             dn = ra.copy()
             up[k] += h
             dn[k] -= h
-            Gp, _ = residual(mix, kin, up, r0, ea, dta, Ta)
-            Gm, _ = residual(mix, kin, dn, r0, ea, dta, Ta)
+            Gp, _ = residual(mix, kin, up, r0, ea, dta, Ta, strict=False)
+            Gm, _ = residual(mix, kin, dn, r0, ea, dta, Ta, strict=False)
             Jm[:, :, k] = ((Gp - Gm) / (2.0 * h)).T
+        # an iterate without a temperature (its T(e) solve failed) ends that
+        # node's iteration as failed
+        nan = ~(np.isfinite(Jm).all((1, 2)) & np.isfinite(G).all(0))
+        Jm[nan] = np.eye(ns)
+        G = np.where(nan[None], 0.0, G)
         delta = -np.linalg.solve(Jm, G.T[:, :, None])[:, :, 0].T
         # keep every density non-negative, and keep a positive thermal
         # energy rho e - sum_s rho_s e0_s (at or below zero no T exists)
@@ -100,7 +114,8 @@ def newton(mix, kin, rs0, rhoe, dt, T0, tol=1e-13, maxit=50):
         # converged when the full (undamped) Newton step is below tolerance
         done = np.max(np.abs(delta), axis=0) <= tol * rhoa
         low[idx] = np.where(theta < STALL, low[idx] + 1, 0)
-        stalled = ~done & (low[idx] >= 2)
+        done &= ~nan
+        stalled = nan | (~done & (low[idx] >= 2))
         ok[idx[done]] = True
         active[idx[done | stalled]] = False
     T[ok], _ = mix.solve_T(rs[:, ok], rhoe[ok], T[ok], tol=1e-14, maxit=100)

@@ -63,11 +63,11 @@ class Mixture:
     def rho_cv(self, rs, T):
         return np.sum(rs * self.cv_species(T), axis=0)
 
-    def solve_T(self, rs, rhoe, T0, tol=1e-10, maxit=50):
+    def solve_T(self, rs, rhoe, T0, tol=1e-10, maxit=50, strict=True):
         """Per-node Newton iteration; every node stops on its own test.
 
-        Returns T and the iteration count per node; raises if any node
-        fails to converge within maxit.
+        Returns T and the iteration count per node.  A node that fails to
+        converge within maxit raises, or with strict=False gets T = NaN.
         """
         shape = np.shape(rhoe)
         rs = rs.reshape(self.ns, -1)
@@ -90,7 +90,9 @@ class Mixture:
             done = np.abs(dT) <= tol * np.abs(Tn)
             active[idx[done]] = False
         if active.any():
-            raise RuntimeError("Newton for T(e) did not converge")
+            if strict:
+                raise RuntimeError("Newton for T(e) did not converge")
+            T[active] = np.nan
         return T.reshape(shape), it.reshape(shape)
 
     def pressure(self, rs, T):

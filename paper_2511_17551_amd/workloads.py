@@ -370,6 +370,21 @@ def mixture_state(Y, rho, vel, T, energy):
     return np.concatenate([rho_s] + [mm[None] for mm in m] + [E[None]], 0)
 
 
+def far_chem_states(n, seed=11):
+    """Seeded compositions far from chemical equilibrium, the hard cases of a
+    per-node chemistry step: T 250-12000 K, rho 1e-3-1 kg/m^3 (log-uniform),
+    air plus NO, N and O at mass fractions 1e-20-0.1 (log-uniform; all three
+    zero in the first node of every 20).  Cold gas carrying atoms and hot
+    gas with trace atoms both occur.  Returns (rho_s (5, n), T (n,))."""
+    rng = np.random.default_rng(seed)
+    rho = 10.0 ** rng.uniform(-3.0, 0.0, n)
+    T = 10.0 ** rng.uniform(math.log10(250.0), math.log10(12000.0), n)
+    Y = np.stack([np.full(n, 0.767), np.full(n, 0.233)] + [10.0 ** rng.uniform(-20.0, -1.0, n) for _ in range(3)])
+    Y[3:, : n // 20] = 0.0
+    Y = Y / Y.sum(0)
+    return Y * rho, T
+
+
 def case_c3(energy, cv, n=24, N=4, seed=3, T1=300.0, p1=1.0e4, mach=3.0, xs=0.3,
             shock=True, force_alpha=-1.0):
     """3D frozen 5-species Euler on the curved hex mesh with a planar shock.

@@ -164,15 +164,7 @@ def test_first_order_convergence_to_the_exact_flow(setup):
 
 
 def far_states(mix, n, seed=11):
-    """Seeded states far from equilibrium: T 250-12000 K, rho 1e-3-1 kg/m^3,
-    air plus NO, N and O at mass fractions 1e-20-0.1 (zero in one node of 20)."""
-    rng = np.random.default_rng(seed)
-    rho = 10.0 ** rng.uniform(-3.0, 0.0, n)
-    T = 10.0 ** rng.uniform(np.log10(250.0), np.log10(12000.0), n)
-    Y = np.stack([np.full(n, 0.767), np.full(n, 0.233)] + [10.0 ** rng.uniform(-20.0, -1.0, n) for _ in range(3)])
-    Y[3:, : n // 20] = 0.0
-    Y = Y / Y.sum(0)
-    rs = Y * rho
+    rs, T = W.far_chem_states(n, seed)
     return rs, mix.rho_e(rs, T), T
 
 
