@@ -89,7 +89,11 @@ typedef struct dgx_species {
     double p_ref;          /* reference pressure of K_eq, Pa                */
 } dgx_species;
 
-/* Reaction table (Eq. chemreact, forward_rate): host arrays, copied. */
+/* Reaction table (Eq. chemreact, forward_rate): host arrays, copied.
+ * A > 0 and finite b, theta_a, else dgx_create returns DGX_E_INVAL.  The
+ * rates are formed in log space, k_f = exp(ln A + b ln T - theta_a/T) and
+ * k_b = exp(ln k_f - ln K_c), so that k_b stays finite where k_f and K_c
+ * underflow (cold gas). */
 typedef struct dgx_reactions {
     int nreactions;        /* 1..32 */
     const double *A;       /* [nr] m^3 mol^-1 s^-1 (bimolecular forward)    */
@@ -151,8 +155,10 @@ typedef struct dgx_newton_stats {
     int64_t iters_total;      /* sum of per-node iterations                */
     int32_t iters_max;        /* max per-node iterations                   */
     double iters_wave_max_mean; /* mean over wavefronts of the per-wave max */
-    int64_t nonconverged;     /* nodes that hit newton_maxit              */
+    int64_t nonconverged;     /* nodes that did not converge               */
     int64_t first_bad;        /* first non-converged node, or -1           */
+    int64_t substeps_total;   /* dgx_chem_step: sum of per-node substeps   */
+    int32_t substeps_max;     /* dgx_chem_step: max per-node substeps (0 otherwise) */
 } dgx_newton_stats;
 
 typedef struct dgx_ctx dgx_ctx;  /* opaque */
@@ -208,21 +214,29 @@ int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double
                int guess_mode, dgx_newton_stats *stats, void *stream);
 
 /* Per-node stiff chemistry, split from the transport (Governing Equations,
- * Eq. source_term; rates of Appendix, Chemical Kinetics): one backward-Euler
- * step over dt >= 0 of the species sources at fixed density, momentum and
- * total energy, in place on the species rows of u (device [nvar][nelem][nn]
- * of the mesh).  Needs a mixture context created with a reaction table
- * (DGX_EQ_EULER_MIX with cfg->reactions, or DGX_EQ_REACT_MIX).  Newton with
- * the analytic Jacobian along the fixed-energy manifold; every iterate's T
- * comes from the T(e) solve warm-started at the previous one (first: the
- * incoming state's T); steps are limited so that rho_s >= 0 and the thermal
- * energy rho e - sum rho_s e0_s stays positive; a node stops when its full
- * Newton step is below tol * rho, after at most maxit iterations.  The
+ * Eq. source_term; rates of Appendix, Chemical Kinetics): backward Euler over
+ * dt >= 0 of the species sources at fixed density, momentum and total
+ * energy, in place on the species rows of u (device [nvar][nelem][nn] of the
+ * mesh).  Needs a mixture context created with a reaction table
+ * (DGX_EQ_EULER_MIX with cfg->reactions, or DGX_EQ_REACT_MIX).  Each step is
+ * solved by Newton with the analytic Jacobian along the fixed-energy
+ * manifold; every iterate's T comes from the T(e) solve warm-started at the
+ * previous one (first: the incoming state's T); steps are limited so that
+ * rho_s >= 0 and the thermal energy rho e - sum rho_s e0_s stays positive;
+ * the iteration stops when its full Newton step is below tol * rho and fails
+ * after maxit iterations or when the limits cut the step below 1e-3 of its
+ * length on two consecutive iterations (a growing mode with dt times its
+ * growth rate near or above 1).  A node whose single step fails covers dt
+ * with substeps dt/2^k (k <= 20): a failed substep is retried at half the
+ * size, and after a successful one the node returns to the next larger size
+ * when its position in dt is a multiple of it.  A node that fails at dt/2^20
+ * keeps its last accepted substep and counts as non-converged.  The
  * library's per-node temperature is left at the new state's T.  Enqueues on
- * stream; with stats (host) it synchronises and fills the iteration
- * statistics (DGX_E_NOCONV if a node failed), with stats == NULL failures are
- * reported by dgx_check.  With a DGX_EQ_EULER_MIX context, dt/2 chemistry,
- * dgx_ssprk3_step over dt and dt/2 chemistry form a Strang splitting. */
+ * stream; with stats (host) it synchronises and fills the iteration and
+ * substep statistics (DGX_E_NOCONV if a node failed), with stats == NULL
+ * failures are reported by dgx_check.  With a DGX_EQ_EULER_MIX context, dt/2
+ * chemistry, dgx_ssprk3_step over dt and dt/2 chemistry form a Strang
+ * splitting. */
 int dgx_chem_step(dgx_ctx *ctx, double *u, double dt, double tol, int maxit, dgx_newton_stats *stats,
                   void *stream);
 

@@ -122,7 +122,7 @@ struct dgx_ctx {
     bool mesh_ok = false;
     int nbc = 0;
     DevBuf<double> geo, Jn, nsub, bc_state, bc_T, T, csnd, alpha, alpha_tmp, alpha_raw, grad, vpart, u1, u2, dtbuf;
-    DevBuf<int> nbr, bc_kind, mort, iters;
+    DevBuf<int> nbr, bc_kind, mort, iters, subs;
     DevBuf<double> tg;
     DevBuf<double> mflux;
     int nmortar = 0;
@@ -411,8 +411,15 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
     if (mix && cfg->volume_flux == DGX_VF_RANOCHA) return DGX_E_INVAL;
     if (mix && cfg->surface_flux != DGX_SF_RUSANOV) return DGX_E_INVAL;
     if (cfg->equation == DGX_EQ_REACT_MIX && !cfg->reactions) return DGX_E_INVAL;
-    if (mix && cfg->reactions && (cfg->reactions->nreactions < 1 || cfg->reactions->nreactions > kMaxR))
-        return DGX_E_INVAL;
+    if (mix && cfg->reactions) {
+        const dgx_reactions *r = cfg->reactions;
+        if (r->nreactions < 1 || r->nreactions > kMaxR || !r->A || !r->b || !r->theta_a || !r->nu || !r->nup)
+            return DGX_E_INVAL;
+        for (int i = 0; i < r->nreactions; ++i)
+            if (!(r->A[i] > 0.0) || !std::isfinite(r->A[i]) || !std::isfinite(r->b[i]) ||
+                !std::isfinite(r->theta_a[i]))
+                return DGX_E_INVAL;
+    }
     if (cfg->equation == DGX_EQ_NS && (cfg->mu < 0.0 || cfg->Pr <= 0.0)) return DGX_E_INVAL;
     if (!mix && !(cfg->gamma > 1.0)) return DGX_E_INVAL;
     dgx_ctx *ctx = new (std::nothrow) dgx_ctx();
@@ -449,7 +456,7 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
         K.nr = r->nreactions;
         const dgx_species &sp = ctx->sp;
         for (int i = 0; i < K.nr; ++i) {
-            K.A[i] = r->A[i];
+            K.lnA[i] = std::log(r->A[i]);
             K.b[i] = r->b[i];
             K.tha[i] = r->theta_a[i];
             double sum = 0.0;
@@ -785,12 +792,25 @@ int dgx_max_dt(dgx_ctx *ctx, const double *u, double cfl, double *dt_host, void 
     return DGX_OK;
 }
 
-// Per-node iteration counts in ctx->iters (-1: not converged) -> stats.
-// Synchronises the stream.
-static int collect_stats(dgx_ctx *ctx, int64_t count, int maxit, dgx_newton_stats *stats, hipStream_t s) {
-    std::vector<int> h(count);
+// Per-node iteration counts in ctx->iters (-1: not converged), and substep
+// counts in ctx->subs when with_subs -> stats.  Synchronises the stream.
+static int collect_stats(dgx_ctx *ctx, int64_t count, int maxit, dgx_newton_stats *stats, hipStream_t s,
+                         bool with_subs = false) {
+    std::vector<int> h(count), hs;
     HIPCHK(hipMemcpyAsync(h.data(), ctx->iters.p, count * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (with_subs) {
+        hs.resize(count);
+        HIPCHK(hipMemcpyAsync(hs.data(), ctx->subs.p, count * sizeof(int), hipMemcpyDeviceToHost, s));
+    }
     HIPCHK(hipStreamSynchronize(s));
+    int64_t stot = 0;
+    int smax = 0;
+    for (int v : hs) {
+        stot += v;
+        smax = std::max(smax, v);
+    }
+    stats->substeps_total = stot;
+    stats->substeps_max = smax;
     int64_t tot = 0, bad = 0, first = -1;
     int mx = 0;
     double wsum = 0.0;
@@ -869,7 +889,8 @@ int dgx_chem_step(dgx_ctx *ctx, double *u, double dt, double tol, int maxit, dgx
     if (!(dt >= 0.0) || !(tol > 0.0) || maxit < 1) return set_err(ctx, DGX_E_INVAL, "bad dt, tol or maxit");
     hipStream_t s = (hipStream_t)stream;
     const int64_t count = (int64_t)ctx->nelem * ctx->nn;
-    if (stats && (rc = dalloc(ctx, ctx->iters, (size_t)count))) return rc;
+    if (stats && ((rc = dalloc(ctx, ctx->iters, (size_t)count)) || (rc = dalloc(ctx, ctx->subs, (size_t)count))))
+        return rc;
     // temperature of the incoming state: the warm start of the inner solves
     if ((rc = enqueue_thermo_mesh(ctx, u, s))) return set_err(ctx, rc, "thermo launch failed");
     int *iters = stats ? ctx->iters.p : nullptr;
@@ -877,15 +898,16 @@ int dgx_chem_step(dgx_ctx *ctx, double *u, double dt, double tol, int maxit, dgx
     const int blocks = (int)((count + tb - 1) / tb);
     const double ttol = 1e-14;
     const int tmaxit = 100;
+    int *subs = stats ? ctx->subs.p : nullptr;
     if (ctx->cfg.dim == 2)
         hipLaunchKernelGGL(k_chem<2>, dim3(blocks), dim3(tb), 0, s, u, count, dt, ctx->kin_d.p, ctx->mix, ctx->T.p, tol,
-                           maxit, ttol, tmaxit, iters, ctx->flags.p);
+                           maxit, ttol, tmaxit, iters, subs, ctx->flags.p);
     else
         hipLaunchKernelGGL(k_chem<3>, dim3(blocks), dim3(tb), 0, s, u, count, dt, ctx->kin_d.p, ctx->mix, ctx->T.p, tol,
-                           maxit, ttol, tmaxit, iters, ctx->flags.p);
+                           maxit, ttol, tmaxit, iters, subs, ctx->flags.p);
     if (hipGetLastError() != hipSuccess) return set_err(ctx, DGX_E_DEVICE, "chemistry launch failed");
     if (!stats) return DGX_OK;
-    return collect_stats(ctx, count, maxit, stats, s);
+    return collect_stats(ctx, count, maxit, stats, s, true);
 }
 
 const double *dgx_last_alpha(const dgx_ctx *ctx) {
@@ -1105,6 +1127,7 @@ void dgx_destroy(dgx_ctx *ctx) {
     ctx->mort.release();
     ctx->mflux.release();
     ctx->iters.release();
+    ctx->subs.release();
     ctx->tg.release();
     ctx->kin_d.release();
     ctx->flags.release();

@@ -29,7 +29,7 @@ struct MixC {
 // Reaction data (device memory, read with uniform addresses).
 struct KinC {
     int nr;
-    double A[kMaxR], b[kMaxR], tha[kMaxR];
+    double lnA[kMaxR], b[kMaxR], tha[kMaxR];  // ln of the pre-exponential factor
     double dnu_sum[kMaxR];          // sum_s (nu' - nu)
     int nu[kMaxR][kNS], nup[kMaxR][kNS];
     double W[kNS];

@@ -1,9 +1,9 @@
-// Per-node stiff chemistry: one backward-Euler step of the species sources
+// Per-node stiff chemistry: backward-Euler steps of the species sources
 // (Governing Equations, Eq. source_term; Appendix, Chemical Kinetics) with
 // the transport split off.  Density, momentum and total energy stay fixed,
-// hence so does rho e, and the species densities solve
+// hence so does rho e, and one step over h from rho_s^a solves
 //
-//   G(rho_s) = rho_s - rho_s^n - dt * omega_s(rho_s, T(rho_s, rho e)) = 0.
+//   G(rho_s) = rho_s - rho_s^a - h * omega_s(rho_s, T(rho_s, rho e)) = 0.
 //
 // Newton's method with the analytic Jacobian along the fixed-energy manifold,
 //   d omega_s / d rho_j = W_s sum_r dnu_rs [ (dR_r/dc_j) / W_j
@@ -16,6 +16,18 @@
 // previous one.  The step is limited so that densities stay non-negative and
 // the thermal energy rho e - sum_s rho_s e0_s stays positive; the iteration
 // stops when the full Newton step is below tol * rho.
+//
+// Substeps.  A growing mode (atom-impact dissociation grows [X] at a rate
+// k [X2]) makes I - h d omega/d rho singular as h times its growth rate
+// reaches 1; past that the root near rho^a is gone, the Newton step points
+// out of the admissible set and the positivity limit cuts it to nothing.  The
+// iteration has failed when that limit leaves less than kChemStall of the
+// step on two consecutive iterations (or after maxit iterations); the node
+// then covers dt with substeps dt / 2^k: a failed substep is retried at half
+// the size, and after a successful one the node goes back to the next larger
+// size when its position is a multiple of it.  Positions are integers in
+// units of dt / 2^kChemKmax; failing at the smallest size is
+// non-convergence.
 #pragma once
 
 #include "physics.h"
@@ -95,8 +107,9 @@ __device__ __forceinline__ void chem_sources(const KinC &K, const MixC &M, const
             dfw[j] = pf;
             dbw[j] = pb;
         }
-        const double kf = K.A[r] * exp(K.b[r] * lnT - K.tha[r] * iT);
-        const double kb = kf * exp(-lnK);
+        const double lnkf = fma(K.b[r], lnT, K.lnA[r]) - K.tha[r] * iT;
+        const double kf = exp(lnkf);
+        const double kb = exp(lnkf - lnK);  // k_f / K_c without the underflow of both at low T
         const double dlnkf = (K.b[r] + K.tha[r] * iT) * iT;
         const double R = kf * fw - kb * bw;
         const double dRdT = kf * fw * dlnkf - kb * bw * (dlnkf - dlnK);
@@ -161,49 +174,28 @@ __device__ __forceinline__ void solve5(double (*A)[kNS], double *b, double *x) {
     }
 }
 
-// One backward-Euler chemistry step per node, in place on the species rows
-// of u ([nvar][count], species first).  T holds the previous temperature on
-// entry (warm start) and the new one on exit; iters (optional) the Newton
-// iteration count, -1 if it did not converge.
-template <int DIM>
-__global__ void __launch_bounds__(256) k_chem(double *__restrict__ u, int64_t count, double dt, const KinC *kin,
-                                              MixC M, double *__restrict__ T, double tol, int maxit, double ttol,
-                                              int tmaxit, int *__restrict__ iters, unsigned *flags) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const KinC &K = *kin;
-    double r0[kNS], rs[kNS];
-    double rho = 0.0;
+constexpr int kChemKmax = 20;        // smallest substep dt / 2^20
+constexpr double kChemStall = 1e-3;  // a step cut below this fraction twice in a row has failed
+
+// Damped Newton for one backward-Euler step over h from ra into rs.  Tn: the
+// temperature of ra on entry, of rs on a converged exit.  Adds the
+// iterations to it; returns false if the iteration failed.
+__device__ __forceinline__ bool chem_newton(const KinC &K, const MixC &M, const double *ra, double *rs, double rho,
+                                            double rhoe, double h, double &Tn, double tol, int maxit, double ttol,
+                                            int tmaxit, int &it) {
 #pragma unroll
-    for (int s = 0; s < kNS; ++s) {
-        r0[s] = u[s * count + i];
-        rs[s] = r0[s];
-        rho += r0[s];
-    }
-    double m2 = 0.0;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-        const double m = u[(kNS + c) * count + i];
-        m2 = fma(m, m, m2);
-    }
-    const double rhoe = u[(kNS + DIM) * count + i] - 0.5 * m2 / rho;
-    double Tn = T[i];
-    int it = 0;
-    bool conv = false;
-    bool fail = false;
-    while (it < maxit) {
+    for (int s = 0; s < kNS; ++s) rs[s] = ra[s];
+    int low = 0;
+    for (int k = 0; k < maxit; ++k) {
         ++it;
-        if (mix_newton(M, rs, rhoe, Tn, ttol, tmaxit) < 0 || !(Tn > 0.0)) {
-            fail = true;
-            break;
-        }
+        if (mix_newton(M, rs, rhoe, Tn, ttol, tmaxit) < 0 || !(Tn > 0.0)) return false;
         double w[kNS], A[kNS][kNS], G[kNS], d[kNS];
         chem_sources(K, M, rs, Tn, w, A);
 #pragma unroll
         for (int s = 0; s < kNS; ++s) {
-            G[s] = -(rs[s] - r0[s] - dt * w[s]);
+            G[s] = -(rs[s] - ra[s] - h * w[s]);
 #pragma unroll
-            for (int j = 0; j < kNS; ++j) A[s][j] = (s == j ? 1.0 : 0.0) - dt * A[s][j];
+            for (int j = 0; j < kNS; ++j) A[s][j] = (s == j ? 1.0 : 0.0) - h * A[s][j];
         }
         solve5(A, G, d);
         // step limits: rho_s >= 0 and a positive thermal energy
@@ -218,21 +210,69 @@ __global__ void __launch_bounds__(256) k_chem(double *__restrict__ u, int64_t co
         if (de0 > 0.0) theta = fmin(theta, 0.9 * thermal / de0);
 #pragma unroll
         for (int s = 0; s < kNS; ++s) rs[s] = fma(theta, d[s], rs[s]);
-        if (!(dmax == dmax)) {
-            fail = true;
+        if (!(dmax == dmax)) return false;
+        if (dmax <= tol * rho) return mix_newton(M, rs, rhoe, Tn, ttol, tmaxit) >= 0;
+        low = theta < kChemStall ? low + 1 : 0;
+        if (low >= 2) return false;
+    }
+    return false;
+}
+
+// Chemistry over dt per node, in place on the species rows of u
+// ([nvar][count], species first).  T holds the incoming state's temperature
+// on entry (warm start) and the new one on exit; iters (optional) the Newton
+// iterations summed over the substeps, -1 if the node did not converge;
+// subs (optional) the number of substeps.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_chem(double *__restrict__ u, int64_t count, double dt, const KinC *kin,
+                                              MixC M, double *__restrict__ T, double tol, int maxit, double ttol,
+                                              int tmaxit, int *__restrict__ iters, int *__restrict__ subs,
+                                              unsigned *flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const KinC &K = *kin;
+    double ra[kNS];
+    double rho = 0.0;
+#pragma unroll
+    for (int s = 0; s < kNS; ++s) {
+        ra[s] = u[s * count + i];
+        rho += ra[s];
+    }
+    double m2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const double m = u[(kNS + c) * count + i];
+        m2 = fma(m, m, m2);
+    }
+    const double rhoe = u[(kNS + DIM) * count + i] - 0.5 * m2 / rho;
+    double Ta = T[i];
+    constexpr int unit = 1 << kChemKmax;
+    int pos = 0, lev = 0, it = 0, nsub = 0;
+    bool conv = true;
+    while (pos < unit) {
+        if (lev > kChemKmax) {
+            conv = false;
             break;
         }
-        if (dmax <= tol * rho) {
-            conv = true;
-            break;
+        double rs[kNS];
+        double Tn = Ta;
+        if (chem_newton(K, M, ra, rs, rho, rhoe, ldexp(dt, -lev), Tn, tol, maxit, ttol, tmaxit, it)) {
+#pragma unroll
+            for (int s = 0; s < kNS; ++s) ra[s] = rs[s];
+            Ta = Tn;
+            pos += unit >> lev;
+            ++nsub;
+            if (lev > 0 && (pos & ((unit >> (lev - 1)) - 1)) == 0) --lev;
+        } else {
+            ++lev;
         }
     }
-    if (conv && mix_newton(M, rs, rhoe, Tn, ttol, tmaxit) < 0) conv = false;
 #pragma unroll
-    for (int s = 0; s < kNS; ++s) u[s * count + i] = rs[s];
-    T[i] = Tn;
+    for (int s = 0; s < kNS; ++s) u[s * count + i] = ra[s];
+    T[i] = Ta;
     if (iters) iters[i] = conv ? it : -1;
-    if (!conv || fail) atomicOr(flags, FLAG_NOCONV);
+    if (subs) subs[i] = nsub;
+    if (!conv) atomicOr(flags, FLAG_NOCONV);
 }
 
 }  // namespace dgx

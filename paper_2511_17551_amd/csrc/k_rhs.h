@@ -686,8 +686,10 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                     for (int q = 0; q < nu; ++q) fw *= conc[s];
                     for (int q = 0; q < nup; ++q) bw *= conc[s];
                 }
-                const double kf = K.A[r] * pow(T, K.b[r]) * exp(-K.tha[r] * iT);
-                const double kb = kf / exp(lnK);
+                // k_b = k_f / K_c in log space: at low T both factors underflow
+                const double lnkf = fma(K.b[r], lnT, K.lnA[r]) - K.tha[r] * iT;
+                const double kf = exp(lnkf);
+                const double kb = exp(lnkf - lnK);
                 const double R = kf * fw - kb * bw;
 #pragma unroll
                 for (int s = 0; s < kNS; ++s) wdot[s] = fma((double)(K.nup[r][s] - K.nu[r][s]), R, wdot[s]);

@@ -63,7 +63,8 @@ class dgx_mesh(C.Structure):
 
 class dgx_newton_stats(C.Structure):
     _fields_ = [("nodes", C.c_int64), ("iters_total", C.c_int64), ("iters_max", C.c_int32),
-                ("iters_wave_max_mean", C.c_double), ("nonconverged", C.c_int64), ("first_bad", C.c_int64)]
+                ("iters_wave_max_mean", C.c_double), ("nonconverged", C.c_int64), ("first_bad", C.c_int64),
+                ("substeps_total", C.c_int64), ("substeps_max", C.c_int32)]
 
 
 def _load():
@@ -243,8 +244,9 @@ def dgx_thermo(ctx, u, T, p=None, guess=GUESS_FREESTREAM, nstates=0, stream=None
                 first_bad=st.first_bad, rc=rc)
 
 
-def dgx_chem_step(ctx, u, dt, tol=1e-13, maxit=100, stream=None, check=True, stats=True):
-    """Backward-Euler chemistry step in place on u's species rows."""
+def dgx_chem_step(ctx, u, dt, tol=1e-13, maxit=50, stream=None, check=True, stats=True):
+    """Backward-Euler chemistry over dt (substeps where the single step
+    fails) in place on u's species rows."""
     if not stats:
         _raise(ctx, lib.dgx_chem_step(ctx, _dev(u), float(dt), float(tol), int(maxit), None, _stream(stream)))
         return None
@@ -254,7 +256,7 @@ def dgx_chem_step(ctx, u, dt, tol=1e-13, maxit=100, stream=None, check=True, sta
         _raise(ctx, rc)
     return dict(nodes=st.nodes, iters_total=st.iters_total, iters_max=st.iters_max,
                 iters_wave_max_mean=st.iters_wave_max_mean, nonconverged=st.nonconverged,
-                first_bad=st.first_bad, rc=rc)
+                first_bad=st.first_bad, substeps_total=st.substeps_total, substeps_max=st.substeps_max, rc=rc)
 
 
 def dgx_last_alpha(ctx, nelem):

@@ -1,9 +1,13 @@
 """Per-node backward-Euler chemistry on the GPU (dgx_chem_step) against the
-oracle: one step at mild, stiff and near-equilibrium step sizes on the hot
+oracle: one call at mild, stiff and near-equilibrium step sizes on the hot
 cylinder state (species densities node by node, conservation of mass and
-atoms, momentum and energy untouched, the temperature left in the library),
-and Strang-split reacting steps: half a chemistry step, one frozen-mixture
-SSPRK3 step with the positivity limiter, half a chemistry step."""
+atoms, momentum and energy untouched, the temperature left in the library);
+seeded far-from-equilibrium compositions where many nodes need substeps
+(node by node, and the substep counts); Strang-split reacting steps (half a
+chemistry step, one frozen-mixture SSPRK3 step with the positivity limiter,
+half a chemistry step) on the hot state; and the impulsively started
+64 x 128 cylinder run reacting for 20 Strang steps, every node converging,
+with sampled nodes of its chemistry calls checked against the oracle."""
 import numpy as np
 import pytest
 
@@ -51,10 +55,10 @@ def oracle_chem(c, u, dt):
     m = flat[5:7]
     rhoe = flat[7] - 0.5 * (m * m).sum(0) / rho
     T0, _ = mix.solve_T(rs0, rhoe, c.cfg["T_guess"])
-    rs, T, it = backward_euler(mix, kin, rs0, rhoe, dt, T0)
+    rs, T, it, nsub = backward_euler(mix, kin, rs0, rhoe, dt, T0)
     out = flat.copy()
     out[:5] = rs
-    return out.reshape(u.shape), T, it
+    return out.reshape(u.shape), T, it, nsub
 
 
 @pytest.mark.parametrize("dt", [1e-12, 1e-9, 1e-6])
@@ -62,7 +66,7 @@ def test_chem_step_matches_oracle(dgx, thermo_fns, dt):
     import torch
     c = frozen_case(thermo_fns, 8, 16)
     print("case", c.name, "dt", dt, flush=True)
-    ref, Tref, it = oracle_chem(c, c.u0, dt)
+    ref, Tref, it, nsub = oracle_chem(c, c.u0, dt)
     s = dgx.Solver(c)
     u = to_dev(c.u0)
     st = dgx.dgx_chem_step(s.ctx, u, dt)
@@ -78,6 +82,7 @@ def test_chem_step_matches_oracle(dgx, thermo_fns, dt):
     print("chem dt %.0e: max |drho_s|/rho gpu-oracle %.3e, change %.3e, iters gpu max %d mean %.2f, oracle max %d"
           % (dt, err, moved, st["iters_max"], st["iters_total"] / st["nodes"], it.max()))
     assert st["nonconverged"] == 0
+    assert st["substeps_total"] == nsub.sum() and st["substeps_max"] == nsub.max()
     assert err < 1e-11
     assert moved > 1e-6
     assert np.array_equal(got[5:], c.u0[5:])
@@ -116,3 +121,83 @@ def test_strang_split_steps(dgx, thermo_fns):
     print("strang 3 steps dt %.3e rel err %.3e, species change %.3e"
           % (dt, rel_err(got, ref), np.abs(ref[:5] - c.u0[:5]).max() / c.u0[:5].sum(0).max()))
     assert rel_err(got, ref) < 1e-9
+
+
+@pytest.mark.parametrize("dt", [1e-9, 1e-7, 1e-5])
+def test_far_from_equilibrium_states(dgx, thermo_fns, dt):
+    """2048 seeded compositions far from equilibrium at rest (rho E = rho e),
+    laid on the 8 x 16 cylinder mesh: species node by node and the substep
+    counts against the oracle."""
+    c = frozen_case(thermo_fns, 8, 16)
+    nvar, nelem, nn = c.u0.shape
+    rs, T = W.far_chem_states(nelem * nn, seed=11)
+    u0 = np.zeros_like(c.u0)
+    u0[:5] = rs.reshape(5, nelem, nn)
+    u0[7] = thermo_fns[0](rs, T).reshape(nelem, nn)
+    print("far states dt", dt, flush=True)
+    ref, Tref, it, nsub = oracle_chem(c, u0, dt)
+    s = dgx.Solver(c)
+    u = to_dev(u0)
+    st = dgx.dgx_chem_step(s.ctx, u, dt)
+    s.check()
+    got = to_host(u)
+    s.close()
+    rho = u0[:5].sum(0)
+    err = np.max(np.abs(got[:5] - ref[:5]) / rho[None])
+    print("far dt %.0e: max |drho_s|/rho %.3e, substeps gpu total %d max %d, oracle total %d max %d, multi %d"
+          % (dt, err, st["substeps_total"], st["substeps_max"], nsub.sum(), nsub.max(), (nsub > 1).sum()))
+    assert st["nonconverged"] == 0
+    assert (nsub > 1).sum() > 10
+    assert st["substeps_total"] == nsub.sum() and st["substeps_max"] == nsub.max()
+    assert err < 1e-11
+    assert np.array_equal(got[5:], u0[5:])
+    assert np.all(got[:5] >= 0.0)
+
+
+def test_impulsive_start_reacting_run(dgx):
+    """The full-size reacting cylinder from its impulsive start: 20 Strang
+    steps at CFL 0.2; every chemistry call converges on every node, and in
+    the calls of steps 2 and 19 the 256 nodes that change most, plus 256
+    drawn at random (seed 5), match the oracle."""
+    import torch
+    probe = W.case_c4(lambda rs, T: 0 * T, lambda rs, T: 1 + 0 * T, nr=4, nth=8)
+    pctx = dgx.dgx_create(probe.cfg, probe.species, probe.reactions)
+    energy, cv = dgx.mixture_energy_fns(pctx)
+    c = W.case_c4(energy, cv)
+    dgx.dgx_destroy(pctx)
+    c.cfg = dict(c.cfg, eq=W.EQ_EULER_MIX)
+    mix = Mixture(c.species)
+    kin = Kinetics(c.species, c.reactions)
+    s = dgx.Solver(c)
+    u = to_dev(c.u0)
+    dt = dgx.dgx_max_dt(s.ctx, u, 0.2)
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    subs = 0
+    for step in range(20):
+        for half in (0, 1):
+            check = step in (2, 19) and half == 1
+            before = to_host(u) if check else None
+            st = dgx.dgx_chem_step(s.ctx, u, 0.5 * dt)
+            assert st["nonconverged"] == 0, (step, half, st)
+            subs = max(subs, st["substeps_max"])
+            if check:
+                after = to_host(u)
+                fb, fa = before.reshape(8, -1), after.reshape(8, -1)
+                rho = fb[:5].sum(0)
+                change = np.abs(fa[:5] - fb[:5]).max(0) / rho
+                pick = np.unique(np.concatenate([np.argsort(change)[-256:], rng.choice(rho.size, 256, replace=False)]))
+                m2 = (fb[5:7, pick] ** 2).sum(0)
+                rhoe = fb[7, pick] - 0.5 * m2 / rho[pick]
+                T0, _ = mix.solve_T(fb[:5, pick], rhoe, c.cfg["T_guess"] + 0 * rhoe)
+                ref, _, _, _ = backward_euler(mix, kin, fb[:5, pick], rhoe, 0.5 * dt, T0)
+                err = np.max(np.abs(fa[:5, pick] - ref) / rho[pick][None])
+                print("step %d: sampled %d nodes, largest change %.3e, max |drho_s|/rho %.3e"
+                      % (step, pick.size, change.max(), err), flush=True)
+                worst = max(worst, err)
+            if half == 0:
+                s.ssprk3(u, dt, 1)
+    s.check()
+    s.close()
+    print("impulsive start: 20 Strang steps, max substeps %d, worst sampled error %.3e" % (subs, worst))
+    assert worst < 1e-11
