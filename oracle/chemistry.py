@@ -31,14 +31,22 @@ rate k [X2]) turns the step's Jacobian singular as h times the growth rate
 reaches 1; beyond that the root near rho^a is gone and the Newton step
 points out of the admissible set, so the positivity limit shrinks it to
 nothing.  Such a Newton iteration is declared failed when the limit cuts the
-step to below STALL of its length on two consecutive iterations (or after
-maxit iterations), and the node then covers the step with backward-Euler
+step to below STALL of its length on two consecutive iterations, or after
+maxit iterations, and the node then covers the step with backward-Euler
 substeps of dt / 2^k: a failed substep is retried at half the size, and
 after a successful one the node returns to the next larger size when its
 position in the step is a multiple of it.  Positions are kept as integers in
 units of dt / 2^KMAX; a node that fails at the smallest size does not
 converge.  Where the single step converges (the usual case) the result is
 that step's root.
+
+Rounding.  Far from equilibrium a Newton iteration can wander for tens of
+iterations before it converges; its path then depends on rounding (of the
+Jacobian above all), and so may whether it lands within maxit.  Two
+implementations of this procedure can therefore take different substep
+sequences at such a node: both results are backward-Euler integrations over
+dt, they differ by the substeps' truncation error, and both keep every
+invariant.
 """
 import numpy as np
 
@@ -112,9 +120,8 @@ def newton(mix, kin, rs0, rhoe, dt, T0, tol=1e-13, maxit=50):
         T[idx] = Ta
         it[idx] += 1
         # converged when the full (undamped) Newton step is below tolerance
-        done = np.max(np.abs(delta), axis=0) <= tol * rhoa
+        done = (np.max(np.abs(delta), axis=0) <= tol * rhoa) & ~nan
         low[idx] = np.where(theta < STALL, low[idx] + 1, 0)
-        done &= ~nan
         stalled = nan | (~done & (low[idx] >= 2))
         ok[idx[done]] = True
         active[idx[done | stalled]] = False

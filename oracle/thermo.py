@@ -40,8 +40,10 @@ class Mixture:
         out = np.array(np.broadcast_to(e, (self.ns,) + np.shape(T)))
         for s in range(self.ns):
             if self.mol[s]:
+                # R theta/(e^x - 1), x = theta/T, in the overflow-free form
+                # R theta e^-x / (1 - e^-x)
                 x = self.th[s] / T
-                out[s] = out[s] + self.Rs[s] * T + self.Rs[s] * self.th[s] / np.expm1(x)
+                out[s] = out[s] + self.Rs[s] * T + self.Rs[s] * self.th[s] * np.exp(-x) / (-np.expm1(-x))
         return out
 
     def cv_species(self, T):
@@ -64,7 +66,11 @@ class Mixture:
         return np.sum(rs * self.cv_species(T), axis=0)
 
     def solve_T(self, rs, rhoe, T0, tol=1e-10, maxit=50, strict=True):
-        """Per-node Newton iteration; every node stops on its own test.
+        """Per-node Newton iteration; every node stops on its own test:
+        |dT| <= tol * |T|, or a residual at the rounding level of the
+        energies it is made of, |rho e(T) - target| <= 8 eps (|target| +
+        sum_s |rho_s e0_s|) (a thermal energy of that size, T ~ 1e-10 K, is
+        determined no better than that).
 
         Returns T and the iteration count per node.  A node that fails to
         converge within maxit raises, or with strict=False gets T = NaN.
@@ -75,6 +81,7 @@ class Mixture:
         T = np.array(np.broadcast_to(T0, shape), float).reshape(-1)
         it = np.zeros(T.shape, np.int64)
         active = np.ones(T.shape, bool)
+        floor = 8.0 * np.finfo(float).eps * (np.abs(target) + (np.abs(rs) * np.abs(self.e0)[:, None]).sum(0))
         for _ in range(maxit):
             if not active.any():
                 break
@@ -87,7 +94,7 @@ class Mixture:
             Tn = Ta - dT
             T[idx] = Tn
             it[idx] += 1
-            done = np.abs(dT) <= tol * np.abs(Tn)
+            done = (np.abs(dT) <= tol * np.abs(Tn)) | (np.abs(f) <= floor[idx])
             active[idx[done]] = False
         if active.any():
             if strict:

@@ -1,7 +1,9 @@
 """Pins of the oracle's RRHO thermodynamics, T(e) Newton and kinetics.
 
 Thermodynamics: round trip T -> e -> T; atoms-only closed form; the
-theta_v -> infinity limit; cv as the derivative of e.  Kinetics: total mass
+theta_v -> infinity limit; cv as the derivative of e; T(e) of a thermal
+energy at the rounding level of the formation energies (near-vacuum gas),
+where e is linear in T.  Kinetics: total mass
 and element conservation of the sources, detailed balance at the
 equilibrium composition fixed by K_c, and the Gibbs-Helmholtz relation
 d(g_s/T)/dT = -h_s/T^2 (which pins the signs of every modal Gibbs term).
@@ -61,6 +63,28 @@ def test_frozen_vibration_limit():
     Rs = sp.Ru / sp.W
     assert np.allclose(m.rho_e(rs, T), 2.5 * Rs[0] * T + sp.e0[0], rtol=1e-14)
     assert np.allclose(m.rho_cv(rs, T), 2.5 * Rs[0], rtol=1e-14)
+
+
+def test_solve_at_rounding_level_thermal_energy(mix):
+    """Air with trace NO and atoms whose thermal energy rho e - sum rho_s e0_s
+    is 1e-10 J/m^3 (T ~ 1e-11 K, as the positivity limiter allows in a
+    near-vacuum wake).  Vibration is frozen there, so e is linear in T:
+    T = thermal / sum_s rho_s cv_s(0), cv_s(0) = 2.5 R_s (molecules) or
+    1.5 R_s (atoms).  The solve converges, to the precision the data carry."""
+    sp = W.Species()
+    Rs = sp.Ru / sp.W
+    Y = np.array([0.767, 0.233, 1.7e-7, 3.3e-11, 4.1e-8])
+    rho = np.array([1.2e-2, 3.6e-4])
+    rs = Y[:, None] * rho
+    thermal = np.array([1.5e-10, 8.4e-11])
+    rhoe = (rs * sp.e0[:, None]).sum(0) + thermal
+    T, it = mix.solve_T(rs, rhoe, 300.0, tol=1e-14, maxit=100)
+    cv0 = np.where(sp.molecule == 1, 2.5, 1.5) * Rs
+    Tc = thermal / (rs * cv0[:, None]).sum(0)
+    assert np.all(T > 0.0)
+    # the thermal energy is known to ~eps * sum rho_s e0_s / thermal relative
+    noise = 8 * np.finfo(float).eps * (rs * sp.e0[:, None]).sum(0) / thermal
+    assert np.all(np.abs(T - Tc) / Tc <= 4 * noise + 1e-12)
 
 
 def test_cv_is_de_dT(mix):
