@@ -223,14 +223,18 @@ int dgx_thermo(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double
  * manifold; every iterate's T comes from the T(e) solve warm-started at the
  * previous one (first: the incoming state's T); steps are limited so that
  * rho_s >= 0 and the thermal energy rho e - sum rho_s e0_s stays positive;
- * the iteration stops when its full Newton step is below tol * rho and fails
- * after maxit iterations or when the limits cut the step below 1e-3 of its
- * length on two consecutive iterations (a growing mode with dt times its
- * growth rate near or above 1).  A node whose single step fails covers dt
+ * the iteration stops when its full Newton step is below tol * rho; it fails
+ * when the limits cut the step below 1e-3 of its length on two consecutive
+ * iterations (a growing mode with dt times its growth rate near or above 1)
+ * or after maxit iterations.  A node whose single step fails covers dt
  * with substeps dt/2^k (k <= 20): a failed substep is retried at half the
  * size, and after a successful one the node returns to the next larger size
  * when its position in dt is a multiple of it.  A node that fails at dt/2^20
- * keeps its last accepted substep and counts as non-converged.  The
+ * keeps its last accepted substep and counts as non-converged.  (Far from
+ * equilibrium a Newton iteration can wander for tens of iterations, and
+ * whether it lands within maxit then depends on rounding: another
+ * implementation may take a different substep sequence at such a node, a
+ * result that differs by the substeps' truncation error.)  The
  * library's per-node temperature is left at the new state's T.  Enqueues on
  * stream; with stats (host) it synchronises and fills the iteration and
  * substep statistics (DGX_E_NOCONV if a node failed), with stats == NULL

@@ -114,15 +114,24 @@ __device__ __forceinline__ void mix_energy_cv(const MixC &M, const double *rs, d
 }
 
 // Newton iteration on sum rho_s e_s(T) = rho e, from T0; returns iterations,
-// or -1 if maxit was reached.
+// or -1 if maxit was reached.  Stops when |dT| <= tol*T, or when the residual
+// is at the rounding level of the energies it is made of (8 eps times
+// |rho e| + sum_s |rho_s e0_s|): where the thermal energy is itself that small
+// (near-vacuum gas left by the positivity limiter, T of order 1e-10 K) no
+// iterate meets a relative test, and T is as accurate as the data allow.
 __device__ __forceinline__ int mix_newton(const MixC &M, const double *rs, double rhoe_target,
                                           double &T, double tol, int maxit) {
+    double floor = fabs(rhoe_target);
+#pragma unroll
+    for (int s = 0; s < kNS; ++s) floor = fma(fabs(rs[s]), fabs(M.e0[s]), floor);
+    floor *= 8.0 * 2.220446049250313e-16;
     for (int it = 1; it <= maxit; ++it) {
         double f, fp;
         mix_energy_cv(M, rs, T, f, fp);
-        const double dT = (f - rhoe_target) / fp;
+        const double r = f - rhoe_target;
+        const double dT = r / fp;
         T -= dT;
-        if (fabs(dT) <= tol * fabs(T)) return it;
+        if (fabs(dT) <= tol * fabs(T) || fabs(r) <= floor) return it;
     }
     return -1;
 }
