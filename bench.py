@@ -102,11 +102,13 @@ def recorded_traffic():
 def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=16, reps=5):
     """Per-node T(e): surrogate-guided vs plain Newton on solver-generated states.
 
-    States: a frozen-chemistry run of the Mach-8 cylinder O-grid (64 x 128,
-    N = 3, positivity limiter, CFL 0.2), snapshots every 20 SSPRK3 steps ->
-    16 x 131072 = 2,097,152 states.  Labels: the plain solve's converged T.
-    The per-node backward-Euler chemistry step is timed separately on the
-    hot, partly dissociated cylinder state (same mesh, dt = 1e-9 s).
+    States: a reacting run of the impulsively started Mach-8 cylinder O-grid
+    (64 x 128, N = 3, positivity limiter, CFL 0.2), each step Strang-split
+    (chemistry over dt/2, one frozen-mixture SSPRK3 step, chemistry over
+    dt/2), snapshots every 20 steps -> 16 x 131072 = 2,097,152 states.
+    Labels: the plain solve's converged T.  The chemistry call is timed on
+    the run's last state (its dt/2) and on the hot, partly dissociated
+    cylinder state (same mesh, dt = 1e-9 s).
     The surrogate is trained on the same set (Adam, batch 4096), then both
     solves are timed (HIP events, same stream, same 1e-10 tolerance).
     """
@@ -122,34 +124,51 @@ def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=16, reps=5
     dt = dgx.dgx_max_dt(s.ctx, u, 0.2)
     snaps = []
     for _ in range(snapshots):
-        s.ssprk3(u, dt, steps_per_snap)
+        for _ in range(steps_per_snap):
+            dgx.dgx_chem_step(s.ctx, u, 0.5 * dt, stats=False)
+            s.ssprk3(u, dt, 1)
+            dgx.dgx_chem_step(s.ctx, u, 0.5 * dt, stats=False)
         snaps.append(u.reshape(u.shape[0], -1).clone())
     s.check()
-    # the chemistry step on the hot cylinder state (fresh copies each time)
+    e0, e1 = _events(torch)
+
+    def time_chem(ctx, src, cdt):
+        """Chemistry over cdt on fresh copies of src: (stats, ms)."""
+        uc = src.clone()
+        st = dgx.dgx_chem_step(ctx, uc, cdt)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            uc.copy_(src)
+            dgx.dgx_chem_step(ctx, uc, cdt, stats=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        e0.record()
+        for _ in range(reps):
+            uc.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        return st, ms - e0.elapsed_time(e1) / reps
+
+    def chem_summary(st, cdt, ms):
+        return dict(nodes=int(st["nodes"]), dt=cdt, ms=round(ms, 4),
+                    iters_mean=round(st["iters_total"] / st["nodes"], 3), iters_max=int(st["iters_max"]),
+                    wave_max_mean=round(st["iters_wave_max_mean"], 3),
+                    substeps_max=int(st["substeps_max"]),
+                    extra_substeps=int(st["substeps_total"] - st["nodes"]))
+
+    run_st, run_ms = time_chem(s.ctx, u, 0.5 * dt)
+    s.check()
+    # the chemistry step on the hot cylinder state
     hot.cfg["eq"] = W.EQ_EULER_MIX
     sh = dgx.Solver(hot)
     uh = torch.from_numpy(hot.u0).to("cuda")
-    uc = uh.clone()
     chem_dt = 1e-9
-    chem_stats = dgx.dgx_chem_step(sh.ctx, uc, chem_dt)
-    e0, e1 = _events(torch)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        uc.copy_(uh)
-        dgx.dgx_chem_step(sh.ctx, uc, chem_dt, stats=False)
-    e1.record()
-    torch.cuda.synchronize()
-    chem_ms = e0.elapsed_time(e1) / reps
-    e0.record()
-    for _ in range(reps):
-        uc.copy_(uh)
-    e1.record()
-    torch.cuda.synchronize()
-    chem_ms -= e0.elapsed_time(e1) / reps
+    chem_stats, chem_ms = time_chem(sh.ctx, uh, chem_dt)
     sh.check()
     sh.close()
-    del uh, uc
+    del uh
     states = torch.cat(snaps, 1).contiguous()
     del snaps
     n = states.shape[1]
@@ -161,7 +180,13 @@ def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=16, reps=5
     train_s = time.perf_counter() - t0
     Ts = torch.empty_like(T)
     st_sur = dgx.dgx_thermo(s.ctx, states, Ts, nstates=n, guess=dgx.GUESS_SURROGATE)
-    maxrel = float(((Ts - T).abs() / T).max())
+    # relative agreement of the converged temperatures, over states above 1 K:
+    # in the near-vacuum wake of the impulsive start the positivity limiter
+    # leaves thermal energies at the rounding level of the formation
+    # energies (T ~ 1e-11 K), where T is determined only to that level
+    phys = T > 1.0
+    maxrel = float(((Ts - T).abs() / T)[phys].max())
+    near_vacuum = int((~phys).sum())
     Tg = torch.empty_like(T)
     res = {}
     for name, guess in (("plain", dgx.GUESS_FREESTREAM), ("surrogate", dgx.GUESS_SURROGATE)):
@@ -207,7 +232,7 @@ def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=16, reps=5
                 iters_mean_surrogate=round(st_sur["iters_total"] / n, 3),
                 wave_max_mean_plain=round(st_plain["iters_wave_max_mean"], 3),
                 wave_max_mean_surrogate=round(st_sur["iters_wave_max_mean"], 3),
-                max_rel_T_diff=maxrel, median_rel_guess_err=guess_err,
+                max_rel_T_diff=maxrel, near_vacuum_states=near_vacuum, median_rel_guess_err=guess_err,
                 disturbed=dict(states=int(nsub), plain_ms=round(sub_ms["plain"], 4),
                                surrogate_ms=round(sub_ms["surrogate"], 4),
                                speedup=round(sub_ms["plain"] / sub_ms["surrogate"], 3),
@@ -217,10 +242,9 @@ def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=16, reps=5
                                wave_max_mean_surrogate=round(ss_sub["iters_wave_max_mean"], 3)),
                 train_epochs=epochs, train_s=round(train_s, 2), loss_first=float(losses[0]),
                 loss_last=float(losses[-1]), tol=1e-10,
-                chemistry=dict(nodes=int(chem_stats["nodes"]), dt=chem_dt, ms=round(chem_ms, 4),
-                               iters_mean=round(chem_stats["iters_total"] / chem_stats["nodes"], 3),
-                               iters_max=int(chem_stats["iters_max"]),
-                               wave_max_mean=round(chem_stats["iters_wave_max_mean"], 3)))
+                chemistry=dict(hot_state=chem_summary(chem_stats, chem_dt, chem_ms),
+                               reacting_run=chem_summary(run_st, 0.5 * dt, run_ms),
+                               strang_steps=snapshots * steps_per_snap))
 
 
 def c3_bytes_per_launch(nelem, nn, nvar, dim, stage_base=True):
