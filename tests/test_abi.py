@@ -1,12 +1,14 @@
 """The C-ABI boundary without a GPU: the shared library loads, exports every
 function include/dgx.h declares (C linkage, unmangled), and the Python
-binding wraps each of them under the same name.  No compute call is made.
+binding wraps each of them under the same name; unsupported configurations
+are rejected (DGX_E_INVAL) before any device work.  No compute call is made.
 """
 import ctypes
 import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -61,3 +63,46 @@ def test_errors_without_a_context(lib_path):
     lib.dgx_create.restype = ctypes.c_int
     lib.dgx_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     assert lib.dgx_create(None, None) < 0
+
+
+def bad_configs():
+    """Unsupported configurations; each must be rejected before any device
+    work, so the check runs without a GPU."""
+    from paper_2511_17551_amd import workloads as W
+    pg = W.case_c2(n=1).cfg
+    mix = W.base_cfg(3, 4, W.EQ_EULER_MIX, volume_flux=W.VF_DUCROS)
+    react = W.base_cfg(2, 3, W.EQ_REACT_MIX, volume_flux=W.VF_DUCROS)
+    sp = W.Species()
+    rx = W.park17_reactions(4)
+
+    def table(A=None, rows=None):
+        r = rows if rows is not None else np.arange(rx.nreactions)
+        return W.Reactions(A=rx.A[r] if A is None else A, b=rx.b[r], theta_a=rx.theta_a[r], nu=rx.nu[r], nup=rx.nup[r])
+
+    bad_A = rx.A.copy()
+    bad_A[3] = 0.0
+    inf_A = rx.A.copy()
+    inf_A[0] = np.inf
+    return [
+        ("dim 1", dict(pg, dim=1), None, None),
+        ("N 2", dict(pg, N=2), None, None),
+        ("N 5", dict(pg, N=5), None, None),
+        ("equation 7", dict(pg, eq=7), None, None),
+        ("gamma 1", dict(pg, gamma=1.0), None, None),
+        ("negative viscosity", dict(pg, mu=-1.0), None, None),
+        ("mixture without species", mix, None, None),
+        ("mixture with the Ranocha flux", dict(mix, volume_flux=W.VF_RANOCHA), sp, None),
+        ("reacting mixture without reactions", react, sp, None),
+        ("A = 0", react, sp, table(A=bad_A)),
+        ("A = inf", react, sp, table(A=inf_A)),
+        ("no reactions", react, sp, table(rows=np.arange(0))),
+        ("33 reactions", react, sp, table(rows=np.concatenate([np.arange(17), np.arange(16)]))),
+    ]
+
+
+def test_create_rejects_unsupported_configurations(lib_path):
+    from paper_2511_17551_amd import dgx
+    for name, cfg, sp, rx in bad_configs():
+        with pytest.raises(dgx.DgxError) as ei:
+            dgx.dgx_create(cfg, sp, rx)
+        assert dgx.ERRORS[ei.value.code] == "DGX_E_INVAL", name
