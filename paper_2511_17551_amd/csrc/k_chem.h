@@ -219,12 +219,16 @@ __device__ __forceinline__ bool chem_newton(const KinC &K, const MixC &M, const 
 }
 
 // Chemistry over dt per node, in place on the species rows of u
-// ([nvar][count], species first).  T holds the incoming state's temperature
+// ([nvar][count], species first).  Two waves per SIMD: the Newton state,
+// the 5x5 Jacobian and the per-reaction terms need about 280 registers, and
+// one wave per SIMD leaves the long dependency chains (T solve, rates,
+// elimination) unhidden; the compiler spills 33 VGPRs at this bound, a
+// better trade (1.45x on the 131,072-node cylinder) than one wave.  T holds the incoming state's temperature
 // on entry (warm start) and the new one on exit; iters (optional) the Newton
 // iterations summed over the substeps, -1 if the node did not converge;
 // subs (optional) the number of substeps.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_chem(double *__restrict__ u, int64_t count, double dt, const KinC *kin,
+__global__ void __launch_bounds__(256, 2) k_chem(double *__restrict__ u, int64_t count, double dt, const KinC *kin,
                                               MixC M, double *__restrict__ T, double tol, int maxit, double ttol,
                                               int tmaxit, int *__restrict__ iters, int *__restrict__ subs,
                                               unsigned *flags) {
