@@ -358,6 +358,13 @@ std::string tune_key(const dgx_ctx *ctx) {
 bool epb_fits(const dgx_ctx *ctx, int epb) {
     if (epb < 1 || epb > 8 || !ctx->rhs) return false;
     if (threads_for(ctx->nn, epb) > 512) return false;
+    if (ctx->cfg.equation == DGX_EQ_NS) {
+        // the gradient kernel's slot (GradShape): own W and face traces, then
+        // the contravariant fluxes of all directions
+        const int dim = ctx->cfg.dim, nw = dim + 1, nsf = 2 * dim * ctx->nf;
+        const size_t gslot = std::max<size_t>((size_t)nw * ctx->nn + (size_t)nw * nsf, (size_t)dim * nw * ctx->nn);
+        if ((size_t)epb * gslot * sizeof(double) > 64 * 1024) return false;
+    }
     return (size_t)epb * ctx->rhs->slot * sizeof(double) <= 64 * 1024;
 }
 

@@ -27,8 +27,10 @@ struct GradShape {
     static constexpr int NF = NN / N1;
     static constexpr int NW = DIM + 1;
     static constexpr int NSF = 2 * DIM * NF;
-    // own W (and later Ft^d), neighbours' face traces of W
-    static constexpr int SLOT = NW * NN + NW * NSF;
+    // own W and the neighbours' face traces of W; later the contravariant
+    // viscous fluxes of all directions
+    static constexpr int SLOT0 = NW * NN + NW * NSF;
+    static constexpr int SLOT = SLOT0 > DIM * NW * NN ? SLOT0 : DIM * NW * NN;
 };
 
 template <int DIM, int N>
@@ -180,28 +182,29 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
             Fv[c][DIM] = en + P.kappa * q[c][DIM];
         }
     }
-    // divergence: volume part and the element's own half of the face terms
+    // divergence: volume part and the element's own half of the face terms.
+    // All directions' contravariant fluxes go to LDS at once.
     double vis[NW];
 #pragma unroll
     for (int k = 0; k < NW; ++k) vis[k] = 0.0;
     double *ff = P.out2;
+    double *ft = smem + el * S::SLOT;  // [DIM][NW][NN]
+    __syncthreads();  // the gradient's readers of sw and sn are done
+    if (valid) {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        double Ft[NW];
+        for (int d = 0; d < DIM; ++d)
 #pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            double s = 0.0;
+            for (int k = 0; k < NW; ++k) {
+                double s = 0.0;
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) s = fma(Ja[d * DIM + c], Fv[c][k], s);
-            Ft[k] = s;
-        }
-        __syncthreads();  // previous readers of sw are done
-        if (valid) {
+                for (int c = 0; c < DIM; ++c) s = fma(Ja[d * DIM + c], Fv[c][k], s);
+                ft[(d * NW + k) * NN + node] = s;
+            }
+    }
+    __syncthreads();
+    if (valid) {
 #pragma unroll
-            for (int k = 0; k < NW; ++k) sw[k * NN + node] = Ft[k];
-        }
-        __syncthreads();
-        if (valid) {
+        for (int d = 0; d < DIM; ++d) {
             const int a = node_pos<N1>(node, d);
             const int l = node_line<N1, DIM>(node, d);
 #pragma unroll
@@ -209,7 +212,7 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
                 const double Dj = sD[a * N1 + j];
                 const int nj = line_node<N1, DIM>(d, j, l);
 #pragma unroll
-                for (int k = 0; k < NW; ++k) vis[k] = fma(Dj, sw[k * NN + nj], vis[k]);
+                for (int k = 0; k < NW; ++k) vis[k] = fma(Dj, ft[(d * NW + k) * NN + nj], vis[k]);
             }
             if (a == 0 || a == N) {
                 const int side = (a == N) ? 1 : 0;
@@ -217,8 +220,9 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
                 double *fo = ff + ((size_t)e * 2 * DIM + 2 * d + side) * NW * NF + l;
 #pragma unroll
                 for (int k = 0; k < NW; ++k) {
-                    vis[k] = fma(sc, Ft[k], vis[k]);
-                    fo[k * NF] = Ft[k];
+                    const double Ftk = ft[(d * NW + k) * NN + node];
+                    vis[k] = fma(sc, Ftk, vis[k]);
+                    fo[k * NF] = Ftk;
                 }
             }
         }
