@@ -172,7 +172,12 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out);
 /* Upload a mesh: the library computes its own LGL operators, metric terms
  * (2D cross form, 3D conservative curl form), Jacobians, face normals and
  * subcell normals (Eqs. mapp, mapped_equation, jacobian).  May be called
- * again to replace the mesh.  Synchronous. */
+ * again to replace the mesh.  A mesh that fails its checks (DGX_E_INVAL:
+ * no elements, a face row that is not a (+d, -d) pair, an index out of
+ * range, a face without neighbour or boundary, a non-positive Jacobian, a
+ * combination without a kernel variant) leaves the context's previous mesh
+ * in place; a failure after the checks (device allocation or copy) leaves
+ * the context without a mesh (DGX_E_STATE until one is set).  Synchronous. */
 int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *mesh);
 
 /* du = L(u, t): the DGSEM right-hand side (Eq. strong_form with the

@@ -524,9 +524,8 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
     if (m->nmortar < 0 || (m->nmortar && !m->mortars)) return set_err(ctx, DGX_E_INVAL, "bad mortar table");
     if (m->nmortar && ctx->cfg.equation != DGX_EQ_EULER)
         return set_err(ctx, DGX_E_INVAL, "mortars are supported for the perfect-gas Euler equations");
-    clear_graph(ctx);
-    ctx->mesh_ok = false;
-    // connectivity
+    // connectivity (every check below runs before the context changes, so a
+    // rejected mesh leaves the previous one in place)
     std::vector<int> nbr((size_t)E * 2 * dim, INT_MIN);
     for (int i = 0; i < m->nface; ++i) {
         const int eL = m->faces[4 * i], fL = m->faces[4 * i + 1], eR = m->faces[4 * i + 2], fR = m->faces[4 * i + 3];
@@ -596,6 +595,8 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
                 e.sf == ctx->cfg.surface_flux && e.curv == 1 && e.mort == 0)
                 sel = &e, affine = false;
     if (!sel) return set_err(ctx, DGX_E_INVAL, "no kernel variant for this configuration and mesh");
+    clear_graph(ctx);
+    ctx->mesh_ok = false;
     ctx->rhs = sel;
     ctx->curved = !affine;
     ctx->nelem = E;
