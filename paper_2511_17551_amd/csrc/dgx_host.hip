@@ -34,8 +34,10 @@ namespace {
 // ------------------------------------------------------------------ dispatch
 using RhsLaunch = void (*)(const RhsParams &, int, int, int, size_t, hipStream_t);
 using GradLaunch = void (*)(const RhsParams &, int, int, size_t, hipStream_t);
+// indicator launch: ..., and for mixtures the fused T(e) solve's outputs
+// (T, frozen sound speed; null: T was solved before) and its T0, tol, maxit
 using IndLaunch = void (*)(const RhsParams &, int, double, double, double *, double *, int, int, size_t,
-                           hipStream_t);
+                           hipStream_t, double *, double *, double, double, int);
 
 template <int DIM, int N, int EQ, int VF, int SF, bool CURV, bool MORT>
 void rhs_launch(const RhsParams &P, int mode, int blocks, int threads, size_t lds, hipStream_t s) {
@@ -48,9 +50,9 @@ void grad_launch(const RhsParams &P, int blocks, int threads, hipStream_t s) {
 }
 template <int DIM, int N, bool MIX>
 void ind_launch(const RhsParams &P, int iv, double amax, double amin, double *a, double *araw, int blocks,
-                int threads, size_t lds, hipStream_t s) {
+                int threads, size_t lds, hipStream_t s, double *Tw, double *cw, double T0, double tol, int maxit) {
     hipLaunchKernelGGL((k_indicator<DIM, N, MIX>), dim3(blocks), dim3(threads), lds, s, P, iv, amax, amin, a,
-                       araw);
+                       araw, Tw, cw, T0, tol, maxit);
 }
 
 struct RhsEntry {
@@ -282,7 +284,10 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
                 double dt, hipStream_t s, EventTape *tp = nullptr) {
     const dgx_config &c = ctx->cfg;
     if (tp) (void)hipEventRecord(tp->ev[0], s);
-    if (is_mix(ctx)) {
+    // mixtures: the T(e) solve runs inside the shock indicator when there is
+    // one (the same per-node steps, one pass over the state less)
+    const bool fuse_T = is_mix(ctx) && c.force_alpha < 0.0 && c.shock && find_ind(ctx);
+    if (is_mix(ctx) && !fuse_T) {
         int rc = enqueue_thermo_mesh(ctx, u, s);
         if (rc) return set_err(ctx, rc, "thermo launch failed");
         tape_mark(tp, "k_thermo", s);
@@ -299,7 +304,8 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
         const IndEntry *ie = find_ind(ctx);
         if (!ie) return set_err(ctx, DGX_E_INVAL, "no indicator kernel for this configuration");
         ie->fn(P, c.ind_var, c.alpha_max, c.alpha_min, ctx->alpha.p, ctx->alpha_raw.p, blocks, th,
-               (size_t)epb * 3 * ctx->nn * sizeof(double), s);
+               (size_t)epb * 3 * ctx->nn * sizeof(double), s, fuse_T ? ctx->T.p : nullptr,
+               fuse_T ? ctx->csnd.p : nullptr, c.T_guess, c.newton_tol, c.newton_maxit);
         if (c.alpha_smooth) {
             const int tb = 256;
             if (c.dim == 2)
@@ -312,7 +318,7 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
                            s);
         }
         P.alpha = ctx->alpha.p;
-        tape_mark(tp, "k_indicator", s);
+        tape_mark(tp, fuse_T ? "k_indicator_T" : "k_indicator", s);
     }
     if (c.equation == DGX_EQ_NS) {
         RhsParams G = P;

@@ -233,18 +233,15 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
     }
 }
 
-// Per-node T(e) Newton (Appendix, Thermodynamics).  Tguess may be null
-// (use T0).  Writes T, optionally p, and the iteration count.
+// The per-node T(e) solve (Appendix, Thermodynamics) of a conserved state
+// read from u ([nvar][count], species first): Newton from t (T0 when t is
+// not a positive number); a failed warm start (warm != 0) is retried from
+// T0.  Returns the iteration count, < 0 on failure; rs, rho for the caller.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_thermo(const double *__restrict__ u, int64_t count,
-                                                const double *__restrict__ Tguess, double T0,
-                                                double tol, int maxit, MixC M, double *__restrict__ T,
-                                                double *__restrict__ pout, double *__restrict__ cout,
-                                                int *__restrict__ iters, unsigned *flags, int warm) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    double rs[kNS];
-    double rho = 0.0;
+__device__ __forceinline__ int node_temperature(const double *__restrict__ u, size_t count, size_t i, double &t,
+                                                double T0, double tol, int maxit, const MixC &M, int warm,
+                                                double *rs, double &rho) {
+    rho = 0.0;
 #pragma unroll
     for (int s = 0; s < kNS; ++s) {
         rs[s] = u[s * count + i];
@@ -257,20 +254,35 @@ __global__ void __launch_bounds__(256) k_thermo(const double *__restrict__ u, in
         m2 = fma(m, m, m2);
     }
     const double rhoe = u[(kNS + DIM) * count + i] - 0.5 * m2 / rho;
-    // guess: the given one, or with warm != 0 the node's previous T (the
-    // right-hand side's solves), else T0; a failed warm start retries from T0
-    double t = Tguess ? Tguess[i] : (warm ? T[i] : T0);
     if (!(t > 0.0) || !isfinite(t)) t = T0;
     int it = mix_newton(M, rs, rhoe, t, tol, maxit);
     if (warm && (it < 0 || !isfinite(t) || !(t > 0.0))) {
         t = T0;
         it = mix_newton(M, rs, rhoe, t, tol, maxit);
     }
+    return (it < 0 || !isfinite(t) || !(t > 0.0)) ? -1 : it;
+}
+
+// Per-node T(e) Newton (Appendix, Thermodynamics).  Tguess may be null
+// (use T0).  Writes T, optionally p, and the iteration count.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_thermo(const double *__restrict__ u, int64_t count,
+                                                const double *__restrict__ Tguess, double T0,
+                                                double tol, int maxit, MixC M, double *__restrict__ T,
+                                                double *__restrict__ pout, double *__restrict__ cout,
+                                                int *__restrict__ iters, unsigned *flags, int warm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double rs[kNS], rho;
+    // guess: the given one, or with warm != 0 the node's previous T (the
+    // right-hand side's solves), else T0; a failed warm start retries from T0
+    double t = Tguess ? Tguess[i] : (warm ? T[i] : T0);
+    const int it = node_temperature<DIM>(u, (size_t)count, (size_t)i, t, T0, tol, maxit, M, warm, rs, rho);
     T[i] = t;
     if (pout) pout[i] = mix_rR(M, rs) * t;
     if (cout) cout[i] = mix_sound(M, rs, rho, t);
     if (iters) iters[i] = it;
-    if (it < 0 || !isfinite(t) || !(t > 0.0)) atomicOr(flags, FLAG_NOCONV);
+    if (it < 0) atomicOr(flags, FLAG_NOCONV);
 }
 
 // Modal shock indicator (Hennemann et al. type, as referenced in
@@ -279,7 +291,8 @@ __global__ void __launch_bounds__(256) k_thermo(const double *__restrict__ u, in
 template <int DIM, int N, bool MIX>
 __global__ void __launch_bounds__(512) k_indicator(RhsParams P, int ind_var, double alpha_max,
                                                    double alpha_min, double *__restrict__ alpha,
-                                                   double *__restrict__ alpha_raw) {
+                                                   double *__restrict__ alpha_raw, double *__restrict__ Tw,
+                                                   double *__restrict__ cw, double T0, double tol, int maxit) {
     constexpr int N1 = N + 1;
     constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
     constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
@@ -298,11 +311,24 @@ __global__ void __launch_bounds__(512) k_indicator(RhsParams P, int ind_var, dou
     const size_t stride = (size_t)P.nelem * NN;
     const size_t gi = (size_t)(valid ? e : 0) * NN + node;
     if (valid) {
+        double Tn = 0.0;
+        if constexpr (MIX) {
+            Tn = P.T[gi];
+            if (Tw) {
+                // the right-hand side's T(e) solve, fused (the same steps as
+                // k_thermo with a warm start): T and the frozen sound speed
+                double rs[kNS], rho;
+                const int it = node_temperature<DIM>(P.u, stride, gi, Tn, T0, tol, maxit, P.M, 1, rs, rho);
+                Tw[gi] = Tn;
+                cw[gi] = mix_sound(P.M, rs, rho, Tn);
+                if (it < 0) atomicOr(P.flags, FLAG_NOCONV);
+            }
+        }
         double uo[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) uo[v] = P.u[v * stride + gi];
         St<DIM, MIX> s;
-        make_state<DIM, MIX>(uo, MIX ? P.T[gi] : 0.0, P.gamma, P.M, s);
+        make_state<DIM, MIX>(uo, Tn, P.gamma, P.M, s);
         x[node] = ind_var == 1 ? s.p : s.rho * s.p;
     }
     __syncthreads();
