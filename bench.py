@@ -402,8 +402,8 @@ def main():
                     help="also run a plain 1 GiB read + 1 GiB write kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single MI355X; how the "
+              "path would shard across GPUs is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
