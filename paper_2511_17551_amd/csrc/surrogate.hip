@@ -80,13 +80,13 @@ __device__ __forceinline__ void features(const double *st, int64_t count, int64_
         const double m = st[(5 + c) * count + i];
         m2 += m * m;
     }
+    // the specific energy in FP64 (kinetic energy can dominate E); the
+    // logarithms and the standardisation in FP32, which the features are
+    // rounded to (and then to BF16 for the matrix unit)
     const double e = (st[(5 + DIM) * count + i] - 0.5 * m2 / rho) / rho;
-    double raw[6];
 #pragma unroll
-    for (int s = 0; s < 5; ++s) raw[s] = log10(fmax(rs[s], 1e-30));
-    raw[5] = e;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) x[k] = (float)((raw[k] - (double)nrm[k]) / (double)nrm[6 + k]);
+    for (int s = 0; s < 5; ++s) x[s] = (log10f(fmaxf((float)rs[s], 1e-30f)) - nrm[s]) / nrm[6 + s];
+    x[5] = (float)((e - (double)nrm[5]) / (double)nrm[11]);
 }
 
 // A fragment of a weight matrix W[rows][ld] (FP32 master) for output block
