@@ -42,13 +42,17 @@ __device__ __forceinline__ unsigned short to_bf16(float f) {
 }
 __device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2v __attribute__((ext_vector_type(2)));
+
+// Four floats to BF16 (round to nearest even) in two paired conversions, one
+// per dword, so that no byte shuffles are needed to assemble the fragment.
 __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
-    bf16x4 v;
-    v[0] = (short)to_bf16(a);
-    v[1] = (short)to_bf16(b);
-    v[2] = (short)to_bf16(c);
-    v[3] = (short)to_bf16(d);
-    return v;
+    const f32x2v lo = {a, b}, hi = {c, d};
+    const u32x2v w = {__builtin_bit_cast(unsigned, __builtin_convertvector(lo, bf16x2v)),
+                      __builtin_bit_cast(unsigned, __builtin_convertvector(hi, bf16x2v))};
+    return __builtin_bit_cast(bf16x4, w);
 }
 
 // tanh(x) = 1 - 2 / (exp(2x) + 1) with the hardware exp and reciprocal
