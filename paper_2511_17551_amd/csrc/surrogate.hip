@@ -170,13 +170,7 @@ __device__ __forceinline__ void forward(const float *P, const float *x, int r, i
 template <int DIM>
 __global__ void __launch_bounds__(256) k_mlp_predict(const float *__restrict__ P, const double *__restrict__ st,
                                                      int64_t count, double *__restrict__ Tg) {
-    __shared__ float sbias[4][H];          // b1, b2, b3, W4
     __shared__ float sx[4][64][8];         // per wave: features of 64 samples
-    for (int i = threadIdx.x; i < 4 * H; i += blockDim.x) {
-        const int l = i / H, k = i % H;
-        sbias[l][k] = P[(l == 0 ? ob1 : l == 1 ? ob2 : l == 2 ? ob3 : oW4) + k];
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
@@ -191,6 +185,19 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float *__restrict__ P
             W3f[mt][kc] = wfrag(P + oW3, H, H, mt, kc, r, g);
         }
     }
+    // this lane's biases (rows 16 mt + 4 g + j) start the accumulators, and
+    // its output weights W4
+    f32x4 bias1[4], bias2[4], bias3[4], w4[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = 16 * mt + 4 * g + j;
+            bias1[mt][j] = P[ob1 + row];
+            bias2[mt][j] = P[ob2 + row];
+            bias3[mt][j] = P[ob3 + row];
+            w4[mt][j] = P[oW4 + row];
+        }
     const float b4 = P[ob4];
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -223,11 +230,10 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float *__restrict__ P
             for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
                 for (int t2 = 0; t2 < 2; ++t2) {
-                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-                    acc = mfma(W1f[mt], xb[t2], acc);
+                    const f32x4 acc = mfma(W1f[mt], xb[t2], bias1[mt]);
                     float h[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) h[j] = tanh_fast(acc[j] + sbias[0][16 * mt + 4 * g + j]);
+                    for (int j = 0; j < 4; ++j) h[j] = tanh_fast(acc[j]);
                     hb[t2][mt] = pack4(h[0], h[1], h[2], h[3]);
                 }
             }
@@ -235,12 +241,12 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float *__restrict__ P
             for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
                 for (int t2 = 0; t2 < 2; ++t2) {
-                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                    f32x4 acc = bias2[mt];
 #pragma unroll
                     for (int kc = 0; kc < 4; ++kc) acc = mfma(W2f[mt][kc], hb[t2][kc], acc);
                     float h[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) h[j] = tanh_fast(acc[j] + sbias[1][16 * mt + 4 * g + j]);
+                    for (int j = 0; j < 4; ++j) h[j] = tanh_fast(acc[j]);
                     hc[t2][mt] = pack4(h[0], h[1], h[2], h[3]);
                 }
             }
@@ -249,14 +255,11 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float *__restrict__ P
             for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
                 for (int t2 = 0; t2 < 2; ++t2) {
-                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                    f32x4 acc = bias3[mt];
 #pragma unroll
                     for (int kc = 0; kc < 4; ++kc) acc = mfma(W3f[mt][kc], hc[t2][kc], acc);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int k = 16 * mt + 4 * g + j;
-                        yp[t2] = fmaf(sbias[3][k], tanh_fast(acc[j] + sbias[2][k]), yp[t2]);
-                    }
+                    for (int j = 0; j < 4; ++j) yp[t2] = fmaf(w4[mt][j], tanh_fast(acc[j]), yp[t2]);
                 }
             }
 #pragma unroll
