@@ -362,7 +362,7 @@ std::string tune_key(const dgx_ctx *ctx) {
 }
 
 bool epb_fits(const dgx_ctx *ctx, int epb) {
-    if (epb < 1 || epb > 8 || !ctx->rhs) return false;
+    if (epb < 1 || epb > 8 || (epb & (epb - 1)) || !ctx->rhs) return false;
     if (threads_for(ctx->nn, epb) > 512) return false;
     if (ctx->cfg.equation == DGX_EQ_NS) {
         // the gradient kernel's slot (GradShape): own W and face traces, then
@@ -1046,7 +1046,7 @@ int dgx_kernel_times(dgx_ctx *ctx, const double *u, int reps, double *ms_out, in
 int dgx_set_launch(dgx_ctx *ctx, int epb, int order) {
     int rc = check_ctx(ctx);
     if (rc) return rc;
-    if (!epb_fits(ctx, epb)) return set_err(ctx, DGX_E_INVAL, "elements per workgroup does not fit");
+    if (!epb_fits(ctx, epb)) return set_err(ctx, DGX_E_INVAL, "elements per workgroup must be 1, 2, 4 or 8 and fit in 512 threads and 64 KB of LDS");
     if (order < -1 || order > 1) return set_err(ctx, DGX_E_INVAL, "workgroup order must be -1, 0 or 1");
     const int xcd = order < 0 ? ctx->xcd : order;
     if (epb != ctx->epb || xcd != ctx->xcd) clear_graph(ctx);
