@@ -86,17 +86,24 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic():
+ORDER_NAMES = {0: "round_robin", 1: "xcd_contiguous"}
+
+
+def recorded_traffic(workload, order):
     """HBM bytes per k_rhs launch (FETCH_SIZE + WRITE_SIZE per dispatch, each
-    divided by its copy-kernel calibration factor) from the committed counter
-    summary, or None when it was taken on other kernel sources."""
+    divided by its copy-kernel calibration factor) of this workload under this
+    workgroup numbering, from the committed counter summary; None when no
+    record matches or it was taken on other kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
-        rec = json.load(fh)
-    if rec.get("source_sha1") != kernel_source_hash():
-        return None
-    return float(rec["traffic_bytes_per_launch"])
+        recs = json.load(fh).get("records", [])
+    sha = kernel_source_hash()
+    for rec in recs:
+        if rec.get("workload") == workload and rec.get("order") == ORDER_NAMES[order] \
+                and rec.get("source_sha1") == sha:
+            return float(rec["traffic_bytes_per_launch"])
+    return None
 
 
 def thermo_leg(torch, W, dgx, snapshots=16, steps_per_snap=20, epochs=16, reps=5):
@@ -258,7 +265,7 @@ def c3_bytes_per_launch(nelem, nn, nvar, dim, stage_base=True):
     return nelem * nn * per_node * 8 + nelem * (8 + 2 * dim * 4)
 
 
-def c3_leg(torch, W, dgx, reps=20):
+def c3_leg(torch, W, dgx, reps=20, order=-1):
     """The curvilinear 24^3 N = 4 frozen 5-species Mach-3 shock case:
     back-to-back right-hand sides on the shock state (each: T(e) Newton per
     node, modal indicator, fused RHS with subcell FV in the shocked elements),
@@ -273,6 +280,9 @@ def c3_leg(torch, W, dgx, reps=20):
     u = torch.from_numpy(c.u0).to("cuda")
     du = torch.empty_like(u)
     epb, tune = dgx.dgx_autotune(s.ctx, u, reps=5)
+    if order >= 0:
+        dgx.dgx_set_launch(s.ctx, epb, order)
+    _, used_order = dgx.dgx_get_launch(s.ctx)
     for _ in range(2):
         dgx.dgx_rhs(s.ctx, u, 0.0, du)
     torch.cuda.synchronize()
@@ -294,9 +304,10 @@ def c3_leg(torch, W, dgx, reps=20):
     return dict(workload="curved24_N4_air5_mach3_shock_rhs", elements=nelem, N=4, nodes=nelem * nn,
                 dof=int(c.u0.size), value=round(c.u0.size / (ms_rhs * 1e-3) / 1e9, 3),
                 unit="GDOF-RHS/s", ms_per_rhs=round(ms_rhs, 5), elements_per_workgroup=epb,
-                shocked_elements=shocked, kernel_ms={k: round(v, 5) for k, v in kt.items()},
+                workgroup_order=ORDER_NAMES[used_order], shocked_elements=shocked, kernel_ms={k: round(v, 5) for k, v in kt.items()},
                 roofline=dict(bound="hbm", kernel="k_rhs", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                              unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), bytes_per_launch=rb))
+                              unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), bytes_per_launch=rb,
+                              traffic=recorded_traffic("curved24_N4_air5_mach3_shock", used_order)))
 
 
 def c4_leg(torch, W, dgx, reps=20):
@@ -398,6 +409,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched AMR + cases leg")
     ap.add_argument("--epb", type=int, default=0,
                     help="elements per workgroup to use instead of autotuning (profiling runs)")
+    ap.add_argument("--order", type=int, default=-1, choices=(-1, 0, 1),
+                    help="workgroup numbering of the headline and curved-shock legs instead of the "
+                         "autotuner's (0 round-robin over the XCDs, 1 XCD-contiguous; profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write kernel (counter calibration)")
     args = ap.parse_args()
@@ -421,6 +435,9 @@ def main():
         epb, tune_ms = args.epb, {}
     else:
         epb, tune_ms = dgx.dgx_autotune(solver.ctx, u, reps=20)
+    if args.order >= 0:
+        dgx.dgx_set_launch(solver.ctx, epb, args.order)
+    _, order = dgx.dgx_get_launch(solver.ctx)
     if args.copy_probe:
         # counter calibration: kernels of known traffic on 1 GiB buffers
         # (larger than the 256 MB Infinity Cache)
@@ -456,7 +473,7 @@ def main():
     gb = grad_bytes_per_launch(nelem, nn, nvar, 3, 4)
     achieved = rb / (k_rhs_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(),
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic("tgv3d_ns_32cube_N3", order),
                 kernel="k_rhs", kernel_ms=round(k_rhs_ms, 5), bytes_per_launch=rb,
                 other_kernels={k: round(v, 5) for k, v in kt.items() if k != "k_rhs"},
                 k_grad_GBs=round(gb / (kt.get("k_grad", float("nan")) * 1e-3) / 1e9, 1))
@@ -467,7 +484,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "tgv3d_ns_32cube_N3_ssprk3", "elements": nelem, "N": 3, "nodes": nelem * nn,
                    "dof": dof, "rhs_per_step": 3, "dt": dt, "wall_s": round(wall, 4),
-                   "elements_per_workgroup": epb, "autotune_ms": {str(k): round(v, 5) for k, v in tune_ms.items()}},
+                   "elements_per_workgroup": epb, "workgroup_order": ORDER_NAMES[order], "autotune_ms": {str(k): round(v, 5) for k, v in tune_ms.items()}},
         "roofline": roof,
     }
     solver.close()
@@ -476,7 +493,7 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_leg(torch, W, dgx)
     if not args.no_c3:
-        out["c3"] = c3_leg(torch, W, dgx)
+        out["c3"] = c3_leg(torch, W, dgx, order=args.order)
         out["c4"] = c4_leg(torch, W, dgx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)

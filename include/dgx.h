@@ -314,7 +314,10 @@ int dgx_kernel_times(dgx_ctx *ctx, const double *u, int reps, double *ms_out, in
  * `reps` SSPRK3 steps as dgx_ssprk3_step runs them (three fused stages, u0
  * in its own buffer, the positivity limiter when configured; into library
  * scratch with dt = 0, so u is read, not modified) with HIP events on
- * `stream`, and keep the fastest pair.  The winner is cached process-wide under the key
+ * `stream`, and keep the fastest pair; the default numbering (XCD-contiguous
+ * while the state takes at most 128 MB, else round-robin) is kept unless
+ * the other one is more than 2% faster, since the two can differ little
+ * in time on one run and much in HBM traffic.  The winner is cached process-wide under the key
  * (dim, N, equation, fluxes, geometry kind, element count) and reused by
  * later dgx_set_mesh calls with the same key.  *epb_out (may be NULL)
  * receives the elements-per-workgroup choice, ms_out (may be NULL, [4]) each
@@ -327,6 +330,11 @@ int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *
  * 1 XCD-contiguous element ranges, -1 keep the current one).  The results do
  * not depend on either (bitwise). */
 int dgx_set_launch(dgx_ctx *ctx, int epb, int order);
+
+/* The current launch shape, as dgx_set_launch takes it: *epb (elements per
+ * workgroup) and *order (0 round-robin over the XCDs, 1 XCD-contiguous);
+ * either pointer may be NULL.  DGX_E_STATE without a mesh. */
+int dgx_get_launch(dgx_ctx *ctx, int *epb, int *order);
 
 /* Text of the last error on this context (never NULL). */
 const char *dgx_last_error(const dgx_ctx *ctx);

@@ -95,6 +95,7 @@ def _load():
                               C.c_size_t, vp], C.c_int),
         "dgx_autotune": ([vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), vp], C.c_int),
         "dgx_set_launch": ([vp, C.c_int, C.c_int], C.c_int),
+        "dgx_get_launch": ([vp, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "dgx_last_error": ([vp], C.c_char_p),
         "dgx_destroy": ([vp], None),
     }
@@ -110,7 +111,7 @@ EXPORTED = ("dgx_create", "dgx_set_mesh", "dgx_rhs", "dgx_ssprk3_step", "dgx_lim
             "dgx_chem_step",
             "dgx_last_alpha", "dgx_surrogate_set", "dgx_surrogate_get", "dgx_surrogate_train",
             "dgx_surrogate_predict", "dgx_surrogate_init", "dgx_surrogate_grad", "dgx_check", "dgx_species_energy", "dgx_kernel_times", "dgx_autotune",
-            "dgx_set_launch", "dgx_last_error", "dgx_destroy")
+            "dgx_set_launch", "dgx_get_launch", "dgx_last_error", "dgx_destroy")
 
 
 def _ptr(a, ctype=C.c_double):
@@ -352,6 +353,13 @@ def dgx_set_launch(ctx, epb, order=-1):
     """Elements per workgroup and workgroup numbering (0 round-robin over the
     XCDs, 1 XCD-contiguous, -1 keep)."""
     _raise(ctx, lib.dgx_set_launch(ctx, int(epb), int(order)))
+
+
+def dgx_get_launch(ctx):
+    """(elements per workgroup, workgroup numbering) in use."""
+    epb, order = C.c_int(), C.c_int()
+    _raise(ctx, lib.dgx_get_launch(ctx, C.byref(epb), C.byref(order)))
+    return epb.value, order.value
 
 
 def dgx_last_error(ctx):

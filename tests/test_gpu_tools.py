@@ -9,7 +9,9 @@
   right-hand side for the shocked mixture), each with a positive average
   duration, and the state left untouched.
 * dgx_last_error: after a rejected call the message names what was wrong;
-  the binding's exception carries the same text."""
+  the binding's exception carries the same text.
+* dgx_get_launch returns the launch shape dgx_set_launch set, unchanged by
+  a rejected dgx_set_launch."""
 import numpy as np
 import pytest
 
@@ -71,8 +73,11 @@ def test_kernel_times_name_the_launches(dgx, thermo_fns):
 def test_last_error_names_the_cause(dgx):
     c = W.case_c2(n=2)
     s = dgx.Solver(c)
+    dgx.dgx_set_launch(s.ctx, 2, 0)
+    assert dgx.dgx_get_launch(s.ctx) == (2, 0)
     with pytest.raises(dgx.DgxError) as ei:
-        dgx.dgx_set_launch(s.ctx, 3, 0)          # not one of 1, 2, 4, 8
+        dgx.dgx_set_launch(s.ctx, 3, 1)          # not one of 1, 2, 4, 8
+    assert dgx.dgx_get_launch(s.ctx) == (2, 0)   # unchanged by the rejected call
     msg = dgx.dgx_last_error(s.ctx)
     assert dgx.ERRORS[ei.value.code] == "DGX_E_INVAL"
     assert "elements per workgroup" in msg and msg in str(ei.value)
