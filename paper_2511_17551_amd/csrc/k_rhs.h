@@ -44,27 +44,8 @@ __device__ __forceinline__ int node_line(int n, int d) {
     if (d == 1) return (n % N1) + N1 * (n / (N1 * N1));
     return n % (N1 * N1);
 }
-// index of pair (a < b) among the N1(N1-1)/2 pairs of a line
-template <int N1>
-__device__ __forceinline__ int pair_index(int a, int b) {
-    return a * N1 - (a * (a + 1)) / 2 + (b - a - 1);
-}
-template <int N1>
-__device__ __forceinline__ void pair_of(int k, int &a, int &b) {
-    a = 0;
-#pragma unroll
-    for (int i = 0; i < N1 - 1; ++i) {
-        const int cnt = N1 - 1 - i;
-        if (k >= cnt && a == i) {
-            k -= cnt;
-            a = i + 1;
-        }
-    }
-    b = a + 1 + k;
-}
-
 // Pairs (a < b) of a line in lexicographic order, packed as 4-bit fields:
-// a of pair k is (kPairA >> 4k) & 15, b likewise.
+// a of pair k is (A >> 4k) & 15, b likewise.
 template <int N1>
 struct PairTab {
     static constexpr unsigned long long pack(bool second) {
@@ -75,6 +56,26 @@ struct PairTab {
         return t;
     }
     static constexpr unsigned long long A = pack(false), B = pack(true);
+};
+
+// Partners of a node along its line: for offset j (1..N1-1) the node at
+// position a pairs with b = (a + j) mod N1.  pidx(j) packs, in 4-bit fields
+// per a, the index of the pair {a, b} in PairTab order, so that a lane finds
+// its pair with one bit-field extract instead of recomputing the index.
+template <int N1>
+struct PartnerTab {
+    static_assert(N1 <= 6, "pair indices below 16, N1 4-bit fields in 32 bits");
+    static constexpr unsigned pidx(int j) {
+        unsigned r = 0;
+        for (int a = 0; a < N1; ++a) {
+            const int b = (a + j) % N1;
+            const int lo = a < b ? a : b, hi = a < b ? b : a;
+            int k = 0;  // pairs before {lo, hi} in PairTab order
+            for (int x = 0; x < lo; ++x) k += N1 - 1 - x;
+            r |= (unsigned)(k + hi - lo - 1) << (4 * a);
+        }
+        return r;
+    }
 };
 
 // A phase of K work items per element, spread over the NT = epb * NN threads
@@ -625,16 +626,16 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
             if (valid) {
                 const int a = node_pos<N1>(node, d);
                 const int l = node_line<N1, DIM>(node, d);
+                const int sa4 = 4 * a;
+                const int kl = l * NPL - ch * PDC;  // the line's first pair in this chunk's buffer
 #pragma unroll
                 for (int j = 1; j < N1; ++j) {
-                    // the other nodes b != a of the line, without branches
-                    const int b = a + j - (a + j >= N1 ? N1 : 0);
-                    const int lo = a < b ? a : b, hi = a < b ? b : a;
-                    const int k = l * NPL + pair_index<N1>(lo, hi);
-                    if (NCH == 1 || (k >= ch * PDC && k < (ch + 1) * PDC)) {
-                        const double coef = sDc[a * N1 + b];
+                    // partner b = (a + j) mod N1: the pair's slot and coefficient
+                    const int k = kl + (int)((PartnerTab<N1>::pidx(j) >> sa4) & 15u);
+                    if (NCH == 1 || (unsigned)k < (unsigned)PDC) {
+                        const double coef = sDc[a * N1 + a + j - (a + j >= N1 ? N1 : 0)];
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) dg[v] = fma(coef, buf[v * PDC + k - ch * PDC], dg[v]);
+                        for (int v = 0; v < NV; ++v) dg[v] = fma(coef, buf[v * PDC + k], dg[v]);
                     }
                 }
             }
