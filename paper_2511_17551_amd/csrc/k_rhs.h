@@ -58,6 +58,15 @@ struct PairTab {
     static constexpr unsigned long long A = pack(false), B = pack(true);
 };
 
+// The slot offset of an LDS buffer, hidden from constant folding: the
+// paired LDS accesses (ds_read2/ds_write2) encode offsets of at most 2 KB, so
+// a large folded constant would cost one address add per access; an opaque
+// offset goes into the base register once.
+__device__ __forceinline__ int opaque_offset(int x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
 // Partners of a node along its line: for offset j (1..N1-1) the node at
 // position a pairs with b = (a + j) mod N1.  pidx(j) packs, in 4-bit fields
 // per a, the index of the pair {a, b} in PairTab order, so that a lane finds
@@ -129,7 +138,12 @@ struct RhsShape {
     static constexpr int NCH = PD * NV > 1200 ? 2 : 1;
     static constexpr int PDC = (PD + NCH - 1) / NCH;    // pairs per chunk
     static constexpr int NSFC = (NSF + NCH - 1) / NCH;  // face nodes per chunk
-    static constexpr int B1 = PDC * NV;
+    // the volume pair fluxes are stored pair-major (a pair's NV fluxes are
+    // contiguous, so one base address serves all of them), with an odd row
+    // stride so that rows written by consecutive lanes start on distinct LDS
+    // banks; the face and subcell buffers are variable-major
+    static constexpr int NVP = NV | 1;
+    static constexpr int B1 = PDC * NVP;
     static constexpr int B2 = NFV * NV;
     static constexpr int B3 = NSFC * NV;
     static constexpr int M12 = B1 > B2 ? B1 : B2;
@@ -186,7 +200,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     using S = RhsShape<DIM, N, EQ, VF, CURV>;
     constexpr int N1 = S::N1, NN = S::NN, NF = S::NF, NV = S::NV, NQ = S::NQ, NW = S::NW;
     constexpr int NPL = S::NPL, PD = S::PD, NFV = S::NFV, NSF = S::NSF;
-    constexpr int NCH = S::NCH, PDC = S::PDC, NSFC = S::NSFC;
+    constexpr int NCH = S::NCH, PDC = S::PDC, NSFC = S::NSFC, NVP = S::NVP;
     constexpr bool MIX = S::MIX;
     constexpr int GA = DIM * DIM + 1;
     constexpr int QB = DIM + 3 + (MIX ? 1 : 0);  // EC slot in sq
@@ -214,7 +228,8 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     double *su = smem + el * S::SLOT;
     double *sq = su + S::SU;
     double *sJa = su + OFF_G;  // curved: the current direction's metric row; affine: Ja, J
-    double *buf = su + OFF_B;
+    const int off_b = opaque_offset(OFF_B);
+    double *buf = su + off_b;
     const size_t stride = (size_t)P.nelem * NN;
     const size_t gi = (size_t)e * NN + node;
     const double gamma = P.gamma;
@@ -558,14 +573,21 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
         }
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const Spread sp = spread_phase(tid, NT, P.epb * PDC, cursor);
-            cursor = sp.cursor;
+            // a chunk of exactly NN pairs per element: each thread takes the
+            // pair of its own element whose slot is its node index (the
+            // spread would give every thread one item as well)
+            constexpr bool OWN = PDC == NN;
+            Spread sp{tid, cursor};
+            if constexpr (!OWN) {
+                sp = spread_phase(tid, NT, P.epb * PDC, cursor);
+                cursor = sp.cursor;
+            }
 #pragma unroll
             for (int r = 0; r < (PDC + NN - 1) / NN; ++r) {
                 const int it = r * NT + sp.t;
-                if (tid < NT && it < nloc * PDC) {
-                    const int ei = it / PDC;
-                    const int jb = it - ei * PDC;      // slot in this chunk's buffer
+                if (OWN ? valid : (tid < NT && it < nloc * PDC)) {
+                    const int ei = OWN ? el : it / PDC;
+                    const int jb = OWN ? node : it - ei * PDC;  // slot in this chunk's buffer
                     const int p = ch * PDC + jb;       // pair index within the direction
                     if (NCH > 1 && p >= PD) continue;
                     const int l = p / NPL;
@@ -575,7 +597,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                     const double *esu = smem + ei * S::SLOT;
                     const double *esq = esu + S::SU;
                     const double *eg = esu + OFF_G;
-                    double *ebuf = smem + ei * S::SLOT + OFF_B;
+                    double *ebuf = smem + ei * S::SLOT + off_b;
                     const int na = line_node<N1, DIM>(d, a, l);
                     const int nb = line_node<N1, DIM>(d, b, l);
                     double nbar[DIM];
@@ -599,7 +621,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                         ducros_state<DIM, MIX>(A, B, nbar, F);
                     }
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) ebuf[v * PDC + jb] = F[v];
+                    for (int v = 0; v < NV; ++v) ebuf[jb * NVP + v] = F[v];
                 }
             }
             if (d == DIM - 1 && ch == NCH - 1) {
@@ -635,7 +657,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                     if (NCH == 1 || (unsigned)k < (unsigned)PDC) {
                         const double coef = sDc[a * N1 + a + j - (a + j >= N1 ? N1 : 0)];
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) dg[v] = fma(coef, buf[v * PDC + k], dg[v]);
+                        for (int v = 0; v < NV; ++v) dg[v] = fma(coef, buf[k * NVP + v], dg[v]);
                     }
                 }
             }
