@@ -49,8 +49,8 @@ __device__ __forceinline__ void chem_sources(const KinC &K, const MixC &M, const
         double g = K.gconst[s] - 2.5 * lnT + M.e0[s] * iT / M.Rs[s];
         if (M.mol[s]) {
             const double x = M.thv[s] * iT;
-            const double em = exp(-x);
-            const double om = -expm1(-x);
+            double em, om;  // e^-x, 1 - e^-x
+            exp_pair(x, em, om);
             const double q = em * rcp(om);
             e += M.Rs[s] * T + M.Rs[s] * M.thv[s] * q;
             cv += M.Rs[s] + M.Rs[s] * x * x * q * rcp(om);

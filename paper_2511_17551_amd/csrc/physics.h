@@ -90,6 +90,20 @@ __device__ __forceinline__ double inv_ln_mean(double x, double y) {
 }
 
 // ---------------------------------------------------------------- mixture
+// e^-x and 1 - e^-x from one transcendental: whichever of the two is at
+// least 1 - e^-1/2 (about 0.39) comes from the other by a subtraction that
+// keeps it within about 2 ulp (x below 1/2: expm1, so that 1 - e^-x keeps
+// its digits as x -> 0; above: exp).
+__device__ __forceinline__ void exp_pair(double x, double &em, double &om) {
+    if (x < 0.5) {
+        om = -expm1(-x);
+        em = 1.0 - om;
+    } else {
+        em = exp(-x);
+        om = 1.0 - em;
+    }
+}
+
 __device__ __forceinline__ void mix_energy_cv(const MixC &M, const double *rs, double T,
                                               double &rhoe, double &rhocv) {
     double e = 0.0, cv = 0.0;
@@ -99,8 +113,8 @@ __device__ __forceinline__ void mix_energy_cv(const MixC &M, const double *rs, d
         double cs = 1.5 * M.Rs[s];
         if (M.mol[s]) {
             const double x = M.thv[s] * rcp(T);
-            const double em = exp(-x);
-            const double om = -expm1(-x);  // 1 - e^-x
+            double em, om;  // e^-x, 1 - e^-x
+            exp_pair(x, em, om);
             // R theta/(e^x - 1) = R theta e^-x / (1 - e^-x); its T-derivative R x^2 e^-x / (1 - e^-x)^2
             const double q = em * rcp(om);
             es += M.Rs[s] * T + M.Rs[s] * M.thv[s] * q;
@@ -151,8 +165,9 @@ __device__ __forceinline__ double mix_sound(const MixC &M, const double *rs, dou
         double cs = 1.5 * M.Rs[s];
         if (M.mol[s]) {
             const double x = M.thv[s] * rcp(T);
-            const double om = -expm1(-x);
-            cs += M.Rs[s] + M.Rs[s] * x * x * exp(-x) * rcp(om * om);
+            double em, om;
+            exp_pair(x, em, om);
+            cs += M.Rs[s] + M.Rs[s] * x * x * em * rcp(om * om);
         }
         cv = fma(rs[s], cs, cv);
     }
