@@ -66,15 +66,18 @@ class Operator:
                                         self.cfg["newton_tol"], self.cfg["newton_maxit"])
         return self.mix.state(u, self.dim, T)
 
+    # volume and surface flux choices (the library's DGX_VF_* / DGX_SF_*
+    # numbering); "kg" / "pirozzoli" as a surface flux serve the oracle's
+    # own kinetic-energy checks
+    VOLUME = {0: gas.ranocha, 1: gas.ducros, 2: gas.kennedy_gruber, 3: gas.pirozzoli}
+    SURFACE = {0: gas.rusanov, 1: gas.ranocha, 2: gas.hll, "kg": gas.kennedy_gruber,
+               "pirozzoli": gas.pirozzoli}
+
     def volume_flux(self, sL, sR, n):
-        if self.cfg["volume_flux"] == 0:
-            return gas.ranocha(sL, sR, n)
-        return gas.ducros(sL, sR, n)
+        return self.VOLUME[self.cfg["volume_flux"]](sL, sR, n)
 
     def surface_flux(self, sL, sR, n):
-        if self.cfg["surface_flux"] == 0:
-            return gas.rusanov(sL, sR, n)
-        return gas.ranocha(sL, sR, n)
+        return self.SURFACE[self.cfg["surface_flux"]](sL, sR, n)
 
     # ------------------------------------------------------------------
     def blending(self, s):

@@ -2,8 +2,9 @@
 
 Paper: Sec. Governing Equations, Eq. adevctive_flux (physical flux),
 Sec. Methodology, Eqs. riemann_problem1-3 (interface Riemann flux, Lax-
-Friedrichs named), Eqs. fluxdiff/fluxdiffcons/conssymm (symmetric,
-consistent two-point fluxes: entropy-conservative or the Ducros split form).
+Friedrichs and HLL named), Eqs. fluxdiff/fluxdiffcons/conssymm (symmetric,
+consistent two-point fluxes: entropy-conservative, or the Ducros,
+Kennedy-Gruber and Pirozzoli split forms the paper lists).
 
 A state is a dict with 'rho' (total density), 'rs' (species densities, mixture
 only), 'v' (dim, ...), 'p', 'rhoE', 'c' (sound speed) and, for the perfect
@@ -15,7 +16,10 @@ Readings where the paper is silent:
   (ln-mean of rho and rho/p, with the small-difference series of the
   logarithmic mean);
 * the Lax-Friedrichs (Rusanov) dissipation uses the Davis estimate
-  max(|v_L.n| + c_L|n|, |v_R.n| + c_R|n|).
+  max(|v_L.n| + c_L|n|, |v_R.n| + c_R|n|);
+* HLL uses the Davis bounds min / max of v.n -+ c|n| over both sides;
+* the split forms are written as two-point fluxes with arithmetic means
+  {{a}} = (a_L + a_R)/2 of the nodal quantities named in each docstring.
 """
 import numpy as np
 
@@ -105,6 +109,55 @@ def ducros(sL, sR, n):
         rows.append(mbar * vn + pbar * n[c])
     rows.append((0.5 * (sL["rhoE"] + sR["rhoE"]) + pbar) * vn)
     return np.stack(rows, 0)
+
+
+def kennedy_gruber(sL, sR, n):
+    """Kennedy-Gruber split form as a two-point flux (perfect gas), one of the
+    split forms the paper lists as interchangeable volume fluxes (Sec.
+    Methodology, after Eq. conssymm): mass {{rho}}{{v.n}}, momentum that mass
+    flux times {{v}} plus {{p}} n, energy that mass flux times {{E/rho}} plus
+    {{p}}{{v.n}}."""
+    vn = dot(0.5 * (sL["v"] + sR["v"]), n)
+    pbar = 0.5 * (sL["p"] + sR["p"])
+    f_rho = 0.5 * (sL["rho"] + sR["rho"]) * vn
+    rows = [f_rho]
+    for c in range(sL["v"].shape[0]):
+        rows.append(f_rho * 0.5 * (sL["v"][c] + sR["v"][c]) + pbar * n[c])
+    e_bar = 0.5 * (sL["rhoE"] / sL["rho"] + sR["rhoE"] / sR["rho"])
+    rows.append(f_rho * e_bar + pbar * vn)
+    return np.stack(rows, 0)
+
+
+def pirozzoli(sL, sR, n):
+    """Pirozzoli split form as a two-point flux (perfect gas), listed beside
+    Kennedy-Gruber (Sec. Methodology): mass and momentum as Kennedy-Gruber,
+    energy the mass flux times {{h}}, h = (E + p)/rho per node."""
+    vn = dot(0.5 * (sL["v"] + sR["v"]), n)
+    pbar = 0.5 * (sL["p"] + sR["p"])
+    f_rho = 0.5 * (sL["rho"] + sR["rho"]) * vn
+    rows = [f_rho]
+    for c in range(sL["v"].shape[0]):
+        rows.append(f_rho * 0.5 * (sL["v"][c] + sR["v"][c]) + pbar * n[c])
+    h_bar = 0.5 * ((sL["rhoE"] + sL["p"]) / sL["rho"] + (sR["rhoE"] + sR["p"]) / sR["rho"])
+    rows.append(f_rho * h_bar)
+    return np.stack(rows, 0)
+
+
+def hll(sL, sR, n):
+    """HLL Riemann flux (named among the interface solvers, Sec. Methodology,
+    Eqs. riemann_problem1-3) with Davis bounds S_L = min(v_L.n - c_L|n|,
+    v_R.n - c_R|n|), S_R = max(v_L.n + c_L|n|, v_R.n + c_R|n|) (scaled n):
+    f_L where S_L >= 0, f_R where S_R <= 0, otherwise
+    (S_R f_L - S_L f_R + S_L S_R (u_R - u_L)) / (S_R - S_L)."""
+    nn = np.sqrt(dot(n, n))
+    vL, vR = dot(sL["v"], n), dot(sR["v"], n)
+    SL = np.minimum(vL - sL["c"] * nn, vR - sR["c"] * nn)
+    SR = np.maximum(vL + sL["c"] * nn, vR + sR["c"] * nn)
+    fL, fR = physical_flux(sL, n), physical_flux(sR, n)
+    uL, uR = conserved(sL), conserved(sR)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mid = (SR * fL - SL * fR + SL * SR * (uR - uL)) / (SR - SL)
+    return np.where(SL >= 0.0, fL, np.where(SR <= 0.0, fR, mid))
 
 
 def entropy_variables(s):

@@ -47,8 +47,11 @@ EQ_REACT_MIX = 3   # as above plus Arrhenius species sources
 
 VF_RANOCHA = 0     # entropy-conservative two-point flux
 VF_DUCROS = 1      # Ducros split-form two-point flux
+VF_KENNEDY_GRUBER = 2  # Kennedy-Gruber split form (perfect gas)
+VF_PIROZZOLI = 3   # Pirozzoli split form (perfect gas)
 SF_RUSANOV = 0     # local Lax-Friedrichs surface flux
 SF_RANOCHA = 1     # EC flux at faces (entropy-conservation checks only)
+SF_HLL = 2         # HLL with Davis wave-speed bounds (perfect gas)
 
 IND_RHO_P = 0      # shock indicator variable rho*p
 IND_P = 1          # shock indicator variable p

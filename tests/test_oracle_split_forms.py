@@ -1,0 +1,127 @@
+"""Pins of the oracle's Kennedy-Gruber and Pirozzoli two-point fluxes and its
+HLL Riemann flux.
+
+* Split forms: consistency (equal states give the physical flux f(u).n),
+  symmetry in the two states, and the two forms coincide when density and
+  pressure are equal on both sides (their energy rows then reduce to the same
+  expression).  At the operator level both are kinetic-energy preserving: on
+  a periodic curved mesh with uniform pressure and the same flux at the
+  faces, the semi-discrete total kinetic energy rate
+  sum J w (v . dm/dt - |v|^2/2 drho/dt) vanishes to rounding.  A momentum
+  flux averaged as {{rho v}} instead of {{rho}}{{v}}, planted in the oracle,
+  breaks that by many orders of magnitude (the check can fail).
+* HLL: consistency; pure upwinding when both wave-speed bounds have one sign
+  (f_L for supersonic flow along n, f_R against it); and in the subsonic
+  branch the flux equals both f_L + S_L (u* - u_L) and f_R + S_R (u* - u_R)
+  with u* the intermediate state that conserves the integral over the wave
+  fan, u* = (S_R u_R - S_L u_L - (f_R - f_L)) / (S_R - S_L).
+"""
+import numpy as np
+
+from oracle import gas
+from oracle.dgsem import Operator
+from paper_2511_17551_amd import workloads as W
+
+
+def states(rng, n, vmax=2.0):
+    rho = rng.uniform(0.2, 3.0, n)
+    v = rng.uniform(-vmax, vmax, (3, n))
+    p = rng.uniform(0.2, 5.0, n)
+    u = np.concatenate([rho[None], rho * v, (p / 0.4 + 0.5 * rho * (v * v).sum(0))[None]])
+    return gas.pg_state(u, 3, 1.4)
+
+
+def test_split_forms_consistency_and_symmetry():
+    rng = np.random.default_rng(11)
+    s, s2 = states(rng, 400), states(rng, 400)
+    n = rng.normal(size=(3, 400))
+    fphys = gas.physical_flux(s, n)
+    scale = np.abs(fphys).max()
+    for flux in (gas.kennedy_gruber, gas.pirozzoli):
+        assert np.abs(flux(s, s, n) - fphys).max() < 1e-13 * scale
+        assert np.abs(flux(s, s2, n) - flux(s2, s, n)).max() < 1e-13 * scale
+
+
+def test_split_forms_coincide_at_equal_density_and_pressure():
+    rng = np.random.default_rng(12)
+    a, b = states(rng, 300), states(rng, 300)
+    b = dict(b, rho=a["rho"], p=a["p"])
+    b["rhoE"] = b["p"] / 0.4 + 0.5 * b["rho"] * (b["v"] ** 2).sum(0)
+    n = rng.normal(size=(3, 300))
+    kg, pi = gas.kennedy_gruber(a, b, n), gas.pirozzoli(a, b, n)
+    assert np.abs(kg - pi).max() < 1e-13 * np.abs(kg).max()
+    # and differ otherwise (energy row only)
+    c = states(rng, 300)
+    d = np.abs(gas.kennedy_gruber(a, c, n) - gas.pirozzoli(a, c, n))
+    assert d[:4].max() < 1e-14 * np.abs(gas.kennedy_gruber(a, c, n)).max() and d[4].max() > 1e-3
+
+
+def kinetic_energy_rate(vf, sf):
+    c = W.curved_periodic_case(n=2, N=3, volume_flux=vf, surface_flux=sf)
+    u = c.u0.copy()
+    s = gas.pg_state(u, 3, 1.4)
+    u[4] = 1.7 / 0.4 + 0.5 * s["rho"] * (s["v"] ** 2).sum(0)   # uniform pressure 1.7
+    op = Operator(c.cfg, c.mesh)
+    du = op.rhs(u)
+    v = u[1:4] / u[0]
+    w = np.einsum("i,j,k->kji", op.b.w, op.b.w, op.b.w).reshape(-1)
+    dens = ((v * du[1:4]).sum(0) - 0.5 * (v * v).sum(0) * du[0]) * op.J * w
+    return abs(dens.sum()), np.abs(dens).sum()
+
+
+def test_split_forms_preserve_kinetic_energy():
+    for vf, sf in ((W.VF_KENNEDY_GRUBER, "kg"), (W.VF_PIROZZOLI, "pirozzoli")):
+        tot, scale = kinetic_energy_rate(vf, sf)
+        assert tot < 1e-13 * scale, (vf, tot, scale)
+
+
+def test_kinetic_energy_check_catches_a_wrong_momentum_average(monkeypatch):
+    def wrong(sL, sR, n):
+        f = gas.kennedy_gruber(sL, sR, n)
+        vn = gas.dot(0.5 * (sL["v"] + sR["v"]), n)
+        for c in range(3):
+            f[1 + c] = 0.5 * (sL["rho"] * sL["v"][c] + sR["rho"] * sR["v"][c]) * vn \
+                + 0.5 * (sL["p"] + sR["p"]) * n[c]
+        return f
+    monkeypatch.setitem(Operator.VOLUME, W.VF_KENNEDY_GRUBER, wrong)
+    monkeypatch.setitem(Operator.SURFACE, "kg", wrong)
+    tot, scale = kinetic_energy_rate(W.VF_KENNEDY_GRUBER, "kg")
+    assert tot > 1e-6 * scale
+
+
+def test_hll_consistency_and_upwinding():
+    rng = np.random.default_rng(13)
+    s, s2 = states(rng, 500), states(rng, 500)
+    n = rng.normal(size=(3, 500))
+    fphys = gas.physical_flux(s, n)
+    assert np.abs(gas.hll(s, s, n) - fphys).max() < 1e-13 * np.abs(fphys).max()
+    # supersonic along +n (or -n) for both states: a normal velocity larger
+    # than the largest |v| + c of either state added
+    nh = n / np.sqrt((n * n).sum(0))
+    shift = 1.5 * max((np.sqrt((st["v"] ** 2).sum(0)) + st["c"]).max() for st in (s, s2))
+    def shifted(st, sign):
+        v = st["v"] + sign * shift * nh
+        u = np.concatenate([st["rho"][None], st["rho"] * v, (st["p"] / 0.4 + 0.5 * st["rho"] * (v * v).sum(0))[None]])
+        return gas.pg_state(u, 3, 1.4)
+    a, b = shifted(s, 1.0), shifted(s2, 1.0)
+    assert np.array_equal(gas.hll(a, b, n), gas.physical_flux(a, n))
+    a, b = shifted(s, -1.0), shifted(s2, -1.0)
+    assert np.array_equal(gas.hll(a, b, n), gas.physical_flux(b, n))
+
+
+def test_hll_equals_the_intermediate_state_flux():
+    rng = np.random.default_rng(14)
+    sL, sR = states(rng, 500, vmax=0.3), states(rng, 500, vmax=0.3)   # subsonic: S_L < 0 < S_R
+    n = rng.normal(size=(3, 500))
+    nn = np.sqrt((n * n).sum(0))
+    vL, vR = gas.dot(sL["v"], n), gas.dot(sR["v"], n)
+    SL = np.minimum(vL - sL["c"] * nn, vR - sR["c"] * nn)
+    SR = np.maximum(vL + sL["c"] * nn, vR + sR["c"] * nn)
+    assert np.all(SL < 0) and np.all(SR > 0)
+    fL, fR = gas.physical_flux(sL, n), gas.physical_flux(sR, n)
+    uL, uR = gas.conserved(sL), gas.conserved(sR)
+    ustar = (SR * uR - SL * uL - (fR - fL)) / (SR - SL)
+    F = gas.hll(sL, sR, n)
+    scale = np.abs(fL).max() + np.abs(fR).max()
+    assert np.abs(F - (fL + SL * (ustar - uL))).max() < 1e-12 * scale
+    assert np.abs(F - (fR + SR * (ustar - uR))).max() < 1e-12 * scale
