@@ -310,6 +310,51 @@ def c3_leg(torch, W, dgx, reps=20, order=-1):
                               traffic=recorded_traffic("curved24_N4_air5_mach3_shock", used_order)))
 
 
+def euler_bytes_per_launch(nelem, nn, nvar):
+    """Algorithmic HBM bytes of one fused k_rhs launch for the perfect-gas
+    Euler equations on affine elements: per node u, u0 read and the next stage
+    written; per element the affine geometry and 2*dim int32 neighbours."""
+    return nelem * nn * 3 * nvar * 8 + nelem * (10 * 8 + 6 * 4)
+
+
+def flux_leg(torch, W, dgx, reps=20):
+    """The 32^3 N=3 Taylor-Green state under the 3D Euler equations with each
+    built volume / surface flux pair: back-to-back right-hand sides and the
+    k_rhs time of its stage-form launch (HIP events)."""
+    variants = [("ranocha_rusanov", W.VF_RANOCHA, W.SF_RUSANOV),
+                ("kennedy_gruber_rusanov", W.VF_KENNEDY_GRUBER, W.SF_RUSANOV),
+                ("pirozzoli_rusanov", W.VF_PIROZZOLI, W.SF_RUSANOV),
+                ("ranocha_hll", W.VF_RANOCHA, W.SF_HLL)]
+    out = {}
+    for name, vf, sf in variants:
+        c = W.case_c2(eq=W.EQ_EULER)
+        c.cfg = dict(c.cfg, volume_flux=vf, surface_flux=sf)
+        nvar, nelem, nn = c.u0.shape
+        s = dgx.Solver(c)
+        u = torch.from_numpy(c.u0).to("cuda")
+        du = torch.empty_like(u)
+        epb, _ = dgx.dgx_autotune(s.ctx, u, reps=5)
+        for _ in range(2):
+            dgx.dgx_rhs(s.ctx, u, 0.0, du)
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch)
+        e0.record()
+        for _ in range(reps):
+            dgx.dgx_rhs(s.ctx, u, 0.0, du)
+        e1.record()
+        torch.cuda.synchronize()
+        s.check()
+        ms = e0.elapsed_time(e1) / reps
+        kt = dgx.dgx_kernel_times(s.ctx, u, reps=10)
+        s.close()
+        rb = euler_bytes_per_launch(nelem, nn, nvar)
+        out[name] = dict(value=round(c.u0.size / (ms * 1e-3) / 1e9, 3), unit="GDOF-RHS/s", ms_per_rhs=round(ms, 5),
+                         k_rhs_ms=round(kt["k_rhs"], 5), elements_per_workgroup=epb,
+                         roofline_frac=round(rb / (kt["k_rhs"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    return dict(workload="tgv3d_euler_32cube_N3_rhs", bytes_per_launch=euler_bytes_per_launch(32768, 64, 5),
+                variants=out)
+
+
 def c4_leg(torch, W, dgx, reps=20):
     """The 2D reacting 5-species cylinder (64 x 128 O-grid, N = 3, 17
     Arrhenius reactions): back-to-back right-hand sides on the hot, partly
@@ -407,6 +452,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the mixture legs (curved N=4 shock, reacting cylinder)")
     ap.add_argument("--no-thermo", action="store_true", help="skip the surrogate vs plain T(e) leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched AMR + cases leg")
+    ap.add_argument("--no-fluxes", action="store_true",
+                    help="skip the leg that times each built volume / surface flux on the TGV (Euler)")
     ap.add_argument("--epb", type=int, default=0,
                     help="elements per workgroup to use instead of autotuning (profiling runs)")
     ap.add_argument("--order", type=int, default=-1, choices=(-1, 0, 1),
@@ -495,6 +542,8 @@ def main():
     if not args.no_c3:
         out["c3"] = c3_leg(torch, W, dgx, order=args.order)
         out["c4"] = c4_leg(torch, W, dgx)
+    if not args.no_fluxes:
+        out["fluxes"] = flux_leg(torch, W, dgx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out))

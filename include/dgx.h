@@ -60,9 +60,20 @@ extern "C" {
 /* two-point volume fluxes (Eq. fluxdiffcons) */
 #define DGX_VF_RANOCHA 0    /* entropy-conservative (perfect gas only) */
 #define DGX_VF_DUCROS 1     /* Ducros split form                       */
+#define DGX_VF_KENNEDY_GRUBER 2  /* Kennedy-Gruber split form (perfect gas) */
+#define DGX_VF_PIROZZOLI 3  /* Pirozzoli split form (perfect gas)      */
 /* surface fluxes (Eqs. riemann_problem1-3) */
 #define DGX_SF_RUSANOV 0    /* local Lax-Friedrichs                     */
 #define DGX_SF_RANOCHA 1    /* EC flux at faces (entropy checks)        */
+#define DGX_SF_HLL 2        /* HLL, Davis wave-speed bounds (perfect gas) */
+/* The split forms listed in the Methodology section as interchangeable
+ * volume fluxes (Kennedy-Gruber: energy {{rho}}{{v.n}}{{E/rho}} +
+ * {{p}}{{v.n}}; Pirozzoli: {{rho}}{{v.n}}{{(E+p)/rho}}; both with momentum
+ * {{rho}}{{v.n}}{{v}} + {{p}} n) and the HLL interface flux are built for
+ * the 3D perfect-gas Euler equations at N = 3 (affine and curved elements,
+ * conforming meshes).  Every other combination of equation, degree,
+ * dimension and flux that the library was not built with makes dgx_create
+ * return DGX_E_INVAL. */
 /* boundary kinds (weak, through the surface flux with an external state) */
 #define DGX_BC_DIRICHLET 0
 #define DGX_BC_OUTFLOW 1

@@ -75,6 +75,9 @@ const RhsEntry kRhs[] = {
     RHS_ENTRY(3, 3, 0, 0, 0, 0), RHS_ENTRY(3, 3, 0, 0, 1, 0), RHS_ENTRY(3, 3, 1, 0, 0, 0),
     RHS_ENTRY(3, 3, 0, 0, 0, 1), RHS_ENTRY(3, 3, 0, 0, 1, 1), RHS_ENTRY(3, 4, 0, 0, 0, 1),
     RHS_ENTRY(3, 4, 0, 0, 1, 1), RHS_ENTRY(3, 3, 0, 1, 0, 1), RHS_ENTRY(3, 4, 0, 1, 0, 1),
+    // other split forms (Kennedy-Gruber, Pirozzoli) and the HLL surface flux
+    RHS_ENTRY(3, 3, 0, 2, 0, 0), RHS_ENTRY(3, 3, 0, 3, 0, 0), RHS_ENTRY(3, 3, 0, 0, 2, 0),
+    RHS_ENTRY(3, 3, 0, 2, 0, 1), RHS_ENTRY(3, 3, 0, 3, 0, 1), RHS_ENTRY(3, 3, 0, 1, 2, 1),
     // mixtures
     RHS_ENTRY(3, 4, 2, 1, 0, 1), RHS_ENTRY(3, 3, 2, 1, 0, 1), RHS_ENTRY(2, 3, 2, 1, 0, 1),
     RHS_ENTRY(2, 3, 3, 1, 0, 1), RHS_ENTRY(2, 3, 3, 1, 0, 0),
@@ -421,7 +424,7 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
     if (cfg->equation < 0 || cfg->equation > 3) return DGX_E_INVAL;
     const bool mix = cfg->equation >= DGX_EQ_EULER_MIX;
     if (mix && (!cfg->species || cfg->species->nspecies != 5)) return DGX_E_INVAL;
-    if (mix && cfg->volume_flux == DGX_VF_RANOCHA) return DGX_E_INVAL;
+    if (mix && cfg->volume_flux != DGX_VF_DUCROS) return DGX_E_INVAL;
     if (mix && cfg->surface_flux != DGX_SF_RUSANOV) return DGX_E_INVAL;
     if (cfg->equation == DGX_EQ_REACT_MIX && !cfg->reactions) return DGX_E_INVAL;
     if (mix && cfg->reactions) {

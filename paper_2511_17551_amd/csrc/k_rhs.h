@@ -468,6 +468,9 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                 if constexpr (SF == 0) {
                     if (side) rusanov<DIM, MIX>(own, ext, nrm, F);
                     else rusanov<DIM, MIX>(ext, own, nrm, F);
+                } else if constexpr (SF == 2) {
+                    if (side) hll<DIM, MIX>(own, ext, nrm, F);
+                    else hll<DIM, MIX>(ext, own, nrm, F);
                 } else {
                     if (side) ranocha_state<DIM, MIX>(own, ext, nrm, gamma, F);
                     else ranocha_state<DIM, MIX>(ext, own, nrm, gamma, F);
@@ -618,7 +621,12 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                         St<DIM, MIX> A, B;
                         lds_state<DIM, MIX>(esu, esq, NN, na, gamma, A);
                         lds_state<DIM, MIX>(esu, esq, NN, nb, gamma, B);
-                        ducros_state<DIM, MIX>(A, B, nbar, F);
+                        if constexpr (VF == 1) {
+                            ducros_state<DIM, MIX>(A, B, nbar, F);
+                        } else {
+                            static_assert(!MIX, "split forms other than Ducros are perfect-gas only");
+                            split_form_state<DIM, VF == 3>(A, B, nbar, F);
+                        }
                     }
 #pragma unroll
                     for (int v = 0; v < NV; ++v) ebuf[jb * NVP + v] = F[v];
@@ -786,6 +794,9 @@ __global__ void __launch_bounds__(128) k_mortar(RhsParams P, int nmort) {
     if constexpr (SF == 0) {
         if (sideL) rusanov<DIM, false>(A, B, nrm, F);
         else rusanov<DIM, false>(B, A, nrm, F);
+    } else if constexpr (SF == 2) {
+        if (sideL) hll<DIM, false>(A, B, nrm, F);
+        else hll<DIM, false>(B, A, nrm, F);
     } else {
         if (sideL) ranocha_state<DIM, false>(A, B, nrm, P.gamma, F);
         else ranocha_state<DIM, false>(B, A, nrm, P.gamma, F);

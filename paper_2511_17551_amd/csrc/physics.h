@@ -242,6 +242,35 @@ __device__ __forceinline__ void cons_of(const St<DIM, MIX> &s, double *u) {
     u[off + DIM] = s.rhoE;
 }
 
+// HLL flux with the Davis bounds S_L = min(v_L.n - c_L|n|, v_R.n - c_R|n|),
+// S_R = max(v_L.n + c_L|n|, v_R.n + c_R|n|) (scaled n): the upwind physical
+// flux when both bounds have one sign, otherwise the flux of the single
+// intermediate state that conserves the integral over the wave fan.
+template <int DIM, bool MIX>
+__device__ __forceinline__ void hll(const St<DIM, MIX> &L, const St<DIM, MIX> &R, const double *n,
+                                    double *F) {
+    constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
+    const double nn = wave_sqrt(dotn<DIM>(n, n));
+    const double vL = dotn<DIM>(L.v, n), vR = dotn<DIM>(R.v, n);
+    const double sL = fmin(vL - L.c * nn, vR - R.c * nn);
+    const double sR = fmax(vL + L.c * nn, vR + R.c * nn);
+    if (sL >= 0.0) {
+        phys_flux<DIM, MIX>(L, n, F);
+    } else if (sR <= 0.0) {
+        phys_flux<DIM, MIX>(R, n, F);
+    } else {
+        double fL[NV], fR[NV], uL[NV], uR[NV];
+        phys_flux<DIM, MIX>(L, n, fL);
+        phys_flux<DIM, MIX>(R, n, fR);
+        cons_of<DIM, MIX>(L, uL);
+        cons_of<DIM, MIX>(R, uR);
+        const double iw = 1.0 / (sR - sL);
+        const double sLR = sL * sR;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) F[k] = (sR * fL[k] - sL * fR[k] + sLR * (uR[k] - uL[k])) * iw;
+    }
+}
+
 template <int DIM, bool MIX>
 __device__ __forceinline__ void rusanov(const St<DIM, MIX> &L, const St<DIM, MIX> &R,
                                         const double *n, double *F) {
@@ -284,6 +313,29 @@ __device__ __forceinline__ void ranocha_state(const St<DIM, MIX> &L, const St<DI
 }
 
 // Ducros split-form flux: {{rho_s}} {{v}}.n, {{m}} {{v}}.n + {{p}} n, ({{rhoE}} + {{p}}) {{v}}.n
+// Kennedy-Gruber (PIRO false) and Pirozzoli (PIRO true) split forms as
+// two-point fluxes, perfect gas: mass flux {{rho}}{{v.n}}, momentum that
+// mass flux times {{v}} plus {{p}} n; energy that mass flux times {{E/rho}}
+// plus {{p}}{{v.n}} (Kennedy-Gruber) or times {{(E + p)/rho}} (Pirozzoli).
+template <int DIM, bool PIRO>
+__device__ __forceinline__ void split_form_state(const St<DIM, false> &L, const St<DIM, false> &R,
+                                                 const double *n, double *F) {
+    double vb[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) vb[c] = 0.5 * (L.v[c] + R.v[c]);
+    const double vn = dotn<DIM>(vb, n);
+    const double pbar = 0.5 * (L.p + R.p);
+    const double fm = 0.5 * (L.rho + R.rho) * vn;
+    F[0] = fm;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) F[1 + c] = fm * vb[c] + pbar * n[c];
+    if constexpr (PIRO) {
+        F[1 + DIM] = fm * (0.5 * ((L.rhoE + L.p) / L.rho + (R.rhoE + R.p) / R.rho));
+    } else {
+        F[1 + DIM] = fm * (0.5 * (L.rhoE / L.rho + R.rhoE / R.rho)) + pbar * vn;
+    }
+}
+
 template <int DIM, bool MIX>
 __device__ __forceinline__ void ducros_state(const St<DIM, MIX> &L, const St<DIM, MIX> &R,
                                              const double *n, double *F) {

@@ -1,0 +1,90 @@
+"""The Kennedy-Gruber and Pirozzoli volume fluxes and the HLL surface flux on
+the GPU, against the oracle (right-hand side, one SSPRK3 step).
+
+* Affine 3^3 periodic Taylor-Green state (3D Euler, N = 3) and the curved
+  2^3 periodic state, each with Kennedy-Gruber and with Pirozzoli volume
+  fluxes (Rusanov faces).
+* HLL faces (Ranocha volume flux on the affine mesh, Ducros on the curved
+  one) on the Taylor-Green state with a mean flow of (+2.5, -2.5, 0) times
+  the largest sound speed added: every x face is supersonic along its
+  normal (HLL takes f_L), every y face supersonic against it (f_R), every z
+  face subsonic (the intermediate-state flux), so all three branches run.
+* One SSPRK3 step with Kennedy-Gruber on the curved mesh."""
+import numpy as np
+import pytest
+
+from paper_2511_17551_amd import workloads as W
+from oracle import gas, ssprk
+from oracle.dgsem import Operator
+from tests.helpers import flux_scale, parity_err, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+RHS_TOL = 1e-11
+STEP_TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def dgx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2511_17551_amd import dgx as mod
+    return mod
+
+
+def tgv_euler(vf, sf, mean_flow=False):
+    c = W.case_c2(n=3, eq=W.EQ_EULER)
+    c.cfg = dict(c.cfg, volume_flux=vf, surface_flux=sf)
+    if mean_flow:
+        s = gas.pg_state(c.u0, 3, c.cfg["gamma"])
+        cmax = s["c"].max()
+        v = s["v"] + np.array([2.5, -2.5, 0.0])[:, None, None] * cmax
+        u = c.u0.copy()
+        u[1:4] = s["rho"] * v
+        u[4] = s["p"] / (c.cfg["gamma"] - 1.0) + 0.5 * s["rho"] * (v * v).sum(0)
+        # every node supersonic in x and y, subsonic in z
+        assert np.all(v[0] > s["c"]) and np.all(-v[1] > s["c"]) and np.all(np.abs(v[2]) < s["c"])
+        c.u0 = u
+    return c
+
+
+CASES = [
+    ("tgv_kennedy_gruber", lambda: tgv_euler(W.VF_KENNEDY_GRUBER, W.SF_RUSANOV)),
+    ("tgv_pirozzoli", lambda: tgv_euler(W.VF_PIROZZOLI, W.SF_RUSANOV)),
+    ("tgv_hll_supersonic", lambda: tgv_euler(W.VF_RANOCHA, W.SF_HLL, mean_flow=True)),
+    ("curved_kennedy_gruber", lambda: W.curved_periodic_case(n=2, N=3, volume_flux=W.VF_KENNEDY_GRUBER)),
+    ("curved_pirozzoli", lambda: W.curved_periodic_case(n=2, N=3, volume_flux=W.VF_PIROZZOLI)),
+    ("curved_ducros_hll", lambda: W.curved_periodic_case(n=2, N=3, volume_flux=W.VF_DUCROS,
+                                                         surface_flux=W.SF_HLL)),
+]
+
+
+@pytest.mark.parametrize("which", range(len(CASES)))
+def test_flux_variant_rhs(dgx, which):
+    name, make = CASES[which]
+    c = make()
+    print("case", name, flush=True)
+    op = Operator(c.cfg, c.mesh)
+    ref = op.rhs(c.u0)
+    s = dgx.Solver(c)
+    got = to_host(s.rhs(to_dev(c.u0)))
+    s.check()
+    s.close()
+    e = parity_err(got, ref, flux_scale(op, c.u0))
+    print("%s: parity %.3e" % (name, e))
+    assert e < RHS_TOL, (name, e)
+
+
+def test_kennedy_gruber_ssprk3_step(dgx):
+    c = W.curved_periodic_case(n=2, N=3, volume_flux=W.VF_KENNEDY_GRUBER)
+    op = Operator(c.cfg, c.mesh)
+    s = dgx.Solver(c)
+    u = to_dev(c.u0)
+    dt = 2e-3
+    s.ssprk3(u, dt, 1)
+    s.check()
+    got = to_host(u)
+    s.close()
+    ref = ssprk.step(lambda v, t: op.rhs(v, t), c.u0, 0.0, dt)
+    e = rel_err(got, ref)
+    print("Kennedy-Gruber step: %.3e" % e)
+    assert e < STEP_TOL
