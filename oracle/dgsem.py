@@ -69,8 +69,8 @@ class Operator:
     # volume and surface flux choices (the library's DGX_VF_* / DGX_SF_*
     # numbering); "kg" / "pirozzoli" as a surface flux serve the oracle's
     # own kinetic-energy checks
-    VOLUME = {0: gas.ranocha, 1: gas.ducros, 2: gas.kennedy_gruber, 3: gas.pirozzoli}
-    SURFACE = {0: gas.rusanov, 1: gas.ranocha, 2: gas.hll, "kg": gas.kennedy_gruber,
+    VOLUME = {0: gas.ranocha, 1: gas.ducros, 2: gas.kennedy_gruber, 3: gas.pirozzoli, 4: gas.central}
+    SURFACE = {0: gas.rusanov, 1: gas.ranocha, 2: gas.hll, 3: gas.hllc, "kg": gas.kennedy_gruber,
                "pirozzoli": gas.pirozzoli}
 
     def volume_flux(self, sL, sR, n):

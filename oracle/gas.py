@@ -17,7 +17,8 @@ Readings where the paper is silent:
   logarithmic mean);
 * the Lax-Friedrichs (Rusanov) dissipation uses the Davis estimate
   max(|v_L.n| + c_L|n|, |v_R.n| + c_R|n|);
-* HLL uses the Davis bounds min / max of v.n -+ c|n| over both sides;
+* HLL uses the Davis bounds min / max of v.n -+ c|n| over both sides, and
+  HLLC the same bounds with Toro's contact speed and star states;
 * the split forms are written as two-point fluxes with arithmetic means
   {{a}} = (a_L + a_R)/2 of the nodal quantities named in each docstring.
 """
@@ -158,6 +159,44 @@ def hll(sL, sR, n):
     with np.errstate(divide="ignore", invalid="ignore"):
         mid = (SR * fL - SL * fR + SL * SR * (uR - uL)) / (SR - SL)
     return np.where(SL >= 0.0, fL, np.where(SR <= 0.0, fR, mid))
+
+
+def central(sL, sR, n):
+    """The standard-DG form as a two-point flux (listed beside the split forms,
+    Sec. Methodology): the mean of the two physical fluxes, (f(u_L) + f(u_R)).n / 2."""
+    return 0.5 * (physical_flux(sL, n) + physical_flux(sR, n))
+
+
+def hllc(sL, sR, n):
+    """HLLC Riemann flux (named among the interface solvers, Sec.
+    Methodology), perfect gas, Davis bounds as in hll, on the unit normal
+    n/|n| and scaled by |n|.  Contact speed
+    S* = (p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R))
+         / (rho_L (S_L - u_L) - rho_R (S_R - u_R)),
+    star states rho_K (S_K - u_K)/(S_K - S*) (1, v_K + (S* - u_K) n,
+    E_K/rho_K + (S* - u_K)(S* + p_K/(rho_K (S_K - u_K)))); the flux is f_L,
+    f_L + S_L (U*_L - U_L), f_R + S_R (U*_R - U_R) or f_R as 0 lies left of
+    S_L, between S_L and S*, between S* and S_R, or right of S_R."""
+    nn = np.sqrt(dot(n, n))
+    nh = n / nn
+    uL, uR = dot(sL["v"], nh), dot(sR["v"], nh)
+    SL = np.minimum(uL - sL["c"], uR - sR["c"])
+    SR = np.maximum(uL + sL["c"], uR + sR["c"])
+    rL, rR = sL["rho"], sR["rho"]
+    Ss = (sR["p"] - sL["p"] + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR))
+
+    def star(st, S, u):
+        fac = st["rho"] * (S - u) / (S - Ss)
+        rows = [fac]
+        rows += [fac * (st["v"][c] + (Ss - u) * nh[c]) for c in range(st["v"].shape[0])]
+        rows.append(fac * (st["rhoE"] / st["rho"] + (Ss - u) * (Ss + st["p"] / (st["rho"] * (S - u)))))
+        return np.stack(rows, 0)
+
+    fL, fR = physical_flux(sL, nh), physical_flux(sR, nh)
+    FsL = fL + SL * (star(sL, SL, uL) - conserved(sL))
+    FsR = fR + SR * (star(sR, SR, uR) - conserved(sR))
+    F = np.where(SL >= 0.0, fL, np.where(Ss >= 0.0, FsL, np.where(SR > 0.0, FsR, fR)))
+    return F * nn
 
 
 def entropy_variables(s):

@@ -49,9 +49,11 @@ VF_RANOCHA = 0     # entropy-conservative two-point flux
 VF_DUCROS = 1      # Ducros split-form two-point flux
 VF_KENNEDY_GRUBER = 2  # Kennedy-Gruber split form (perfect gas)
 VF_PIROZZOLI = 3   # Pirozzoli split form (perfect gas)
+VF_CENTRAL = 4     # standard-DG form: mean of the physical fluxes (perfect gas)
 SF_RUSANOV = 0     # local Lax-Friedrichs surface flux
 SF_RANOCHA = 1     # EC flux at faces (entropy-conservation checks only)
 SF_HLL = 2         # HLL with Davis wave-speed bounds (perfect gas)
+SF_HLLC = 3        # HLLC, Davis bounds and Toro's contact speed (perfect gas)
 
 IND_RHO_P = 0      # shock indicator variable rho*p
 IND_P = 1          # shock indicator variable p

@@ -125,3 +125,80 @@ def test_hll_equals_the_intermediate_state_flux():
     scale = np.abs(fL).max() + np.abs(fR).max()
     assert np.abs(F - (fL + SL * (ustar - uL))).max() < 1e-12 * scale
     assert np.abs(F - (fR + SR * (ustar - uR))).max() < 1e-12 * scale
+
+
+def test_central_flux_reduces_to_the_collocation_derivative():
+    """With the standard-DG (central) two-point flux on affine elements, the
+    flux-differencing volume term equals the plain collocation derivative
+    sum_d D_d (f(u).Ja^d) of the nodal fluxes, less 2 D_nn f_n along each
+    line: zero at interior LGL nodes, at the end nodes the strong form's
+    boundary term f/w that this operator carries in its surface terms."""
+    from oracle.geometry import ref_deriv, tensor, flat
+    c = W.case_c2(n=2, eq=W.EQ_EULER)
+    c.cfg = dict(c.cfg, volume_flux=W.VF_CENTRAL)
+    op = Operator(c.cfg, c.mesh)
+    s = op.states(c.u0)
+    G = op.volume_terms(s, np.zeros(c.mesh.nelem))
+    n1 = op.b.n1
+    ref = np.zeros_like(G)
+    node = np.arange(n1 ** 3)
+    for d in range(3):
+        g = gas.physical_flux(s, op.Ja[d])
+        Dnn = np.diag(op.b.D)[(node // n1 ** d) % n1]
+        for v in range(5):
+            ref[v] += flat(ref_deriv(tensor(g[v], 3, n1), op.b.D, d, 3), 3) - 2.0 * Dnn * g[v]
+    assert np.abs(G - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_central_flux_consistency_and_symmetry():
+    rng = np.random.default_rng(15)
+    s, s2 = states(rng, 300), states(rng, 300)
+    n = rng.normal(size=(3, 300))
+    fphys = gas.physical_flux(s, n)
+    assert np.abs(gas.central(s, s, n) - fphys).max() < 1e-14 * np.abs(fphys).max()
+    assert np.array_equal(gas.central(s, s2, n), gas.central(s2, s, n))
+
+
+def contact(rng, m, un):
+    """Pairs of states across a contact: equal pressure and normal velocity,
+    different densities and tangential velocities."""
+    a, b = states(rng, m), states(rng, m)
+    n = rng.normal(size=(3, m))
+    nh = n / np.sqrt((n * n).sum(0))
+    out = []
+    for st in (a, b):
+        v = st["v"] - (st["v"] * nh).sum(0) * nh + un * nh
+        p = a["p"]
+        u = np.concatenate([st["rho"][None], st["rho"] * v, (p / 0.4 + 0.5 * st["rho"] * (v * v).sum(0))[None]])
+        out.append(gas.pg_state(u, 3, 1.4))
+    return out[0], out[1], n
+
+
+def test_hllc_consistency_upwinding_and_exact_contact():
+    rng = np.random.default_rng(16)
+    s, s2 = states(rng, 500), states(rng, 500)
+    n = rng.normal(size=(3, 500))
+    fphys = gas.physical_flux(s, n)
+    assert np.abs(gas.hllc(s, s, n) - fphys).max() < 1e-13 * np.abs(fphys).max()
+    nh = n / np.sqrt((n * n).sum(0))
+    shift = 1.5 * max((np.sqrt((st["v"] ** 2).sum(0)) + st["c"]).max() for st in (s, s2))
+    for sign, pick in ((1.0, 0), (-1.0, 1)):
+        ab = []
+        for st in (s, s2):
+            v = st["v"] + sign * shift * nh
+            u = np.concatenate([st["rho"][None], st["rho"] * v, (st["p"] / 0.4 + 0.5 * st["rho"] * (v * v).sum(0))[None]])
+            ab.append(gas.pg_state(u, 3, 1.4))
+        f = gas.physical_flux(ab[pick], n)
+        assert np.abs(gas.hllc(ab[0], ab[1], n) - f).max() < 1e-13 * np.abs(f).max()
+    # an isolated contact is resolved exactly: the flux of the upwind state
+    # (moving contact) or p n alone (stationary contact); HLL smears it
+    for un, pick in ((0.7, 0), (-0.7, 1)):
+        a, b, n = contact(rng, 400, un)
+        f = gas.physical_flux((a, b)[pick], n)
+        assert np.abs(gas.hllc(a, b, n) - f).max() < 1e-12 * np.abs(f).max()
+        assert np.abs(gas.hll(a, b, n) - f).max() > 1e-2 * np.abs(f).max()
+    a, b, n = contact(rng, 400, 0.0)
+    F = gas.hllc(a, b, n)
+    pn = a["p"] * n
+    assert np.abs(F[0]).max() < 1e-13 * np.abs(pn).max() and np.abs(F[4]).max() < 1e-13 * np.abs(pn).max()
+    assert np.abs(F[1:4] - pn).max() < 1e-13 * np.abs(pn).max()
