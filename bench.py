@@ -324,7 +324,9 @@ def flux_leg(torch, W, dgx, reps=20):
     variants = [("ranocha_rusanov", W.VF_RANOCHA, W.SF_RUSANOV),
                 ("kennedy_gruber_rusanov", W.VF_KENNEDY_GRUBER, W.SF_RUSANOV),
                 ("pirozzoli_rusanov", W.VF_PIROZZOLI, W.SF_RUSANOV),
-                ("ranocha_hll", W.VF_RANOCHA, W.SF_HLL)]
+                ("central_rusanov", W.VF_CENTRAL, W.SF_RUSANOV),
+                ("ranocha_hll", W.VF_RANOCHA, W.SF_HLL),
+                ("ranocha_hllc", W.VF_RANOCHA, W.SF_HLLC)]
     out = {}
     for name, vf, sf in variants:
         c = W.case_c2(eq=W.EQ_EULER)

@@ -62,14 +62,17 @@ extern "C" {
 #define DGX_VF_DUCROS 1     /* Ducros split form                       */
 #define DGX_VF_KENNEDY_GRUBER 2  /* Kennedy-Gruber split form (perfect gas) */
 #define DGX_VF_PIROZZOLI 3  /* Pirozzoli split form (perfect gas)      */
+#define DGX_VF_CENTRAL 4    /* standard-DG form, (f_L + f_R).n/2 (perfect gas) */
 /* surface fluxes (Eqs. riemann_problem1-3) */
 #define DGX_SF_RUSANOV 0    /* local Lax-Friedrichs                     */
 #define DGX_SF_RANOCHA 1    /* EC flux at faces (entropy checks)        */
 #define DGX_SF_HLL 2        /* HLL, Davis wave-speed bounds (perfect gas) */
+#define DGX_SF_HLLC 3       /* HLLC, Toro's contact speed (perfect gas)   */
 /* The split forms listed in the Methodology section as interchangeable
  * volume fluxes (Kennedy-Gruber: energy {{rho}}{{v.n}}{{E/rho}} +
  * {{p}}{{v.n}}; Pirozzoli: {{rho}}{{v.n}}{{(E+p)/rho}}; both with momentum
- * {{rho}}{{v.n}}{{v}} + {{p}} n) and the HLL interface flux are built for
+ * {{rho}}{{v.n}}{{v}} + {{p}} n; the standard-DG form (f_L + f_R).n/2) and
+ * the HLL and HLLC interface fluxes are built for
  * the 3D perfect-gas Euler equations at N = 3 (affine and curved elements,
  * conforming meshes).  Every other combination of equation, degree,
  * dimension and flux that the library was not built with makes dgx_create

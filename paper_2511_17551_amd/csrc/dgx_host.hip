@@ -78,6 +78,9 @@ const RhsEntry kRhs[] = {
     // other split forms (Kennedy-Gruber, Pirozzoli) and the HLL surface flux
     RHS_ENTRY(3, 3, 0, 2, 0, 0), RHS_ENTRY(3, 3, 0, 3, 0, 0), RHS_ENTRY(3, 3, 0, 0, 2, 0),
     RHS_ENTRY(3, 3, 0, 2, 0, 1), RHS_ENTRY(3, 3, 0, 3, 0, 1), RHS_ENTRY(3, 3, 0, 1, 2, 1),
+    // standard-DG volume form and the HLLC surface flux
+    RHS_ENTRY(3, 3, 0, 4, 0, 0), RHS_ENTRY(3, 3, 0, 4, 0, 1), RHS_ENTRY(3, 3, 0, 0, 3, 0),
+    RHS_ENTRY(3, 3, 0, 1, 3, 1),
     // mixtures
     RHS_ENTRY(3, 4, 2, 1, 0, 1), RHS_ENTRY(3, 3, 2, 1, 0, 1), RHS_ENTRY(2, 3, 2, 1, 0, 1),
     RHS_ENTRY(2, 3, 3, 1, 0, 1), RHS_ENTRY(2, 3, 3, 1, 0, 0),

@@ -471,6 +471,10 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                 } else if constexpr (SF == 2) {
                     if (side) hll<DIM, MIX>(own, ext, nrm, F);
                     else hll<DIM, MIX>(ext, own, nrm, F);
+                } else if constexpr (SF == 3) {
+                    static_assert(!MIX, "HLLC is perfect-gas only");
+                    if (side) hllc<DIM>(own, ext, nrm, F);
+                    else hllc<DIM>(ext, own, nrm, F);
                 } else {
                     if (side) ranocha_state<DIM, MIX>(own, ext, nrm, gamma, F);
                     else ranocha_state<DIM, MIX>(ext, own, nrm, gamma, F);
@@ -623,6 +627,8 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                         lds_state<DIM, MIX>(esu, esq, NN, nb, gamma, B);
                         if constexpr (VF == 1) {
                             ducros_state<DIM, MIX>(A, B, nbar, F);
+                        } else if constexpr (VF == 4) {
+                            central_state<DIM, MIX>(A, B, nbar, F);
                         } else {
                             static_assert(!MIX, "split forms other than Ducros are perfect-gas only");
                             split_form_state<DIM, VF == 3>(A, B, nbar, F);

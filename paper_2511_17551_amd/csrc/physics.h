@@ -271,6 +271,57 @@ __device__ __forceinline__ void hll(const St<DIM, MIX> &L, const St<DIM, MIX> &R
     }
 }
 
+// HLLC flux (perfect gas), the HLL bounds with Toro's contact speed
+// S* = (p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R))
+//      / (rho_L (S_L - u_L) - rho_R (S_R - u_R)) on the unit normal, and the
+// star states rho_K (S_K - u_K)/(S_K - S*) (1, v_K + (S* - u_K) n,
+// E_K/rho_K + (S* - u_K)(S* + p_K/(rho_K (S_K - u_K)))); scaled by |n|.
+template <int DIM>
+__device__ __forceinline__ void hllc(const St<DIM, false> &L, const St<DIM, false> &R, const double *n,
+                                     double *F) {
+    constexpr int NV = DIM + 2;
+    const double nn = wave_sqrt(dotn<DIM>(n, n));
+    const double inn = rcp(nn);
+    double nh[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) nh[c] = n[c] * inn;
+    const double uL = dotn<DIM>(L.v, nh), uR = dotn<DIM>(R.v, nh);
+    const double sL = fmin(uL - L.c, uR - R.c);
+    const double sR = fmax(uL + L.c, uR + R.c);
+    const St<DIM, false> &K = sL >= 0.0 ? L : R;  // the upwind state when 0 is outside the fan
+    if (sL >= 0.0 || sR <= 0.0) {
+        phys_flux<DIM, false>(K, n, F);
+        return;
+    }
+    const double mL = L.rho * (sL - uL), mR = R.rho * (sR - uR);
+    const double ss = (R.p - L.p + mL * uL - mR * uR) / (mL - mR);
+    const bool left = ss >= 0.0;
+    const St<DIM, false> &S = left ? L : R;
+    const double sk = left ? sL : sR, uk = left ? uL : uR, mk = left ? mL : mR;
+    double f[NV], u[NV], us[NV];
+    phys_flux<DIM, false>(S, nh, f);
+    cons_of<DIM, false>(S, u);
+    const double fac = mk / (sk - ss);
+    us[0] = fac;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) us[1 + c] = fac * (S.v[c] + (ss - uk) * nh[c]);
+    us[1 + DIM] = fac * (S.rhoE / S.rho + (ss - uk) * (ss + S.p / mk));
+#pragma unroll
+    for (int k = 0; k < NV; ++k) F[k] = (f[k] + sk * (us[k] - u[k])) * nn;
+}
+
+// The standard-DG form as a two-point flux: (f(u_L) + f(u_R)).n / 2.
+template <int DIM, bool MIX>
+__device__ __forceinline__ void central_state(const St<DIM, MIX> &L, const St<DIM, MIX> &R, const double *n,
+                                              double *F) {
+    constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
+    double fL[NV], fR[NV];
+    phys_flux<DIM, MIX>(L, n, fL);
+    phys_flux<DIM, MIX>(R, n, fR);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) F[k] = 0.5 * (fL[k] + fR[k]);
+}
+
 template <int DIM, bool MIX>
 __device__ __forceinline__ void rusanov(const St<DIM, MIX> &L, const St<DIM, MIX> &R,
                                         const double *n, double *F) {

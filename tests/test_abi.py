@@ -95,8 +95,9 @@ def bad_configs():
         ("mixture with the Kennedy-Gruber flux", dict(mix, volume_flux=W.VF_KENNEDY_GRUBER), sp, None),
         ("mixture with the HLL flux", dict(mix, surface_flux=W.SF_HLL), sp, None),
         ("Navier-Stokes with the Pirozzoli flux (not built)", dict(pg, volume_flux=W.VF_PIROZZOLI), None, None),
-        ("volume flux 4", dict(pg, eq=W.EQ_EULER, volume_flux=4), None, None),
-        ("surface flux 3", dict(pg, eq=W.EQ_EULER, surface_flux=3), None, None),
+        ("volume flux 5", dict(pg, eq=W.EQ_EULER, volume_flux=5), None, None),
+        ("surface flux 4", dict(pg, eq=W.EQ_EULER, surface_flux=4), None, None),
+        ("mixture with the HLLC flux", dict(mix, surface_flux=W.SF_HLLC), sp, None),
         ("reacting mixture without reactions", react, sp, None),
         ("A = 0", react, sp, table(A=bad_A)),
         ("A = inf", react, sp, table(A=inf_A)),

@@ -1,15 +1,21 @@
-"""The Kennedy-Gruber and Pirozzoli volume fluxes and the HLL surface flux on
-the GPU, against the oracle (right-hand side, one SSPRK3 step).
+"""The Kennedy-Gruber, Pirozzoli and standard-DG (central) volume fluxes and
+the HLL and HLLC surface fluxes on the GPU, against the oracle (right-hand
+side, one SSPRK3 step).
 
 * Affine 3^3 periodic Taylor-Green state (3D Euler, N = 3) and the curved
-  2^3 periodic state, each with Kennedy-Gruber and with Pirozzoli volume
+  2^3 periodic state, each with Kennedy-Gruber, Pirozzoli and central volume
   fluxes (Rusanov faces).
-* HLL faces (Ranocha volume flux on the affine mesh, Ducros on the curved
-  one) on the Taylor-Green state with a mean flow of (+2.5, -2.5, 0) times
-  the largest sound speed added: every x face is supersonic along its
-  normal (HLL takes f_L), every y face supersonic against it (f_R), every z
-  face subsonic (the intermediate-state flux), so all three branches run.
-* One SSPRK3 step with Kennedy-Gruber on the curved mesh."""
+* HLL and HLLC faces (Ranocha volume flux on the affine mesh, Ducros on the
+  curved one).  On the Taylor-Green state a mean flow of (+2.5, -2.5, 0)
+  times the largest sound speed is added: every x face is supersonic along
+  its normal (the flux is f_L), every y face supersonic against it (f_R),
+  every z face subsonic (HLL's intermediate state; HLLC's star states on
+  either side of the contact), so all branches run.
+* One SSPRK3 step with Kennedy-Gruber on the curved mesh.
+
+The Taylor-Green density is uniform, where the Kennedy-Gruber and Pirozzoli
+energy fluxes coincide; on the curved state they differ by 6e-2 in the
+parity norm, so there a swapped flux fails the 1e-11 bound.
 import numpy as np
 import pytest
 
@@ -55,6 +61,12 @@ CASES = [
     ("curved_pirozzoli", lambda: W.curved_periodic_case(n=2, N=3, volume_flux=W.VF_PIROZZOLI)),
     ("curved_ducros_hll", lambda: W.curved_periodic_case(n=2, N=3, volume_flux=W.VF_DUCROS,
                                                          surface_flux=W.SF_HLL)),
+    ("tgv_central", lambda: tgv_euler(W.VF_CENTRAL, W.SF_RUSANOV)),
+    ("curved_central", lambda: W.curved_periodic_case(n=2, N=3, volume_flux=W.VF_CENTRAL)),
+    ("tgv_hllc_supersonic", lambda: tgv_euler(W.VF_RANOCHA, W.SF_HLLC, mean_flow=True)),
+    ("tgv_hllc", lambda: tgv_euler(W.VF_RANOCHA, W.SF_HLLC)),
+    ("curved_ducros_hllc", lambda: W.curved_periodic_case(n=2, N=3, volume_flux=W.VF_DUCROS,
+                                                          surface_flux=W.SF_HLLC)),
 ]
 
 
