@@ -15,7 +15,7 @@ side, one SSPRK3 step).
 
 The Taylor-Green density is uniform, where the Kennedy-Gruber and Pirozzoli
 energy fluxes coincide; on the curved state they differ by 6e-2 in the
-parity norm, so there a swapped flux fails the 1e-11 bound.
+parity norm, so there a swapped flux fails the 1e-11 bound."""
 import numpy as np
 import pytest
 
