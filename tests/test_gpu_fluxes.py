@@ -11,6 +11,8 @@ side, one SSPRK3 step).
   its normal (the flux is f_L), every y face supersonic against it (f_R),
   every z face subsonic (HLL's intermediate state; HLLC's star states on
   either side of the contact), so all branches run.
+* The Navier-Stokes Taylor-Green state (BR1 viscous terms) with each of the
+  new volume and surface fluxes.
 * One SSPRK3 step with Kennedy-Gruber on the curved mesh.
 
 The Taylor-Green density is uniform, where the Kennedy-Gruber and Pirozzoli
@@ -53,6 +55,13 @@ def tgv_euler(vf, sf, mean_flow=False):
     return c
 
 
+def tgv_ns(vf, sf):
+    """The Navier-Stokes Taylor-Green state (BR1 viscous terms) with other fluxes."""
+    c = W.case_c2(n=3)
+    c.cfg = dict(c.cfg, volume_flux=vf, surface_flux=sf)
+    return c
+
+
 CASES = [
     ("tgv_kennedy_gruber", lambda: tgv_euler(W.VF_KENNEDY_GRUBER, W.SF_RUSANOV)),
     ("tgv_pirozzoli", lambda: tgv_euler(W.VF_PIROZZOLI, W.SF_RUSANOV)),
@@ -67,6 +76,11 @@ CASES = [
     ("tgv_hllc", lambda: tgv_euler(W.VF_RANOCHA, W.SF_HLLC)),
     ("curved_ducros_hllc", lambda: W.curved_periodic_case(n=2, N=3, volume_flux=W.VF_DUCROS,
                                                           surface_flux=W.SF_HLLC)),
+    ("tgv_ns_kennedy_gruber", lambda: tgv_ns(W.VF_KENNEDY_GRUBER, W.SF_RUSANOV)),
+    ("tgv_ns_pirozzoli", lambda: tgv_ns(W.VF_PIROZZOLI, W.SF_RUSANOV)),
+    ("tgv_ns_central", lambda: tgv_ns(W.VF_CENTRAL, W.SF_RUSANOV)),
+    ("tgv_ns_hll", lambda: tgv_ns(W.VF_RANOCHA, W.SF_HLL)),
+    ("tgv_ns_hllc", lambda: tgv_ns(W.VF_RANOCHA, W.SF_HLLC)),
 ]
 
 
