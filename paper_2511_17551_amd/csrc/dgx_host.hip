@@ -84,6 +84,9 @@ const RhsEntry kRhs[] = {
     // the same fluxes with the BR1 viscous terms (affine elements)
     RHS_ENTRY(3, 3, 1, 2, 0, 0), RHS_ENTRY(3, 3, 1, 3, 0, 0), RHS_ENTRY(3, 3, 1, 4, 0, 0),
     RHS_ENTRY(3, 3, 1, 0, 2, 0), RHS_ENTRY(3, 3, 1, 0, 3, 0),
+    // and at N = 4 on curved (or affine) perfect-gas elements
+    RHS_ENTRY(3, 4, 0, 2, 0, 1), RHS_ENTRY(3, 4, 0, 3, 0, 1), RHS_ENTRY(3, 4, 0, 4, 0, 1),
+    RHS_ENTRY(3, 4, 0, 1, 2, 1), RHS_ENTRY(3, 4, 0, 1, 3, 1),
     // mixtures
     RHS_ENTRY(3, 4, 2, 1, 0, 1), RHS_ENTRY(3, 3, 2, 1, 0, 1), RHS_ENTRY(2, 3, 2, 1, 0, 1),
     RHS_ENTRY(2, 3, 3, 1, 0, 1), RHS_ENTRY(2, 3, 3, 1, 0, 0),

@@ -12,7 +12,8 @@ side, one SSPRK3 step).
   every z face subsonic (HLL's intermediate state; HLLC's star states on
   either side of the contact), so all branches run.
 * The Navier-Stokes Taylor-Green state (BR1 viscous terms) with each of the
-  new volume and surface fluxes.
+  new volume and surface fluxes, and the curved periodic state at N = 4
+  with each of them (Ducros volume flux with the HLL / HLLC faces).
 * One SSPRK3 step with Kennedy-Gruber on the curved mesh.
 
 The Taylor-Green density is uniform, where the Kennedy-Gruber and Pirozzoli
@@ -81,6 +82,13 @@ CASES = [
     ("tgv_ns_central", lambda: tgv_ns(W.VF_CENTRAL, W.SF_RUSANOV)),
     ("tgv_ns_hll", lambda: tgv_ns(W.VF_RANOCHA, W.SF_HLL)),
     ("tgv_ns_hllc", lambda: tgv_ns(W.VF_RANOCHA, W.SF_HLLC)),
+    ("curved_N4_kennedy_gruber", lambda: W.curved_periodic_case(n=2, N=4, volume_flux=W.VF_KENNEDY_GRUBER)),
+    ("curved_N4_pirozzoli", lambda: W.curved_periodic_case(n=2, N=4, volume_flux=W.VF_PIROZZOLI)),
+    ("curved_N4_central", lambda: W.curved_periodic_case(n=2, N=4, volume_flux=W.VF_CENTRAL)),
+    ("curved_N4_ducros_hll", lambda: W.curved_periodic_case(n=2, N=4, volume_flux=W.VF_DUCROS,
+                                                            surface_flux=W.SF_HLL)),
+    ("curved_N4_ducros_hllc", lambda: W.curved_periodic_case(n=2, N=4, volume_flux=W.VF_DUCROS,
+                                                             surface_flux=W.SF_HLLC)),
 ]
 
 
