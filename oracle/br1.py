@@ -14,8 +14,10 @@ Readings:
   uses q_1 in the third direction; the viscous flux used is
   F_v^c = (0, tau_{.c}, (tau v)_c - q_c), q = -kappa grad T, and the
   equation is du/dt = ... + div F_v.
-* Primitive set W = (v, T) with T = p / (rho R); constant mu, Stokes
-  hypothesis, kappa = mu gamma R / ((gamma - 1) Pr).
+* Primitive set W = (v, T) with T = p / (rho R); constant mu, or
+  Sutherland's law mu(T) = mu (T/T0)^(3/2) (T0 + S)/(T + S) (Eq. sutherland)
+  when sutherland_S > 0; Stokes hypothesis, kappa = mu gamma R / ((gamma -
+  1) Pr).
 * The divergence is taken in strong form with the averaged interface flux,
   one scaled normal per face (from the element on the face's minus side).
 """
@@ -88,9 +90,14 @@ def viscous_rhs(op, u, s):
     b = op.b
     mesh = op.mesh
     R = cfg["R"]
-    mu = cfg["mu"]
-    kappa = mu * cfg["gamma"] * R / ((cfg["gamma"] - 1.0) * cfg["Pr"])
     W = primitives(s, R)
+    mu = cfg["mu"]
+    if cfg.get("sutherland_S", 0.0) > 0.0:
+        # Sutherland's law (Eq. sutherland), node by node
+        S, T0 = cfg["sutherland_S"], cfg["sutherland_T0"]
+        T = W[dim]
+        mu = mu * (T / T0) ** 1.5 * (T0 + S) / (T + S)
+    kappa = mu * cfg["gamma"] * R / ((cfg["gamma"] - 1.0) * cfg["Pr"])
     q = gradients(op, W)
     Fv = viscous_flux(s, q, mu, kappa, dim)            # list over c
     out = np.zeros_like(u)

@@ -267,7 +267,8 @@ def base_cfg(dim, N, eq, **kw):
                volume_flux=VF_RANOCHA, surface_flux=SF_RUSANOV,
                shock=False, alpha_max=0.5, alpha_min=1e-3, ind_var=IND_RHO_P,
                alpha_smooth=False, force_alpha=-1.0,
-               newton_tol=1e-10, newton_maxit=50, T_guess=300.0, positivity=False)
+               newton_tol=1e-10, newton_maxit=50, T_guess=300.0, positivity=False,
+               sutherland_S=0.0, sutherland_T0=1.0)
     cfg.update(kw)
     return cfg
 
