@@ -142,6 +142,11 @@ typedef struct dgx_config {
     int positivity;        /* 1 = Zhang-Shu positivity limiter after every SSPRK3 stage */
     const dgx_species *species;      /* mixture equations, else NULL */
     const dgx_reactions *reactions;  /* DGX_EQ_REACT_MIX, else NULL  */
+    /* DGX_EQ_NS viscosity law (Eq. sutherland): with sutherland_S > 0,
+     * mu(T) = mu (T/T0)^(3/2) (T0 + S)/(T + S) and the conductivity follows
+     * at constant Pr; sutherland_S = 0 keeps mu constant.  T0 > 0 required
+     * when S > 0 (else DGX_E_INVAL). */
+    double sutherland_S, sutherland_T0;
 } dgx_config;
 
 /* Mesh (host arrays, copied by dgx_set_mesh).  Conforming face row

@@ -44,9 +44,9 @@ void rhs_launch(const RhsParams &P, int mode, int blocks, int threads, size_t ld
     hipLaunchKernelGGL((k_rhs<DIM, N, EQ, VF, SF, CURV, MORT>), dim3(blocks), dim3(threads), lds, s, P, mode);
 }
 template <int DIM, int N>
-void grad_launch(const RhsParams &P, int blocks, int threads, hipStream_t s) {
+void grad_launch(const RhsParams &P, int blocks, int threads, hipStream_t s, double suthS, double suthT0) {
     const size_t lds = (size_t)P.epb * GradShape<DIM, N>::SLOT * sizeof(double);
-    hipLaunchKernelGGL((k_grad<DIM, N>), dim3(blocks), dim3(threads), lds, s, P);
+    hipLaunchKernelGGL((k_grad<DIM, N>), dim3(blocks), dim3(threads), lds, s, P, suthS, suthT0);
 }
 template <int DIM, int N, bool MIX>
 void ind_launch(const RhsParams &P, int iv, double amax, double amin, double *a, double *araw, int blocks,
@@ -336,9 +336,10 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
         RhsParams G = P;
         G.out = ctx->vpart.p;
         G.out2 = ctx->grad.p;
-        if (c.dim == 3 && c.N == 3) grad_launch<3, 3>(G, blocks, th, s);
-        else if (c.dim == 3 && c.N == 4) grad_launch<3, 4>(G, blocks, th, s);
-        else if (c.dim == 2 && c.N == 3) grad_launch<2, 3>(G, blocks, th, s);
+        const double sS = c.sutherland_S, sT = c.sutherland_T0;
+        if (c.dim == 3 && c.N == 3) grad_launch<3, 3>(G, blocks, th, s, sS, sT);
+        else if (c.dim == 3 && c.N == 4) grad_launch<3, 4>(G, blocks, th, s, sS, sT);
+        else if (c.dim == 2 && c.N == 3) grad_launch<2, 3>(G, blocks, th, s, sS, sT);
         else return set_err(ctx, DGX_E_INVAL, "NS gradients not built for this dim/N");
         tape_mark(tp, "k_grad", s);
     }
@@ -431,6 +432,8 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
     *out = nullptr;
     if ((cfg->dim != 2 && cfg->dim != 3) || (cfg->N != 3 && cfg->N != 4)) return DGX_E_INVAL;
     if (cfg->equation < 0 || cfg->equation > 3) return DGX_E_INVAL;
+    if (!(cfg->sutherland_S >= 0.0) || (cfg->sutherland_S > 0.0 && !(cfg->sutherland_T0 > 0.0)))
+        return DGX_E_INVAL;
     const bool mix = cfg->equation >= DGX_EQ_EULER_MIX;
     if (mix && (!cfg->species || cfg->species->nspecies != 5)) return DGX_E_INVAL;
     if (mix && cfg->volume_flux != DGX_VF_DUCROS) return DGX_E_INVAL;

@@ -33,8 +33,11 @@ struct GradShape {
     static constexpr int SLOT = SLOT0 > DIM * NW * NN ? SLOT0 : DIM * NW * NN;
 };
 
+// suthS > 0: Sutherland's law mu(T) = mu (T/T0)^(3/2) (T0 + S)/(T + S)
+// (Eq. sutherland) at every node, the conductivity scaled alike (constant
+// Pr); suthS = 0: constant mu.
 template <int DIM, int N>
-__global__ void __launch_bounds__(512) k_grad(RhsParams P) {
+__global__ void __launch_bounds__(512) k_grad(RhsParams P, double suthS, double suthT0) {
     using S = GradShape<DIM, N>;
     constexpr int N1 = N + 1, NN = S::NN, NF = S::NF, NW = S::NW, NSF = S::NSF;
     constexpr int NV = DIM + 2;
@@ -166,6 +169,13 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
     // nodal viscous flux
     double Fv[DIM][NW];
     {
+        double mu = P.mu, kappa = P.kappa;
+        if (suthS > 0.0) {
+            const double th = Wo[DIM] / suthT0;
+            const double f = th * sqrt(th) * (suthT0 + suthS) / (Wo[DIM] + suthS);
+            mu *= f;
+            kappa *= f;
+        }
         double div = 0.0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) div += q[k][k];
@@ -174,12 +184,12 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P) {
             double en = 0.0;
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
-                double t = P.mu * (q[c][k] + q[k][c]);
-                if (k == c) t -= (2.0 / 3.0) * P.mu * div;
+                double t = mu * (q[c][k] + q[k][c]);
+                if (k == c) t -= (2.0 / 3.0) * mu * div;
                 en = fma(t, Wo[k], en);
                 Fv[c][k] = t;
             }
-            Fv[c][DIM] = en + P.kappa * q[c][DIM];
+            Fv[c][DIM] = en + kappa * q[c][DIM];
         }
     }
     // divergence: volume part and the element's own half of the face terms.

@@ -51,7 +51,8 @@ class dgx_config(C.Structure):
                 ("ind_var", C.c_int), ("alpha_smooth", C.c_int), ("force_alpha", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int), ("T_guess", C.c_double),
                 ("positivity", C.c_int),
-                ("species", C.POINTER(dgx_species)), ("reactions", C.POINTER(dgx_reactions))]
+                ("species", C.POINTER(dgx_species)), ("reactions", C.POINTER(dgx_reactions)),
+                ("sutherland_S", C.c_double), ("sutherland_T0", C.c_double)]
 
 
 class dgx_mesh(C.Structure):
@@ -173,6 +174,7 @@ def dgx_create(cfg: dict, species=None, reactions=None):
     c.ind_var, c.alpha_smooth, c.force_alpha = cfg["ind_var"], int(bool(cfg["alpha_smooth"])), cfg["force_alpha"]
     c.newton_tol, c.newton_maxit, c.T_guess = cfg["newton_tol"], cfg["newton_maxit"], cfg["T_guess"]
     c.positivity = int(bool(cfg.get("positivity", False)))
+    c.sutherland_S, c.sutherland_T0 = cfg.get("sutherland_S", 0.0), cfg.get("sutherland_T0", 1.0)
     if species is not None:
         keep.sp = make_species(species)
         c.species = C.pointer(keep.sp)

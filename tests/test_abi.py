@@ -98,6 +98,8 @@ def bad_configs():
         ("volume flux 5", dict(pg, eq=W.EQ_EULER, volume_flux=5), None, None),
         ("surface flux 4", dict(pg, eq=W.EQ_EULER, surface_flux=4), None, None),
         ("mixture with the HLLC flux", dict(mix, surface_flux=W.SF_HLLC), sp, None),
+        ("negative Sutherland constant", dict(pg, sutherland_S=-1.0), None, None),
+        ("Sutherland law without a reference temperature", dict(pg, sutherland_S=110.0, sutherland_T0=0.0), None, None),
         ("reacting mixture without reactions", react, sp, None),
         ("A = 0", react, sp, table(A=bad_A)),
         ("A = inf", react, sp, table(A=inf_A)),
