@@ -92,6 +92,8 @@ const RhsEntry kRhs[] = {
     RHS_ENTRY(2, 3, 3, 1, 0, 1), RHS_ENTRY(2, 3, 3, 1, 0, 0),
     // non-conforming (mortar) meshes
     RHS_ENTRY_M(3, 3, 0, 0, 0), RHS_ENTRY_M(3, 3, 0, 0, 1), RHS_ENTRY_M(3, 4, 0, 0, 0), RHS_ENTRY_M(2, 3, 0, 0, 0),
+    // the other volume forms with Rusanov mortar faces
+    RHS_ENTRY_M(3, 3, 0, 2, 0), RHS_ENTRY_M(3, 3, 0, 3, 0), RHS_ENTRY_M(3, 3, 0, 4, 0),
 };
 
 struct IndEntry {

@@ -41,6 +41,20 @@ def test_small_amr_rhs(dgx, sf):
     assert e < RHS_TOL
 
 
+@pytest.mark.parametrize("vf", [W.VF_KENNEDY_GRUBER, W.VF_PIROZZOLI, W.VF_CENTRAL])
+def test_small_amr_rhs_other_volume_forms(dgx, vf):
+    """The Kennedy-Gruber, Pirozzoli and standard-DG volume forms on the
+    2:1 non-conforming mesh (Rusanov faces and mortars)."""
+    c = W.case_amr(base=4, radii=(0.4, 0.25), centre=(0.45, 0.5, 0.55))
+    c.cfg["volume_flux"] = vf
+    op = Operator(c.cfg, c.mesh)
+    ref = op.rhs(c.u0)
+    got = gpu_rhs(dgx, c)
+    e = parity_err(got, ref, flux_scale(op, c.u0))
+    print("small amr vf=%d parity %.3e" % (vf, e))
+    assert e < RHS_TOL
+
+
 def test_small_amr_ssprk3(dgx):
     c = W.case_amr(base=4, radii=(0.4, 0.25), centre=(0.45, 0.5, 0.55))
     op = Operator(c.cfg, c.mesh)
