@@ -76,7 +76,8 @@ extern "C" {
  * the 3D perfect-gas Euler equations at N = 3 (affine and curved elements,
  * conforming meshes; the three volume forms also on 2:1 non-conforming
  * meshes with Rusanov faces), at N = 4 (curved kernels, which also take
- * affine meshes) and for 3D Navier-Stokes at N = 3 (affine elements).  Every other combination of equation, degree,
+ * affine meshes), for 3D Navier-Stokes at N = 3 (affine elements) and for
+ * the 2D Euler equations at N = 3 (affine elements).  Every other combination of equation, degree,
  * dimension and flux that the library was not built with makes dgx_create
  * return DGX_E_INVAL. */
 /* boundary kinds (weak, through the surface flux with an external state) */

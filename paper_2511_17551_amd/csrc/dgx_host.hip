@@ -81,6 +81,9 @@ const RhsEntry kRhs[] = {
     // standard-DG volume form and the HLLC surface flux
     RHS_ENTRY(3, 3, 0, 4, 0, 0), RHS_ENTRY(3, 3, 0, 4, 0, 1), RHS_ENTRY(3, 3, 0, 0, 3, 0),
     RHS_ENTRY(3, 3, 0, 1, 3, 1),
+    // and for the 2D Euler equations (affine elements)
+    RHS_ENTRY(2, 3, 0, 2, 0, 0), RHS_ENTRY(2, 3, 0, 3, 0, 0), RHS_ENTRY(2, 3, 0, 4, 0, 0),
+    RHS_ENTRY(2, 3, 0, 0, 2, 0), RHS_ENTRY(2, 3, 0, 0, 3, 0),
     // the same fluxes with the BR1 viscous terms (affine elements)
     RHS_ENTRY(3, 3, 1, 2, 0, 0), RHS_ENTRY(3, 3, 1, 3, 0, 0), RHS_ENTRY(3, 3, 1, 4, 0, 0),
     RHS_ENTRY(3, 3, 1, 0, 2, 0), RHS_ENTRY(3, 3, 1, 0, 3, 0),

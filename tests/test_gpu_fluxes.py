@@ -12,8 +12,9 @@ side, one SSPRK3 step).
   every z face subsonic (HLL's intermediate state; HLLC's star states on
   either side of the contact), so all branches run.
 * The Navier-Stokes Taylor-Green state (BR1 viscous terms) with each of the
-  new volume and surface fluxes, and the curved periodic state at N = 4
-  with each of them (Ducros volume flux with the HLL / HLLC faces).
+  new volume and surface fluxes, the curved periodic state at N = 4 with
+  each of them (Ducros volume flux with the HLL / HLLC faces), and the 2D
+  isentropic vortex with each.
 * One SSPRK3 step with Kennedy-Gruber on the curved mesh.
 
 The Taylor-Green density is uniform, where the Kennedy-Gruber and Pirozzoli
@@ -63,6 +64,13 @@ def tgv_ns(vf, sf):
     return c
 
 
+def vortex(vf, sf):
+    """The 2D isentropic vortex (Euler, N = 3) with other fluxes."""
+    c = W.case_c1(n=6, surface_flux=sf)
+    c.cfg = dict(c.cfg, volume_flux=vf)
+    return c
+
+
 CASES = [
     ("tgv_kennedy_gruber", lambda: tgv_euler(W.VF_KENNEDY_GRUBER, W.SF_RUSANOV)),
     ("tgv_pirozzoli", lambda: tgv_euler(W.VF_PIROZZOLI, W.SF_RUSANOV)),
@@ -89,6 +97,11 @@ CASES = [
                                                             surface_flux=W.SF_HLL)),
     ("curved_N4_ducros_hllc", lambda: W.curved_periodic_case(n=2, N=4, volume_flux=W.VF_DUCROS,
                                                              surface_flux=W.SF_HLLC)),
+    ("vortex2d_kennedy_gruber", lambda: vortex(W.VF_KENNEDY_GRUBER, W.SF_RUSANOV)),
+    ("vortex2d_pirozzoli", lambda: vortex(W.VF_PIROZZOLI, W.SF_RUSANOV)),
+    ("vortex2d_central", lambda: vortex(W.VF_CENTRAL, W.SF_RUSANOV)),
+    ("vortex2d_hll", lambda: vortex(W.VF_RANOCHA, W.SF_HLL)),
+    ("vortex2d_hllc", lambda: vortex(W.VF_RANOCHA, W.SF_HLLC)),
 ]
 
 
