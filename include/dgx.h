@@ -66,7 +66,7 @@ extern "C" {
 /* surface fluxes (Eqs. riemann_problem1-3) */
 #define DGX_SF_RUSANOV 0    /* local Lax-Friedrichs                     */
 #define DGX_SF_RANOCHA 1    /* EC flux at faces (entropy checks)        */
-#define DGX_SF_HLL 2        /* HLL, Davis wave-speed bounds (perfect gas) */
+#define DGX_SF_HLL 2        /* HLL, Davis wave-speed bounds             */
 #define DGX_SF_HLLC 3       /* HLLC, Toro's contact speed (perfect gas)   */
 /* The split forms listed in the Methodology section as interchangeable
  * volume fluxes (Kennedy-Gruber: energy {{rho}}{{v.n}}{{E/rho}} +
@@ -77,7 +77,9 @@ extern "C" {
  * conforming meshes; the three volume forms also on 2:1 non-conforming
  * meshes with Rusanov faces), at N = 4 (curved kernels, which also take
  * affine meshes), for 3D Navier-Stokes at N = 3 (affine elements) and for
- * the 2D Euler equations at N = 3 (affine elements).  Every other combination of equation, degree,
+ * the 2D Euler equations at N = 3 (affine elements).  HLL is also built for
+ * the frozen 5-species equations at N = 4 on curved elements (frozen sound
+ * speed in the wave-speed bounds).  Every other combination of equation, degree,
  * dimension and flux that the library was not built with makes dgx_create
  * return DGX_E_INVAL. */
 /* boundary kinds (weak, through the surface flux with an external state) */

@@ -92,6 +92,7 @@ const RhsEntry kRhs[] = {
     RHS_ENTRY(3, 4, 0, 1, 2, 1), RHS_ENTRY(3, 4, 0, 1, 3, 1),
     // mixtures
     RHS_ENTRY(3, 4, 2, 1, 0, 1), RHS_ENTRY(3, 3, 2, 1, 0, 1), RHS_ENTRY(2, 3, 2, 1, 0, 1),
+    RHS_ENTRY(3, 4, 2, 1, 2, 1),  // HLL faces on the curved 5-species shock
     RHS_ENTRY(2, 3, 3, 1, 0, 1), RHS_ENTRY(2, 3, 3, 1, 0, 0),
     // non-conforming (mortar) meshes
     RHS_ENTRY_M(3, 3, 0, 0, 0), RHS_ENTRY_M(3, 3, 0, 0, 1), RHS_ENTRY_M(3, 4, 0, 0, 0), RHS_ENTRY_M(2, 3, 0, 0, 0),
@@ -442,7 +443,7 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
     const bool mix = cfg->equation >= DGX_EQ_EULER_MIX;
     if (mix && (!cfg->species || cfg->species->nspecies != 5)) return DGX_E_INVAL;
     if (mix && cfg->volume_flux != DGX_VF_DUCROS) return DGX_E_INVAL;
-    if (mix && cfg->surface_flux != DGX_SF_RUSANOV) return DGX_E_INVAL;
+    if (mix && cfg->surface_flux != DGX_SF_RUSANOV && cfg->surface_flux != DGX_SF_HLL) return DGX_E_INVAL;
     if (cfg->equation == DGX_EQ_REACT_MIX && !cfg->reactions) return DGX_E_INVAL;
     if (mix && cfg->reactions) {
         const dgx_reactions *r = cfg->reactions;

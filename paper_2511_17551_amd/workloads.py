@@ -52,7 +52,7 @@ VF_PIROZZOLI = 3   # Pirozzoli split form (perfect gas)
 VF_CENTRAL = 4     # standard-DG form: mean of the physical fluxes (perfect gas)
 SF_RUSANOV = 0     # local Lax-Friedrichs surface flux
 SF_RANOCHA = 1     # EC flux at faces (entropy-conservation checks only)
-SF_HLL = 2         # HLL with Davis wave-speed bounds (perfect gas)
+SF_HLL = 2         # HLL with Davis wave-speed bounds
 SF_HLLC = 3        # HLLC, Davis bounds and Toro's contact speed (perfect gas)
 
 IND_RHO_P = 0      # shock indicator variable rho*p

@@ -93,7 +93,7 @@ def bad_configs():
         ("mixture without species", mix, None, None),
         ("mixture with the Ranocha flux", dict(mix, volume_flux=W.VF_RANOCHA), sp, None),
         ("mixture with the Kennedy-Gruber flux", dict(mix, volume_flux=W.VF_KENNEDY_GRUBER), sp, None),
-        ("mixture with the HLL flux", dict(mix, surface_flux=W.SF_HLL), sp, None),
+        ("reacting mixture with the HLL flux (not built)", dict(react, surface_flux=W.SF_HLL), sp, table()),
         ("Navier-Stokes at N = 4 with the Pirozzoli flux (not built)", dict(pg, N=4, volume_flux=W.VF_PIROZZOLI), None, None),
         ("volume flux 5", dict(pg, eq=W.EQ_EULER, volume_flux=5), None, None),
         ("surface flux 4", dict(pg, eq=W.EQ_EULER, surface_flux=4), None, None),

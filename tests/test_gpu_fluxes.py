@@ -15,6 +15,7 @@ side, one SSPRK3 step).
   new volume and surface fluxes, the curved periodic state at N = 4 with
   each of them (Ducros volume flux with the HLL / HLLC faces), and the 2D
   isentropic vortex with each.
+* HLL faces on the curved 5-species Mach-3 shock (3^3 elements, N = 4).
 * One SSPRK3 step with Kennedy-Gruber on the curved mesh.
 
 The Taylor-Green density is uniform, where the Kennedy-Gruber and Pirozzoli
@@ -71,6 +72,16 @@ def vortex(vf, sf):
     return c
 
 
+def shock_hll():
+    """The curved 5-species Mach-3 shock (3^3 elements, N = 4, Ducros volume
+    flux, shocked elements blended) with HLL faces."""
+    from oracle.thermo import Mixture
+    mix = Mixture(W.Species())
+    c = W.case_c3(lambda rs, T: mix.rho_e(rs, T), lambda rs, T: mix.rho_cv(rs, T), n=3)
+    c.cfg = dict(c.cfg, surface_flux=W.SF_HLL)
+    return c
+
+
 CASES = [
     ("tgv_kennedy_gruber", lambda: tgv_euler(W.VF_KENNEDY_GRUBER, W.SF_RUSANOV)),
     ("tgv_pirozzoli", lambda: tgv_euler(W.VF_PIROZZOLI, W.SF_RUSANOV)),
@@ -102,6 +113,7 @@ CASES = [
     ("vortex2d_central", lambda: vortex(W.VF_CENTRAL, W.SF_RUSANOV)),
     ("vortex2d_hll", lambda: vortex(W.VF_RANOCHA, W.SF_HLL)),
     ("vortex2d_hllc", lambda: vortex(W.VF_RANOCHA, W.SF_HLLC)),
+    ("curved_air5_shock_hll", lambda: shock_hll()),
 ]
 
 
@@ -110,7 +122,7 @@ def test_flux_variant_rhs(dgx, which):
     name, make = CASES[which]
     c = make()
     print("case", name, flush=True)
-    op = Operator(c.cfg, c.mesh)
+    op = Operator(c.cfg, c.mesh, species=getattr(c, "species", None), reactions=getattr(c, "reactions", None))
     ref = op.rhs(c.u0)
     s = dgx.Solver(c)
     got = to_host(s.rhs(to_dev(c.u0)))
