@@ -15,7 +15,9 @@ import numpy as np
 
 def legendre(n, x):
     """P_n(x) and P_n'(x) by the three-term recurrence."""
-    x = np.asarray(x, float)
+    x = np.asarray(x)
+    if x.dtype.kind != "f":
+        x = x.astype(float)
     p0 = np.ones_like(x)
     if n == 0:
         return p0, np.zeros_like(x)
@@ -30,14 +32,15 @@ def legendre(n, x):
     return p1, d1
 
 
-def lgl(N):
+def lgl(N, dtype=np.float64):
     """LGL nodes (ascending) and weights for polynomial degree N.
 
     Nodes: -1, +1 and the N-1 roots of P_N', found by Newton's method on
     P_N' started from Chebyshev-Gauss-Lobatto points.  Weights:
-    w_j = 2 / (N (N+1) P_N(xi_j)^2).
+    w_j = 2 / (N (N+1) P_N(xi_j)^2).  ``dtype`` (float64 or longdouble) is
+    the precision of the iteration and the result.
     """
-    x = -np.cos(np.pi * np.arange(N + 1) / N)
+    x = -np.cos(np.pi * np.arange(N + 1, dtype=dtype) / N)
     inner = x[1:-1].copy()
     for _ in range(100):
         _, dp = legendre(N, inner)
@@ -48,7 +51,7 @@ def lgl(N):
         inner = inner - step
         if np.max(np.abs(step)) < 1e-16:
             break
-    x = np.concatenate(([-1.0], inner, [1.0]))
+    x = np.concatenate((np.array([-1.0], dtype), inner, np.array([1.0], dtype)))
     p, _ = legendre(N, x)
     w = 2.0 / (N * (N + 1) * p * p)
     return x, w
@@ -56,7 +59,7 @@ def lgl(N):
 
 def barycentric_weights(x):
     n = len(x)
-    lam = np.ones(n)
+    lam = np.ones(n, x.dtype)
     for j in range(n):
         for k in range(n):
             if k != j:
@@ -68,7 +71,7 @@ def derivative_matrix(x):
     """D_nj = l_j'(x_n) by the barycentric formula; diagonal = -sum of row."""
     lam = barycentric_weights(x)
     n = len(x)
-    D = np.zeros((n, n))
+    D = np.zeros((n, n), x.dtype)
     for i in range(n):
         for j in range(n):
             if i != j:
@@ -91,10 +94,10 @@ def interpolation_matrix(x, y):
 def legendre_vandermonde(x):
     """V_ij = phi_j(x_i) with orthonormal Legendre phi_j = sqrt((2j+1)/2) P_j."""
     n = len(x)
-    V = np.zeros((n, n))
+    V = np.zeros((n, n), x.dtype)
     for j in range(n):
         p, _ = legendre(j, x)
-        V[:, j] = np.sqrt((2 * j + 1) / 2.0) * p
+        V[:, j] = np.sqrt(x.dtype.type((2 * j + 1) / 2.0)) * p
     return V
 
 
@@ -112,13 +115,27 @@ def gauss_legendre(n):
     return x, w
 
 
-class Basis:
-    """Everything the oracle needs for one polynomial degree N."""
+def inverse(A):
+    """Matrix inverse in A's precision: LAPACK in float64, then Newton-Schulz
+    refinement X <- X (2I - A X) (quadratic) for extended precision, which
+    LAPACK does not offer."""
+    X = np.linalg.inv(A.astype(np.float64)).astype(A.dtype)
+    if A.dtype != np.float64:
+        I2 = 2 * np.eye(A.shape[0], dtype=A.dtype)
+        for _ in range(3):
+            X = X @ (I2 - A @ X)
+    return X
 
-    def __init__(self, N):
+
+class Basis:
+    """Everything the oracle needs for one polynomial degree N, in float64
+    or, for rounding studies, in extended precision (np.longdouble)."""
+
+    def __init__(self, N, dtype=np.float64):
         self.N = N
         self.n1 = N + 1
-        self.xi, self.w = lgl(N)
+        self.dtype = dtype
+        self.xi, self.w = lgl(N, dtype)
         self.D = derivative_matrix(self.xi)
         self.V = legendre_vandermonde(self.xi)
-        self.Vinv = np.linalg.inv(self.V)
+        self.Vinv = inverse(self.V)

@@ -55,7 +55,7 @@ def gradients(op, W):
         np.add.at(dref[d], (slice(None), eR[:, None], nr[None, :]), -(Ws - WR) / b.w[0])
     if len(mesh.bfaces):
         raise NotImplementedError("BR1 boundary conditions are not part of this operator")
-    q = np.zeros((dim, nw) + W.shape[1:])
+    q = np.zeros((dim, nw) + W.shape[1:], W.dtype)
     for c in range(dim):
         for d in range(dim):
             q[c] += op.Ja[d, c][None] * dref[d]

@@ -43,18 +43,23 @@ BC_DIRICHLET, BC_OUTFLOW, BC_SLIPWALL = 0, 1, 2
 
 
 class Operator:
-    def __init__(self, cfg, mesh, species=None, reactions=None):
+    def __init__(self, cfg, mesh, species=None, reactions=None, dtype=np.float64):
+        """``dtype`` float64 (the oracle) or np.longdouble (x87 80-bit, for
+        measuring the rounding of float64 evaluations: operators, metrics and
+        every step run in that precision on the same inputs)."""
         self.cfg = cfg
         self.mesh = mesh
         self.dim = mesh.dim
         self.N = mesh.N
-        self.b = Basis(self.N)
-        self.Ja, self.J = metrics(mesh.x, self.b, self.dim)
+        self.dtype = dtype
+        self.b = Basis(self.N, dtype)
+        self.Ja, self.J = metrics(np.asarray(mesh.x, dtype), self.b, self.dim)
         self.fn = [face_nodes(self.dim, self.N, f) for f in range(2 * self.dim)]
         self.eq = cfg["eq"]
         self.mix = Mixture(species) if self.eq in (EQ_EULER_MIX, EQ_REACT_MIX) else None
         self.kin = Kinetics(species, reactions) if self.eq == EQ_REACT_MIX else None
         self.nsub = subcell_normals(self.Ja, self.b, self.dim) if cfg.get("shock") else None
+        self.boundary_exact = None   # optional Phi(x) of Dirichlet boundaries (manufactured solutions)
         self.last = {}
 
     # ------------------------------------------------------------------
@@ -84,9 +89,9 @@ class Operator:
         cfg = self.cfg
         E = self.mesh.nelem
         if cfg.get("force_alpha", -1.0) >= 0.0:
-            return np.full(E, float(cfg["force_alpha"])), None
+            return np.full(E, cfg["force_alpha"], self.dtype), None
         if not cfg.get("shock"):
-            return np.zeros(E), None
+            return np.zeros(E, self.dtype), None
         eps = s["p"] if cfg.get("ind_var", 0) == 1 else s["rho"] * s["p"]
         Erat = modal_energy_ratio(eps, self.b, self.dim)
         alpha, raw = blending_factor(Erat, self.N, cfg["alpha_max"], cfg["alpha_min"])
@@ -103,7 +108,7 @@ class Operator:
         dim = self.dim
         nvar = self.cfg["nvar"]
         E = self.mesh.nelem
-        G = np.zeros((nvar, E, n1 ** dim))
+        G = np.zeros((nvar, E, n1 ** dim), self.dtype)
         use_fv = np.any(alpha > 0.0)
         for d in range(dim):
             sl = {k: (line_view(v, d, dim, n1) if isinstance(v, np.ndarray) else v)
@@ -117,18 +122,18 @@ class Operator:
                     nbar = 0.5 * (Jl[..., q] + Jl[..., p])
                     Fs[(q, p)] = self.volume_flux(nodes[q], nodes[p], nbar)
             shape = (nvar,) + Jl.shape[1:-1]
-            Fbar = [np.zeros(shape) for _ in range(n1 + 1)]
+            Fbar = [np.zeros(shape, self.dtype) for _ in range(n1 + 1)]
             for j in range(1, n1):
-                acc = np.zeros(shape)
+                acc = np.zeros(shape, self.dtype)
                 for p in range(j, n1):
                     for q in range(0, j):
                         acc += 2.0 * b.w[q] * b.D[q, p] * Fs[(q, p)]
                 Fbar[j] = acc
-            Gl = np.zeros(shape + (n1,))
+            Gl = np.zeros(shape + (n1,), self.dtype)
             a = alpha.reshape((1, E, 1))
             if use_fv:
                 ns = self.nsub[d]
-                Ffv = [np.zeros(shape) for _ in range(n1 + 1)]
+                Ffv = [np.zeros(shape, self.dtype) for _ in range(n1 + 1)]
                 for m in range(1, n1):
                     Ffv[m] = self.surface_fv(nodes[m - 1], nodes[m], ns[..., m])
             for n in range(n1):
@@ -144,8 +149,15 @@ class Operator:
         return gas.rusanov(sL, sR, n)
 
     # ------------------------------------------------------------------
-    def external_state(self, s_int, u_int, kind, state, n, T_int):
+    def external_state(self, s_int, u_int, kind, state, n, T_int, x_face=None):
+        """External state of a boundary face (Eq. system_equation, U = Phi on
+        the boundary, imposed weakly through the surface flux).  Dirichlet
+        takes the boundary's constant state, or, when ``boundary_exact`` is
+        set (a manufactured solution's Phi(x)), that function at the face
+        nodes ``x_face``."""
         if kind == BC_DIRICHLET:
+            if self.boundary_exact is not None:
+                return self.states(np.asarray(self.boundary_exact(x_face), self.dtype))
             ue = np.broadcast_to(state.reshape((-1,) + (1,) * (u_int.ndim - 1)), u_int.shape).copy()
             return self.states(ue)
         if kind == BC_OUTFLOW:
@@ -176,27 +188,34 @@ class Operator:
             F = self.surface_flux(sL, sR, n)
             np.add.at(G, (slice(None), eL[:, None], nl[None, :]), F / b.w[N])
             np.add.at(G, (slice(None), eR[:, None], nr[None, :]), -F / b.w[0])
-        for (e, f, bc) in mesh.bfaces:
-            d, side = divmod(int(f), 2)
+        # boundary faces, all faces of one local face index and boundary
+        # together (each boundary face node receives its one flux)
+        bf = mesh.bfaces
+        for f in range(2 * self.dim):
+            rows = bf[bf[:, 1] == f]
+            if len(rows) == 0:
+                continue
+            d, side = divmod(f, 2)
             nodes = self.fn[f]
-            ui = u[:, e, nodes]
-            si = gas.take(s, (np.array([[e]]), nodes[None, :]))
-            si = {k: (v[..., 0, :] if isinstance(v, np.ndarray) else v) for k, v in si.items()}
-            n = self.Ja[d][:, e, nodes]
-            Ti = si.get("T")
-            se = self.external_state(si, ui, int(mesh.bc_kind[bc]), mesh.bc_state[bc], n, Ti)
-            if side == 1:
-                F = self.surface_flux(si, se, n)
-                G[:, e, nodes] += F / b.w[N]
-            else:
-                F = self.surface_flux(se, si, n)
-                G[:, e, nodes] -= F / b.w[0]
+            for bc in np.unique(rows[:, 2]):
+                e = rows[rows[:, 2] == bc, 0]
+                idx = (e[:, None], nodes[None, :])
+                ui = u[(slice(None),) + idx]
+                si = gas.take(s, idx)
+                n = self.Ja[d][(slice(None),) + idx]
+                se = self.external_state(si, ui, int(mesh.bc_kind[bc]), mesh.bc_state[bc], n, si.get("T"),
+                                         x_face=mesh.x[(slice(None),) + idx])
+                if side == 1:
+                    np.add.at(G, (slice(None),) + idx, self.surface_flux(si, se, n) / b.w[N])
+                else:
+                    np.add.at(G, (slice(None),) + idx, -self.surface_flux(se, si, n) / b.w[0])
         if len(mesh.mortars):
             from .mortar import mortar_surface_terms
             mortar_surface_terms(self, s, G)
 
     # ------------------------------------------------------------------
     def rhs(self, u, t=0.0, alpha=None):
+        u = np.asarray(u, self.dtype)
         s = self.states(u)
         if alpha is None:
             alpha, raw = self.blending(s)

@@ -47,14 +47,14 @@ def metrics(x, basis, dim):
     dx = np.stack([np.stack([ref_deriv(X[c], D, d, dim) for d in range(dim)], 0)
                    for c in range(dim)], 0)  # dx[c][d]
     if dim == 2:
-        Ja = np.empty((2, 2) + X.shape[1:])
+        Ja = np.empty((2, 2) + X.shape[1:], X.dtype)
         Ja[0, 0] = dx[1, 1]
         Ja[0, 1] = -dx[0, 1]
         Ja[1, 0] = -dx[1, 0]
         Ja[1, 1] = dx[0, 0]
         J = dx[0, 0] * dx[1, 1] - dx[0, 1] * dx[1, 0]
     else:
-        Ja = np.empty((3, 3) + X.shape[1:])
+        Ja = np.empty((3, 3) + X.shape[1:], X.dtype)
         for n in range(3):
             m = (n + 1) % 3
             l = (n + 2) % 3
@@ -114,7 +114,7 @@ def subcell_normals(Ja, basis, dim):
         dJ = np.stack([ref_deriv(Jd[c], basis.D, d, dim) for c in range(dim)], 0)
         Jl = np.stack([line_view(flat(Jd[c], dim), d, dim, n1) for c in range(dim)], 0)
         dl = np.stack([line_view(flat(dJ[c], dim), d, dim, n1) for c in range(dim)], 0)
-        ns = np.zeros(Jl.shape[:-1] + (n1 + 1,))
+        ns = np.zeros(Jl.shape[:-1] + (n1 + 1,), Jl.dtype)
         ns[..., 0] = Jl[..., 0]
         for m in range(1, n1 + 1):
             ns[..., m] = ns[..., m - 1] + basis.w[m - 1] * dl[..., m - 1]

@@ -42,3 +42,34 @@ def parity_err(got, ref, scale):
     # a variable that is identically zero on both sides agrees exactly
     ratio = np.where(den > 0, num / np.where(den > 0, den, 1.0), np.where(num > 0, np.inf, 0.0))
     return float(ratio.max())
+
+
+def eps_units(got, ref, scale):
+    """Per variable ||got_v - ref_v||_inf / (eps_64 S_v): the difference in
+    units of float64 rounding at the flux-divergence scale."""
+    got = np.asarray(got, np.longdouble)
+    ref = np.asarray(ref, np.longdouble)
+    num = np.abs(got - ref).reshape(ref.shape[0], -1).max(1).astype(np.float64)
+    return num / (np.finfo(np.float64).eps * np.asarray(scale))
+
+
+def ld_reference(case, u=None):
+    """The oracle's right-hand side in extended precision (x87 80-bit long
+    double, eps 1.1e-19) on the same float64 inputs: the discrete operator's
+    value to far below float64 rounding."""
+    from oracle.dgsem import Operator
+    op = Operator(case.cfg, case.mesh, case.species, case.reactions, dtype=np.longdouble)
+    return op.rhs(case.u0 if u is None else u)
+
+
+def oracle_dt(op, u, cfl):
+    """Time step from the oracle's own states (the CFL rule of the workloads):
+    cfl * 2 / ((N+1) max_n sum_d (|v.Ja^d| + c |Ja^d|) / J_n), so that no
+    input of an oracle run comes from the library."""
+    from oracle import gas
+    s = op.states(u)
+    lam = 0.0
+    for d in range(op.dim):
+        Ja = op.Ja[d]
+        lam = lam + np.abs(gas.dot(s["v"], Ja)) + s["c"] * np.sqrt(gas.dot(Ja, Ja))
+    return float(cfl * 2.0 / ((op.N + 1) * np.max(lam / op.J)))

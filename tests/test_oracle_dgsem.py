@@ -27,6 +27,71 @@ def test_metric_identities_curved():
         assert np.abs(s).max() < 1e-13 * np.abs(op.Ja).max()
 
 
+def _mapped_volume(lo, hi, amp, q=12):
+    """Volume of the box [lo, hi] under the curved map x = X + amp s(X)(1,1,1),
+    s = sin(pi X) sin(pi Y) sin(pi Z): Gauss-Legendre quadrature of the map's
+    analytic Jacobian determinant 1 + amp (s_X + s_Y + s_Z)."""
+    g, w = np.polynomial.legendre.leggauss(q)
+    pts = [0.5 * (lo[d] + hi[d]) + 0.5 * (hi[d] - lo[d]) * g for d in range(3)]
+    X, Y, Z = np.meshgrid(*pts, indexing="ij")
+    p = math.pi
+    det = 1.0 + amp * p * (np.cos(p * X) * np.sin(p * Y) * np.sin(p * Z)
+                           + np.sin(p * X) * np.cos(p * Y) * np.sin(p * Z)
+                           + np.sin(p * X) * np.sin(p * Y) * np.cos(p * Z))
+    w3 = np.einsum("i,j,k->ijk", w, w, w) * np.prod([(hi[d] - lo[d]) / 2 for d in range(3)])
+    return float((det * w3).sum())
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_curved_jacobian_volumes(N):
+    """Eq. jacobian on the curved map: the quadrature of J over each element is
+    that element's volume under the analytic map (to the interpolation error of
+    the map, converging at order >= N + 1), and the elements tile the unit cube
+    (the map takes [0,1]^3 onto itself): sum_k sum_n w_n J_n = 1 to roundoff.
+    The elements' volumes differ from the uniform 1/n^3 by up to 24%, so a
+    wrong or dropped term in the determinant fails here."""
+    errs = []
+    for n in (2, 3):
+        c = W.curved_periodic_case(n=n, N=N)
+        op = Operator(c.cfg, c.mesh)
+        vol = (op.J * quad_weights(op)).sum(1)
+        assert abs(vol.sum() - 1.0) < 1e-14
+        exact = []
+        for e in range(n ** 3):
+            i, j, k = e % n, (e // n) % n, e // (n * n)
+            exact.append(_mapped_volume((i / n, j / n, k / n), ((i + 1) / n, (j + 1) / n, (k + 1) / n), 0.1))
+        exact = np.array(exact)
+        assert np.abs(exact * n ** 3 - 1.0).max() > 0.2
+        errs.append(np.abs(vol - exact).max() * n ** 3)
+    assert errs[0] < (2e-5 if N == 3 else 5e-8), errs
+    assert errs[0] / errs[1] > 1.5 ** (N + 1), errs
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_curved_metric_terms_against_the_map(N):
+    """Eqs. mapped_equation, jacobian: the curl-form metric terms Ja^i (rows
+    of the adjugate of dx/dxi) against the cofactors of the analytic map's
+    Jacobian, (h/2)^2 (a_j x a_k) with a_d = dx/dX_d, at every node.  The
+    curl form differentiates a degree-N interpolant, so its nodal error
+    falls like h^N (asserted: EOC >= N - 0.2 on 4^3 -> 8^3); a wrong index,
+    sign or cyclic order in the curl gives an O(1) error."""
+    errs = []
+    for n in (4, 8):
+        c = W.curved_periodic_case(n=n, N=N)
+        op = Operator(c.cfg, c.mesh)
+        X = W.structured_mesh(3, N, (n,) * 3, (0.0,) * 3, (1.0,) * 3, (True,) * 3)[0]
+        p, a, h = math.pi, 0.1, 1.0 / n
+        g = a * p * np.array([np.cos(p * X[0]) * np.sin(p * X[1]) * np.sin(p * X[2]),
+                              np.sin(p * X[0]) * np.cos(p * X[1]) * np.sin(p * X[2]),
+                              np.sin(p * X[0]) * np.sin(p * X[1]) * np.cos(p * X[2])])
+        A = np.array([[(1.0 if cc == d else 0.0) + g[d] for d in range(3)] for cc in range(3)]) * (h / 2)
+        Ja = np.array([np.cross(A[:, (i + 1) % 3], A[:, (i + 2) % 3], axis=0) for i in range(3)])
+        errs.append(np.abs(op.Ja - Ja).max() / np.abs(Ja).max())
+    eoc = math.log2(errs[0] / errs[1])
+    assert errs[1] < (1e-3 if N == 3 else 5e-5), errs
+    assert eoc >= N - 0.2, (errs, eoc)
+
+
 @pytest.mark.parametrize("alpha", [0.0, 0.5, 1.0])
 @pytest.mark.parametrize("N", [3, 4])
 def test_freestream_curved(alpha, N):
