@@ -183,6 +183,10 @@ typedef struct dgx_newton_stats {
     int64_t first_bad;        /* first non-converged node, or -1           */
     int64_t substeps_total;   /* dgx_chem_step: sum of per-node substeps   */
     int32_t substeps_max;     /* dgx_chem_step: max per-node substeps (0 otherwise) */
+    int64_t fallbacks;        /* dgx_thermo with DGX_GUESS_SURROGATE: nodes whose
+                                 solve from the learned guess failed and was
+                                 redone from T_guess (their iteration counts
+                                 include both attempts)                    */
 } dgx_newton_stats;
 
 typedef struct dgx_ctx dgx_ctx;  /* opaque */
@@ -233,7 +237,10 @@ int dgx_max_dt(dgx_ctx *ctx, const double *u, double cfl, double *dt_host, void 
 /* Per-node temperature from energy (Appendix Eqs. Internal_energy and
  * eos): Newton on sum rho_s e_s(T) = rho e to |dT| <= newton_tol*T, started
  * from T_guess (DGX_GUESS_FREESTREAM) or the trained surrogate
- * (DGX_GUESS_SURROGATE).  u: device [nvar][nelem][nn] of a mixture context,
+ * (DGX_GUESS_SURROGATE); a node whose solve from the surrogate's guess fails
+ * (no convergence within newton_maxit, or a non-finite or non-positive
+ * iterate) is solved again from T_guess, so the converged T does not depend
+ * on the network (stats->fallbacks counts such nodes).  u: device [nvar][nelem][nn] of a mixture context,
  * or nstates = count of a packed [nvar][count] state set when the mesh is not
  * used (pass nstates > 0).  T, p (p may be NULL): device [count].  With
  * stats (host) the iteration counts are gathered and the call synchronises;
@@ -320,6 +327,17 @@ int dgx_check(dgx_ctx *ctx, void *stream);
  * context's mixture at one temperature (host computation, for building
  * states).  e, cv: host [5]. */
 int dgx_species_energy(const dgx_ctx *ctx, double T, double *e, double *cv);
+
+/* Mixture thermal energy and heat capacity densities (Appendix,
+ * Thermodynamics, Eq. Internal_energy; Governing Equations, Eq.
+ * internal_energies): rho e = sum_s rho_s e_s(T_i) and rho cv = sum_s rho_s
+ * cv_s(T_i) for n states, on the host (for building mixture states; no
+ * device work).  rs: host [5][n] species densities (kg/m^3, order N2, O2,
+ * NO, N, O), T: host [n] temperatures (K, > 0), rhoe, rhocv: host [n] outputs
+ * (either may be NULL, not both).  DGX_E_INVAL without a mixture context,
+ * for n < 0 or a non-positive T (no output written then). */
+int dgx_mixture_energy(const dgx_ctx *ctx, const double *rs, const double *T, int64_t n, double *rhoe,
+                       double *rhocv);
 
 /* Kernel timing for profiling: enqueue `reps` evaluations of the
  * right-hand side in the fused form of the second SSPRK3 stage

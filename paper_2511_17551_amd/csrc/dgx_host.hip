@@ -846,7 +846,7 @@ static int collect_stats(dgx_ctx *ctx, int64_t count, int maxit, dgx_newton_stat
     }
     stats->substeps_total = stot;
     stats->substeps_max = smax;
-    int64_t tot = 0, bad = 0, first = -1;
+    int64_t tot = 0, bad = 0, first = -1, fallbacks = 0;
     int mx = 0;
     double wsum = 0.0;
     int64_t nw = 0;
@@ -854,6 +854,10 @@ static int collect_stats(dgx_ctx *ctx, int64_t count, int maxit, dgx_newton_stat
         int wm = 0;
         for (int64_t j = i; j < std::min(count, i + 64); ++j) {
             int it = h[j];
+            if (it >= 0 && (it & kItersFallback)) {
+                ++fallbacks;
+                it &= ~kItersFallback;
+            }
             if (it < 0) {
                 ++bad;
                 if (first < 0) first = j;
@@ -872,6 +876,7 @@ static int collect_stats(dgx_ctx *ctx, int64_t count, int maxit, dgx_newton_stat
     stats->iters_wave_max_mean = nw ? wsum / nw : 0.0;
     stats->nonconverged = bad;
     stats->first_bad = first;
+    stats->fallbacks = fallbacks;
     if (bad) return set_err(ctx, DGX_E_NOCONV, std::to_string(bad) + " nodes did not converge");
     return DGX_OK;
 }
@@ -975,6 +980,25 @@ int dgx_species_energy(const dgx_ctx *ctx, double T, double *e, double *cv) {
         }
         e[s] = es;
         cv[s] = cs;
+    }
+    return DGX_OK;
+}
+
+int dgx_mixture_energy(const dgx_ctx *ctx, const double *rs, const double *T, int64_t n, double *rhoe,
+                       double *rhocv) {
+    if (!ctx || !ctx->has_sp || n < 0 || (n > 0 && (!rs || !T || (!rhoe && !rhocv)))) return DGX_E_INVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (!(T[i] > 0.0)) return DGX_E_INVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        double e[kNS], cv[kNS];
+        dgx_species_energy(ctx, T[i], e, cv);
+        double se = 0.0, sc = 0.0;
+        for (int s = 0; s < kNS; ++s) {
+            se += rs[(size_t)s * n + i] * e[s];
+            sc += rs[(size_t)s * n + i] * cv[s];
+        }
+        if (rhoe) rhoe[i] = se;
+        if (rhocv) rhocv[i] = sc;
     }
     return DGX_OK;
 }

@@ -44,6 +44,9 @@ constexpr int kMortBase = -(1 << 24);
 
 // Device error flags (bit mask), sticky until dgx_check.
 enum : unsigned { FLAG_NONPHYS = 1u, FLAG_NOCONV = 2u };
+// per-node iteration counts: this bit marks a solve from a given guess that
+// failed and was redone from the freestream guess
+constexpr int kItersFallback = 1 << 20;
 
 struct RhsParams {
     int nelem;

@@ -284,14 +284,25 @@ __global__ void __launch_bounds__(256) k_thermo(const double *__restrict__ u, in
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     double rs[kNS], rho;
-    // guess: the given one, or with warm != 0 the node's previous T (the
-    // right-hand side's solves), else T0; a failed warm start retries from T0
+    // guess: the given one (a learned guess), or with warm != 0 the node's
+    // previous T (the right-hand side's solves), else T0.  A failed warm
+    // start, and a failed solve from a given guess, are retried from T0, so
+    // the converged T never depends on how good the guess was; the
+    // iteration count then includes both attempts, and the retry is marked
+    // in the count (bit kItersFallback) for the statistics.
     double t = Tguess ? Tguess[i] : (warm ? T[i] : T0);
-    const int it = node_temperature<DIM>(u, (size_t)count, (size_t)i, t, T0, tol, maxit, M, warm, rs, rho);
+    int it = node_temperature<DIM>(u, (size_t)count, (size_t)i, t, T0, tol, maxit, M, warm, rs, rho);
+    bool fell_back = false;
+    if (Tguess && it < 0) {
+        t = T0;
+        const int it2 = node_temperature<DIM>(u, (size_t)count, (size_t)i, t, T0, tol, maxit, M, 0, rs, rho);
+        it = it2 < 0 ? -1 : it2 + maxit;
+        fell_back = true;
+    }
     T[i] = t;
     if (pout) pout[i] = mix_rR(M, rs) * t;
     if (cout) cout[i] = mix_sound(M, rs, rho, t);
-    if (iters) iters[i] = it;
+    if (iters) iters[i] = it < 0 ? -1 : (fell_back ? (it | kItersFallback) : it);
     if (it < 0) atomicOr(flags, FLAG_NOCONV);
 }
 

@@ -65,7 +65,7 @@ class dgx_mesh(C.Structure):
 class dgx_newton_stats(C.Structure):
     _fields_ = [("nodes", C.c_int64), ("iters_total", C.c_int64), ("iters_max", C.c_int32),
                 ("iters_wave_max_mean", C.c_double), ("nonconverged", C.c_int64), ("first_bad", C.c_int64),
-                ("substeps_total", C.c_int64), ("substeps_max", C.c_int32)]
+                ("substeps_total", C.c_int64), ("substeps_max", C.c_int32), ("fallbacks", C.c_int64)]
 
 
 def _load():
@@ -92,6 +92,8 @@ def _load():
         "dgx_surrogate_grad": ([vp, vp, vp, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float), vp], C.c_int),
         "dgx_check": ([vp, vp], C.c_int),
         "dgx_species_energy": ([vp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+        "dgx_mixture_energy": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int64,
+                                C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
         "dgx_kernel_times": ([vp, vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_char_p,
                               C.c_size_t, vp], C.c_int),
         "dgx_autotune": ([vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), vp], C.c_int),
@@ -109,9 +111,10 @@ def _load():
 
 lib = _load()
 EXPORTED = ("dgx_create", "dgx_set_mesh", "dgx_rhs", "dgx_ssprk3_step", "dgx_limit_positivity", "dgx_max_dt", "dgx_thermo",
+
             "dgx_chem_step",
             "dgx_last_alpha", "dgx_surrogate_set", "dgx_surrogate_get", "dgx_surrogate_train",
-            "dgx_surrogate_predict", "dgx_surrogate_init", "dgx_surrogate_grad", "dgx_check", "dgx_species_energy", "dgx_kernel_times", "dgx_autotune",
+            "dgx_surrogate_predict", "dgx_surrogate_init", "dgx_surrogate_grad", "dgx_check", "dgx_species_energy", "dgx_mixture_energy", "dgx_kernel_times", "dgx_autotune",
             "dgx_set_launch", "dgx_get_launch", "dgx_last_error", "dgx_destroy")
 
 
@@ -244,7 +247,7 @@ def dgx_thermo(ctx, u, T, p=None, guess=GUESS_FREESTREAM, nstates=0, stream=None
         _raise(ctx, rc)
     return dict(nodes=st.nodes, iters_total=st.iters_total, iters_max=st.iters_max,
                 iters_wave_max_mean=st.iters_wave_max_mean, nonconverged=st.nonconverged,
-                first_bad=st.first_bad, rc=rc)
+                first_bad=st.first_bad, fallbacks=st.fallbacks, rc=rc)
 
 
 def dgx_chem_step(ctx, u, dt, tol=1e-13, maxit=50, stream=None, check=True, stats=True):
@@ -334,6 +337,19 @@ def dgx_species_energy(ctx, T):
     return np.array(e[:]), np.array(cv[:])
 
 
+def dgx_mixture_energy(ctx, rs, T):
+    """(rho e, rho cv) of host states: rs (5, n), T (n,) -> two (n,) arrays."""
+    rs = np.ascontiguousarray(rs, np.float64)
+    T = np.ascontiguousarray(T, np.float64)
+    n = T.shape[0]
+    if rs.shape != (5, n):
+        raise ValueError("rs must have shape (5, n)")
+    rhoe = np.empty(n)
+    rhocv = np.empty(n)
+    _raise(ctx, lib.dgx_mixture_energy(ctx, _ptr(rs), _ptr(T), n, _ptr(rhoe), _ptr(rhocv)))
+    return rhoe, rhocv
+
+
 def dgx_kernel_times(ctx, u, reps=20, stream=None):
     """{kernel name: average ms} of one fused-stage right-hand side."""
     ms = (C.c_double * 8)()
@@ -413,18 +429,19 @@ class Solver:
 
 
 def mixture_energy_fns(ctx):
-    """energy(rho_s, T), cv(rho_s, T) built from the library's species tables
-    (used to build mixture states when the oracle is not involved)."""
+    """energy(rho_s, T), cv(rho_s, T) from dgx_mixture_energy (used to build
+    mixture states when the oracle is not involved): the arrays are broadcast
+    to one shape, flattened to (5, n) and (n,), and the library's results
+    reshaped back."""
     def make(which):
         def fn(rs, T):
             if (ctx.value if isinstance(ctx, C.c_void_p) else ctx) not in _LIVE:
                 raise RuntimeError("mixture energy functions used after their context was destroyed")
+            rs = np.asarray(rs, float)
             T = np.asarray(T, float)
             shape = np.broadcast_shapes(rs.shape[1:], T.shape)
-            Tb = np.broadcast_to(T, shape)
-            uniq, inv = np.unique(Tb, return_inverse=True)
-            tab = np.array([dgx_species_energy(ctx, float(t))[which] for t in uniq])  # (nu, 5)
-            es = tab[inv.reshape(shape)]                                              # shape + (5,)
-            return np.sum(np.moveaxis(es, -1, 0) * rs, axis=0)
+            rsb = np.broadcast_to(rs, (rs.shape[0],) + shape).reshape(rs.shape[0], -1)
+            Tb = np.broadcast_to(T, shape).reshape(-1)
+            return dgx_mixture_energy(ctx, rsb, Tb)[which].reshape(shape)
         return fn
     return make(0), make(1)

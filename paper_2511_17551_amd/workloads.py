@@ -345,6 +345,33 @@ def curved_periodic_case(n=3, N=3, eq=EQ_EULER, amp=0.1, seed=7, **kw):
     return Case("curved_periodic", cfg, mesh, u0)
 
 
+def curved_channel_case(n=3, N=3, mach=2.0, amp=0.1, seed=7, **kw):
+    """Perfect-gas supersonic channel on the curved unit cube: x = 0 is a
+    Dirichlet inflow (rho 1, p 1, u = mach * c along x), x = 1 an outflow
+    (external state = interior state), y and z periodic.  The initial state
+    is the inflow state plus the smooth seeded perturbation of
+    ``curved_periodic_case`` at a tenth of its amplitude."""
+    x, faces, bfaces = structured_mesh(3, N, (n, n, n), (0.0,) * 3, (1.0,) * 3, (False, True, True),
+                                       lambda X: curved_map(X, amp), bc_lo=(0, None, None),
+                                       bc_hi=(1, None, None))
+    cfg = base_cfg(3, N, EQ_EULER, **kw)
+    g = cfg["gamma"]
+    uin = mach * math.sqrt(g)
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, 3, size=(3, 3))
+    ph = rng.uniform(0, 2 * math.pi, 3)
+    arg = [2 * math.pi * (k[i, 0] * x[0] + k[i, 1] * x[1] + k[i, 2] * x[2]) + ph[i] for i in range(3)]
+    rho = 1.0 + 0.03 * np.sin(arg[0])
+    v = (uin + 0.02 * np.cos(arg[1]), 0.02 * np.sin(arg[2]), 0.01 * np.cos(arg[0]))
+    p = 1.0 + 0.025 * np.cos(arg[2])
+    u0 = _pg_conserved(rho, v, p, g)
+    inflow = _pg_conserved(np.array(1.0), (np.array(uin), np.array(0.0), np.array(0.0)), np.array(1.0), g)
+    bc_state = np.stack([inflow, inflow])
+    mesh = Mesh(3, N, x, faces, bfaces, np.zeros((0, 7), np.int32),
+                np.array([BC_DIRICHLET, BC_OUTFLOW], np.int32), bc_state)
+    return Case("curved_channel", cfg, mesh, u0)
+
+
 def curved_map(X, amp=0.1):
     """x = X + amp*sin(pi X)sin(pi Y)sin(pi Z) added to every coordinate."""
     s = amp * np.sin(math.pi * X[0]) * np.sin(math.pi * X[1]) * np.sin(math.pi * X[2])
@@ -392,7 +419,7 @@ def far_chem_states(n, seed=11):
 
 
 def case_c3(energy, cv, n=24, N=4, seed=3, T1=300.0, p1=1.0e4, mach=3.0, xs=0.3,
-            shock=True, force_alpha=-1.0):
+            shock=True, force_alpha=-1.0, outflow=False):
     """3D frozen 5-species Euler on the curved hex mesh with a planar shock.
 
     ``energy(rho_s, T)`` and ``cv(rho_s, T)`` (thermal energy and heat
@@ -400,8 +427,9 @@ def case_c3(energy, cv, n=24, N=4, seed=3, T1=300.0, p1=1.0e4, mach=3.0, xs=0.3,
     (T1, p1), velocity mach * frozen sound speed along x; post-shock state
     from the gamma = 1.4 Rankine-Hugoniot ratios, expressed through the
     mixture energy at the post-shock temperature.  x = 0 carries the
-    pre-shock and x = 1 the post-shock state (Dirichlet); y and z are
-    periodic.
+    pre-shock and x = 1 the post-shock state (Dirichlet; with ``outflow``
+    x = 1 is an outflow boundary instead, external state = interior state);
+    y and z are periodic.
     """
     sp = Species()
     x, faces, bfaces = structured_mesh(3, N, (n, n, n), (0.0,) * 3, (1.0,) * 3,
@@ -442,7 +470,7 @@ def case_c3(energy, cv, n=24, N=4, seed=3, T1=300.0, p1=1.0e4, mach=3.0, xs=0.3,
     bc_state = np.stack([st(p1 / ((Y0 * Rs).sum() * T1), T1, u1),
                          st(p1 / ((Y0 * Rs).sum() * T1) * r_ratio, T2, u1 / r_ratio)])
     mesh = Mesh(3, N, x, faces, bfaces, np.zeros((0, 7), np.int32),
-                np.array([BC_DIRICHLET, BC_DIRICHLET], np.int32), bc_state)
+                np.array([BC_DIRICHLET, BC_OUTFLOW if outflow else BC_DIRICHLET], np.int32), bc_state)
     cfg = base_cfg(3, N, EQ_EULER_MIX, volume_flux=VF_DUCROS, shock=shock,
                    force_alpha=force_alpha, T_guess=T1)
     return Case("curved_shock_air5", cfg, mesh, u0, species=sp,

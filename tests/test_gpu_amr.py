@@ -6,7 +6,7 @@ import pytest
 from paper_2511_17551_amd import workloads as W
 from oracle.dgsem import Operator
 from oracle import ssprk
-from tests.helpers import rel_err, parity_err, flux_scale, to_dev, to_host
+from tests.helpers import rel_err, parity_err, flux_scale, to_dev, to_host, oracle_dt
 
 pytestmark = pytest.mark.gpu
 RHS_TOL = 1e-11
@@ -56,17 +56,19 @@ def test_small_amr_rhs_other_volume_forms(dgx, vf):
 
 
 def test_small_amr_ssprk3(dgx):
+    """100 SSPRK3 steps on the small 2:1 mesh (498 elements, mortars), dt
+    from the oracle's CFL rule (0.5)."""
     c = W.case_amr(base=4, radii=(0.4, 0.25), centre=(0.45, 0.5, 0.55))
     op = Operator(c.cfg, c.mesh)
+    dt = oracle_dt(op, c.u0, 0.5)
     s = dgx.Solver(c)
     u = to_dev(c.u0)
-    dt = dgx.dgx_max_dt(s.ctx, u, 0.5)
-    s.ssprk3(u, dt, 20)
+    s.ssprk3(u, dt, 100)
     s.check()
     got = to_host(u)
     s.close()
-    ref, _ = ssprk.run(lambda v, t: op.rhs(v, t), c.u0, 0.0, dt, 20)
-    print("small amr 20 steps rel err %.3e" % rel_err(got, ref))
+    ref, _ = ssprk.run(lambda v, t: op.rhs(v, t), c.u0, 0.0, dt, 100)
+    print("small amr 100 steps rel err %.3e" % rel_err(got, ref))
     assert rel_err(got, ref) < 1e-9
 
 

@@ -8,7 +8,7 @@ import pytest
 from paper_2511_17551_amd import workloads as W
 from oracle.dgsem import Operator
 from oracle.thermo import Mixture
-from tests.helpers import rel_err, parity_err, flux_scale, to_dev, to_host
+from tests.helpers import rel_err, parity_err, flux_scale, to_dev, to_host, oracle_dt
 
 pytestmark = pytest.mark.gpu
 RHS_TOL = 1e-11
@@ -53,15 +53,73 @@ def check_alpha(op, alpha):
     assert np.max(np.abs(alpha - ref)) < 1e-10, np.max(np.abs(alpha - ref))
 
 
-@pytest.mark.parametrize("n", [3, 4])
-def test_curved_shock_rhs_small(dgx, thermo_fns, n):
-    c = W.case_c3(*thermo_fns, n=n)
+@pytest.mark.parametrize("n,ind_var,smooth,outflow", [
+    (3, W.IND_RHO_P, False, False), (4, W.IND_RHO_P, False, False),
+    (4, W.IND_P, False, False), (4, W.IND_RHO_P, True, False), (4, W.IND_P, True, False),
+    (4, W.IND_RHO_P, False, True)])
+def test_curved_shock_rhs_small(dgx, thermo_fns, n, ind_var, smooth, outflow):
+    """The curved shock at 3^3 and 4^3 elements; the pressure indicator
+    (ind_var = p), the half-neighbour smoothing of alpha, and an outflow
+    boundary (external state = interior) at x = 1 on the GPU."""
+    c = W.case_c3(*thermo_fns, n=n, outflow=outflow)
+    c.cfg["ind_var"] = ind_var
+    c.cfg["alpha_smooth"] = smooth
     op, ref, got, alpha = run_case(dgx, c)
     check_alpha(op, alpha)
     assert (op.last["alpha"] > 0).any()
+    if smooth:
+        # smoothing raised some element's alpha above its own indicator value
+        c2 = W.case_c3(*thermo_fns, n=n, outflow=outflow)
+        c2.cfg["ind_var"] = ind_var
+        op2 = Operator(c2.cfg, c2.mesh, species=c2.species)
+        op2.rhs(c2.u0)
+        assert (op.last["alpha"] > op2.last["alpha"]).any()
     e = parity_err(got, ref, flux_scale(op, c.u0))
-    print("curved shock n=%d parity %.3e plain %.3e" % (n, e, rel_err(got, ref)))
+    print("curved shock n=%d ind_var=%d smooth=%d outflow=%d parity %.3e plain %.3e"
+          % (n, ind_var, smooth, outflow, e, rel_err(got, ref)))
     assert e < RHS_TOL
+
+
+@pytest.mark.parametrize("sf", [W.SF_RUSANOV, W.SF_HLL])
+def test_curved_shock_100_steps_with_limiter(dgx, thermo_fns, sf):
+    """100 SSPRK3 steps of the curved Mach-3 shock (4^3 elements, N = 4):
+    T(e) Newton, modal indicator, subcell FV blend and the positivity limiter
+    after every stage, dt from the oracle's CFL rule (0.5).  The blending
+    factor's alpha_min cut is discontinuous: the oracle records how close any
+    element comes to it over all 300 right-hand sides (relative to alpha_min)
+    and the test asserts none comes within 1e-6, so both sides take the same
+    branch everywhere."""
+    from oracle import ssprk
+    from oracle.positivity import limit
+    c = W.case_c3(*thermo_fns, n=4)
+    c.cfg["positivity"] = True
+    c.cfg["surface_flux"] = sf
+    op = Operator(c.cfg, c.mesh, species=c.species)
+    w = op.b.w
+    wq = np.einsum("i,j,k->kji", w, w, w).reshape(-1)
+    lim = lambda v: limit(v, op.J, wq, 3, c.species.e0)[0]
+    dt = oracle_dt(op, c.u0, 0.5)
+    amin = c.cfg["alpha_min"]
+    closest, shocked = [np.inf], []
+
+    def L(v, t):
+        du = op.rhs(v, t)
+        raw = op.last["alpha_raw"]
+        closest[0] = min(closest[0], float(np.min(np.abs(raw - amin) / amin)))
+        shocked.append(int((op.last["alpha"] > 0).sum()))
+        return du
+    ref, _ = ssprk.run(L, c.u0, 0.0, dt, 100, limiter=lim)
+    s = dgx.Solver(c)
+    u = to_dev(c.u0)
+    s.ssprk3(u, dt, 100)
+    s.check()
+    got = to_host(u)
+    s.close()
+    err = rel_err(got, ref)
+    print("curved shock sf=%d 100 steps (dt %.3e): rel err %.3e; shocked elements %d..%d; closest approach "
+          "to the alpha_min cut %.3e alpha_min" % (sf, dt, err, min(shocked), max(shocked), closest[0]))
+    assert closest[0] > ALPHA_CUT_MARGIN
+    assert err < 1e-9
 
 
 @pytest.mark.parametrize("alpha", [0.0, 0.5, 1.0])
@@ -92,7 +150,7 @@ def test_curved_shock_rhs_full(dgx, thermo_fns):
     assert e < RHS_TOL
 
 
-@pytest.mark.parametrize("guess", [0])
+@pytest.mark.parametrize("guess", [0, 1])
 def test_thermo_matches_oracle(dgx, thermo_fns, guess):
     c = W.case_c3(*thermo_fns, n=6)
     mix = Mixture(c.species)
@@ -116,6 +174,49 @@ def test_thermo_matches_oracle(dgx, thermo_fns, guess):
     err = np.max(np.abs(got - Tref) / Tref)
     print("thermo guess=%d rel err %.3e stats %s" % (guess, err, st))
     assert err < 1e-10
+
+
+def test_wild_guess_falls_back_to_the_freestream_solve(dgx, thermo_fns):
+    """A network whose guess is finite but absurd (1e20 K) with a Newton
+    budget of 6 iterations: the oracle shows that the solve from 1e20 K fails
+    within 6 iterations at thousands of nodes of this state, while the plain
+    solve from the freestream guess needs at most 5.  The guided solve must
+    redo those nodes from the freestream guess: every T matches the oracle to
+    1e-10 and the statistics count the fallbacks."""
+    c = W.case_c3(*thermo_fns, n=6)
+    c.cfg["newton_maxit"] = 6
+    mix = Mixture(c.species)
+    u0 = c.u0
+    rs = u0[:5].reshape(5, -1)
+    m = u0[5:8].reshape(3, -1)
+    rhoe = u0[8].reshape(-1) - 0.5 * (m * m).sum(0) / rs.sum(0)
+    Tref, it_ref = mix.solve_T(rs, rhoe, 300.0, maxit=6)
+    assert it_ref.max() <= 5
+    with np.errstate(all="ignore"):
+        Twild, _ = mix.solve_T(rs, rhoe, np.full(rhoe.shape, 1e20), maxit=6, strict=False)
+    expect_fail = int(np.isnan(Twild).sum())
+    assert expect_fail > 1000
+    s = dgx.Solver(c)
+    import torch
+    prm = np.zeros(dgx.SUR_PARAMS + dgx.SUR_NORM, np.float32)
+    prm[dgx.SUR_PARAMS + 6:dgx.SUR_PARAMS + 12] = 1.0   # feature std
+    prm[dgx.SUR_PARAMS + 12] = 1e20                     # T mean: the guess
+    prm[dgx.SUR_PARAMS + 13] = 1.0                      # T std
+    dgx.dgx_surrogate_set(s.ctx, prm)
+    u = to_dev(u0)
+    T = torch.empty(u0.shape[1:], dtype=torch.float64, device="cuda")
+    st = dgx.dgx_thermo(s.ctx, u, T, None, guess=dgx.GUESS_SURROGATE)
+    got = to_host(T).reshape(-1)
+    s.check()
+    s.close()
+    err = np.max(np.abs(got - Tref) / Tref)
+    print("wild guess: rel err %.3e, fallbacks %d (oracle: %d fail from 1e20 K), stats %s"
+          % (err, st["fallbacks"], expect_fail, st))
+    assert err < 1e-10
+    assert st["nonconverged"] == 0
+    # rounding may move a node across the 6-iteration edge; the count is of
+    # the oracle's order
+    assert 0.5 * expect_fail <= st["fallbacks"] <= min(2 * expect_fail, rhoe.size)
 
 
 @pytest.mark.parametrize("size", [(8, 16), (64, 128)])

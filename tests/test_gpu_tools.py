@@ -3,6 +3,9 @@
 * dgx_species_energy: the context's species energies and heat capacities
   against the oracle's rigid-rotor / harmonic-oscillator tables from 50 K to
   20000 K (host arithmetic on both sides, different code).
+* dgx_mixture_energy: rho e and rho cv of seeded mixture states against the
+  oracle's sums over species (Eq. Internal_energy), one temperature per
+  state, and its argument checks.
 * dgx_kernel_times: the kernels of one right-hand side, named in launch
   order (gradient pass before the fused right-hand side for Navier-Stokes;
   the indicator, with the temperature solve fused into it, before the
@@ -49,6 +52,32 @@ def test_species_energy_matches_oracle(dgx, thermo_fns):
     s.close()
     print("species tables: max rel err e %.2e, cv %.2e" % (worst_e, worst_cv))
     assert worst_e < 1e-13 and worst_cv < 1e-13
+
+
+def test_mixture_energy_matches_oracle(dgx, thermo_fns):
+    c = W.case_c4(*thermo_fns, nr=4, nth=8, hot=True)
+    mix = Mixture(c.species)
+    rs, T = W.far_chem_states(997, seed=13)
+    s = dgx.Solver(c)
+    rhoe, rhocv = dgx.dgx_mixture_energy(s.ctx, rs, T)
+    ref_e, ref_cv = mix.rho_e(rs, T), mix.rho_cv(rs, T)
+    scale = np.abs(rs * mix.e_species(T)).sum(0)
+    err_e = float(np.max(np.abs(rhoe - ref_e) / scale))
+    err_cv = float(np.max(np.abs(rhocv - ref_cv) / ref_cv))
+    print("mixture sums: max rel err rho e %.2e (of sum |rho_s e_s|), rho cv %.2e" % (err_e, err_cv))
+    assert err_e < 1e-13 and err_cv < 1e-13
+    # the binding's energy functions broadcast through the same entry point
+    energy, cv = dgx.mixture_energy_fns(s.ctx)
+    Tb = np.full((3, 4), 2500.0)
+    rsb = np.broadcast_to(rs[:, :1, None], (5, 3, 4))
+    assert np.allclose(energy(rsb, Tb), mix.rho_e(np.ascontiguousarray(rsb), Tb), rtol=1e-13)
+    assert np.allclose(cv(rs, 2500.0), mix.rho_cv(rs, np.full(rs.shape[1], 2500.0)), rtol=1e-13)
+    # a non-positive temperature is rejected, nothing written
+    bad = T.copy()
+    bad[5] = 0.0
+    with pytest.raises(dgx.DgxError):
+        dgx.dgx_mixture_energy(s.ctx, rs, bad)
+    s.close()
 
 
 def timed(dgx, c, expect):
