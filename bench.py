@@ -8,8 +8,9 @@ evaluations fused with the stage updates, replayed from a HIP graph), so
 
     GDOF-RHS/s = 3 * DOF * steps / seconds / 1e9.
 
-Prints one JSON line (see the keys below).  The oracle (NumPy, one thread)
-is timed on the same 32^3 state for the cpu_baseline entry.
+The headline is the median of 5 timed runs of --steps steps each.  Prints
+one JSON line (see the keys below).  The oracle (NumPy) is timed on the same
+32^3 state for the cpu_baseline entry, on one core and on all usable cores.
 """
 import argparse
 import hashlib
@@ -49,24 +50,81 @@ def grad_bytes_per_launch(nelem, nn, nvar, dim, n1):
     return nelem * nn * (nvar + dim + 1) * 8 + nelem * (2 * dim * (dim + 1) * nf * 8 + (dim * dim + 1) * 8 + 2 * dim * 4)
 
 
-def cpu_baseline(case, budget_s=20.0):
-    """Oracle right-hand sides on the same state, one thread, ~budget_s."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rhs_worker(n, reps, barrier, out):
+    """One process of the all-cores leg: builds the oracle for the n^3 TGV
+    state, waits for every process to be ready, then times `reps` right-hand
+    sides single-threaded and puts the seconds into `out`."""
     from threadpoolctl import threadpool_limits
+    from paper_2511_17551_amd import workloads as W
     from oracle.dgsem import Operator
+    case = W.case_c2(n=n)
+    with threadpool_limits(limits=1):
+        op = Operator(case.cfg, case.mesh)
+        barrier.wait()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            op.rhs(case.u0)
+        out.put(time.perf_counter() - t0)
+
+
+def cpu_baseline(n=32, budget_s=10.0, max_procs=16):
+    """The oracle (NumPy FP64) on the headline state, timed on this host's
+    cores before the GPU is touched: one process on one thread (right-hand
+    sides until ~budget_s), then one single-threaded process per usable core
+    (at most max_procs, the host share of one GPU), each evaluating one full
+    right-hand side of its own copy of the state, wall time of the slowest.
+    Returns the all-cores throughput as the value, the one-core figure beside
+    it, the core counts and the CPU model."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from paper_2511_17551_amd import workloads as W
+    from oracle.dgsem import Operator
+    case = W.case_c2(n=n)
+    dof = case.u0.size
     with threadpool_limits(limits=1):
         op = Operator(case.cfg, case.mesh)
         t0 = time.perf_counter()
-        n = 0
+        k = 0
         while True:
             op.rhs(case.u0)
-            n += 1
-            el = time.perf_counter() - t0
-            if el > budget_s or n >= 10:
+            k += 1
+            el1 = time.perf_counter() - t0
+            if el1 > budget_s or k >= 10:
                 break
-    dof = case.u0.size
-    return dict(value=dof * n / el / 1e9, unit="GDOF-RHS/s", cores=1, kind="oracle",
-                sample="%d full right-hand sides of the 32^3 N=3 TGV state (%.1f s, NumPy FP64, 1 thread)"
-                % (n, el))
+    del op
+    one = dof * k / el1 / 1e9
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    procs = max(1, min(usable, max_procs))
+    ctx = mp.get_context("fork")   # the GPU is not initialised yet: plain fork, no exec
+    barrier, q = ctx.Barrier(procs), ctx.Queue()
+    ps = [ctx.Process(target=_oracle_rhs_worker, args=(n, 1, barrier, q)) for _ in range(procs)]
+    for p in ps:
+        p.start()
+    secs = [q.get() for _ in ps]
+    for p in ps:
+        p.join()
+    elp = max(secs)   # all processes ran concurrently from the barrier on
+    allc = dof * procs / elp / 1e9
+    return dict(value=allc, unit="GDOF-RHS/s", cores=procs, kind="oracle",
+                one_core=dict(value=one, unit="GDOF-RHS/s", cores=1, rhs=k, seconds=round(el1, 2)),
+                nproc=os.cpu_count(), usable_cores=usable, cpu_model=_cpu_model(),
+                sample="the %d^3 N=3 Navier-Stokes TGV state (%d DOF), NumPy FP64: one thread, "
+                       "%d right-hand sides in %.1f s; then %d single-threaded processes started together, "
+                       "one right-hand side each, the slowest %.1f s" % (n, dof, k, el1, procs, elp))
 
 
 def _events(torch):
@@ -450,6 +508,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs of --steps steps each; the median is reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the mixture legs (curved N=4 shock, reacting cylinder)")
     ap.add_argument("--no-thermo", action="store_true", help="skip the surrogate vs plain T(e) leg")
@@ -468,6 +528,9 @@ def main():
         print("bench.py measures one GPU only: the library runs on a single MI355X; how the "
               "path would shard across GPUs is described, not implemented", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle on the host cores first, while no process has touched the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
 
     import torch
     from paper_2511_17551_amd import workloads as W
@@ -501,17 +564,24 @@ def main():
     solver.ssprk3(u, dt, max(args.warmup, 1))
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t0.record(stream)
-    solver.ssprk3(u, dt, args.steps)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
+    # `repeats` timed runs of exactly `steps` steps each (200 steps take
+    # ~0.11 s), each bracketed by device synchronisation; the median run is
+    # the headline
+    reps_ms, walls = [], []
+    for _ in range(max(1, args.repeats)):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        t0.record(stream)
+        solver.ssprk3(u, dt, args.steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - wall0)
+        reps_ms.append(t0.elapsed_time(t1))
     solver.check()
-    ms = t0.elapsed_time(t1)
+    ms = float(np.median(reps_ms))
+    wall = float(np.median(walls))
     ms_per_step = ms / args.steps
     value = 3.0 * dof / (ms_per_step * 1e-3) / 1e9
 
@@ -533,6 +603,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "tgv3d_ns_32cube_N3_ssprk3", "elements": nelem, "N": 3, "nodes": nelem * nn,
                    "dof": dof, "rhs_per_step": 3, "dt": dt, "wall_s": round(wall, 4),
+                   "repeats": len(reps_ms), "repeat_ms_per_step": [round(r / args.steps, 5) for r in reps_ms],
                    "elements_per_workgroup": epb, "workgroup_order": ORDER_NAMES[order], "autotune_ms": {str(k): round(v, 5) for k, v in tune_ms.items()}},
         "roofline": roof,
     }
@@ -546,8 +617,8 @@ def main():
         out["c4"] = c4_leg(torch, W, dgx)
     if not args.no_fluxes:
         out["fluxes"] = flux_leg(torch, W, dgx)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 
