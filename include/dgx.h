@@ -378,6 +378,23 @@ int dgx_set_launch(dgx_ctx *ctx, int epb, int order);
  * either pointer may be NULL.  DGX_E_STATE without a mesh. */
 int dgx_get_launch(dgx_ctx *ctx, int *epb, int *order);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture when called without stats, tight serving loops, harnesses that
+ * forbid hipMalloc): dgx_thermo with the same arguments, results and errors,
+ * whose scratch (the surrogate's guesses, the per-node iteration counts and
+ * the statistics accumulators) lives in a static device buffer of the library
+ * instead of memory allocated on first use.  The call allocates nothing (no
+ * hipMalloc or hipFree, no host allocation): the caller passes u, T and p.
+ * Limit: at most DGX_NOALLOC_MAX_STATES states (the mesh's nodes when
+ * nstates <= 0); more is DGX_E_INVAL before any launch.  The buffer (about
+ * 12.6 MB) is set up on a GPU at the first call there and held until the
+ * process ends; all calls on one GPU share it, so calls that overlap on one
+ * GPU (other streams, other threads, other contexts) race and must be
+ * ordered by the caller.  With stats it synchronises, as dgx_thermo does. */
+#define DGX_NOALLOC_MAX_STATES 1048576
+int dgx_thermo_noalloc(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double *p,
+                       int guess_mode, dgx_newton_stats *stats, void *stream);
+
 /* Text of the last error on this context (never NULL). */
 const char *dgx_last_error(const dgx_ctx *ctx);
 

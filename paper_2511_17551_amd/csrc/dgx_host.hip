@@ -136,6 +136,7 @@ struct dgx_ctx {
     MixC mix{};
     KinC kin{};
     std::string err;
+    const char *err_fixed = nullptr;  // static text of the last error (no allocation), else err
     // mesh
     int nelem = 0;
     bool curved = false;
@@ -167,7 +168,16 @@ struct dgx_ctx {
 namespace {
 
 int set_err(dgx_ctx *ctx, int code, const std::string &msg) {
-    if (ctx) ctx->err = msg;
+    if (ctx) {
+        ctx->err = msg;
+        ctx->err_fixed = nullptr;
+    }
+    return code;
+}
+
+// An error whose text is a string literal: records it without allocating.
+int set_err_fixed(dgx_ctx *ctx, int code, const char *msg) {
+    if (ctx) ctx->err_fixed = msg;
     return code;
 }
 
@@ -1182,9 +1192,155 @@ int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *
     return DGX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// dgx_thermo_noalloc: dgx_thermo for callers that cannot allocate device
+// memory.  Its scratch (the surrogate's guesses, the per-node iteration
+// counts, the statistics accumulators) lives in one static device array of
+// the library instead of buffers allocated on first use.  Each GPU holds its
+// own copy of the array, at its own address, until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns on
+// that device (the array's name is a host-side stand-in).  Every call on a
+// GPU shares that GPU's copy: calls that overlap on one GPU race.
+namespace {
+
+constexpr int64_t kNoallocMaxStates = DGX_NOALLOC_MAX_STATES;
+// guesses (double) + iteration counts (int, two per double) + accumulators
+constexpr size_t kNoallocAcc = 8;
+constexpr size_t kNoallocDoubles = (size_t)kNoallocMaxStates + (size_t)kNoallocMaxStates / 2 + kNoallocAcc;
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+double *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_rc[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (set up once per device, with that
+// device current), or nullptr.
+double *noalloc_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::call_once(g_scratch_once[dev], [dev] {
+        void *ptr = nullptr;
+        g_scratch_rc[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = g_scratch_rc[dev] == hipSuccess ? static_cast<double *>(ptr) : nullptr;
+    });
+    return g_scratch_ptr[dev];
+}
+
+// accumulator slots (unsigned 64-bit): 0 sum of iterations, 1 non-converged,
+// 2 fallbacks, 3 sum over waves of the per-wave maximum, 4 maximum, 5 first
+// non-converged index (ULLONG_MAX: none)
+__global__ void k_noalloc_clear(unsigned long long *acc) {
+    if (threadIdx.x < kNoallocAcc) acc[threadIdx.x] = threadIdx.x == 5 ? ~0ull : 0ull;
+}
+
+// Statistics of the per-node iteration counts, the same rules as the host
+// reduction of dgx_thermo: a non-converged node (-1) counts maxit
+// iterations, the fallback bit is counted and removed, waves are the chunks
+// of 64 consecutive nodes.
+__global__ void __launch_bounds__(256) k_noalloc_stats(const int *__restrict__ iters, int64_t count, int maxit,
+                                                       unsigned long long *acc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int it = 0, bad = 0, fb = 0;
+    if (i < count) {
+        it = iters[i];
+        if (it >= 0 && (it & kItersFallback)) {
+            fb = 1;
+            it &= ~kItersFallback;
+        }
+        if (it < 0) {
+            bad = 1;
+            it = maxit;
+        }
+    }
+    // wave (64 lanes = 64 consecutive nodes) reductions
+    int wmax = it, wsum = it, wbad = bad, wfb = fb;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        wmax = max(wmax, __shfl_xor(wmax, off));
+        wsum += __shfl_xor(wsum, off);
+        wbad += __shfl_xor(wbad, off);
+        wfb += __shfl_xor(wfb, off);
+    }
+    if (bad) atomicMin(&acc[5], (unsigned long long)i);
+    const int64_t w0 = i - (threadIdx.x & 63);
+    if ((threadIdx.x & 63) == 0 && w0 < count) {
+        atomicAdd(&acc[0], (unsigned long long)wsum);
+        atomicAdd(&acc[1], (unsigned long long)wbad);
+        atomicAdd(&acc[2], (unsigned long long)wfb);
+        atomicAdd(&acc[3], (unsigned long long)wmax);
+        atomicMax(&acc[4], (unsigned long long)wmax);
+    }
+}
+
+}  // namespace
+
+int dgx_thermo_noalloc(dgx_ctx *ctx, const double *u, int64_t nstates, double *T, double *p, int guess_mode,
+                       dgx_newton_stats *stats, void *stream) {
+    if (!ctx) return DGX_E_INVAL;
+    if (!is_mix(ctx)) return set_err_fixed(ctx, DGX_E_INVAL, "thermo needs a mixture context");
+    if (!u || !T) return set_err_fixed(ctx, DGX_E_INVAL, "null pointer");
+    if (guess_mode != DGX_GUESS_FREESTREAM && guess_mode != DGX_GUESS_SURROGATE)
+        return set_err_fixed(ctx, DGX_E_INVAL, "bad guess mode");
+    int64_t count = nstates;
+    if (count <= 0) {
+        if (!ctx->mesh_ok) return set_err_fixed(ctx, DGX_E_STATE, "no mesh and no state count");
+        count = (int64_t)ctx->nelem * ctx->nn;
+    }
+    if (count > kNoallocMaxStates)
+        return set_err_fixed(ctx, DGX_E_INVAL,
+                             "dgx_thermo_noalloc: more states than DGX_NOALLOC_MAX_STATES (1048576)");
+    if (guess_mode == DGX_GUESS_SURROGATE && !ctx->sur.ready)
+        return set_err_fixed(ctx, DGX_E_STATE, "surrogate has no weights");
+    double *base = noalloc_scratch();
+    if (!base) return set_err_fixed(ctx, DGX_E_DEVICE, "no address for the static scratch on this device");
+    double *tg_s = base;
+    int *iters_s = reinterpret_cast<int *>(base + kNoallocMaxStates);
+    auto *acc = reinterpret_cast<unsigned long long *>(base + kNoallocMaxStates + kNoallocMaxStates / 2);
+    hipStream_t s = (hipStream_t)stream;
+    const double *tg = nullptr;
+    if (guess_mode == DGX_GUESS_SURROGATE) {
+        if (surrogate_predict(ctx->sur, ctx->cfg.dim, u, count, tg_s, s))
+            return set_err_fixed(ctx, DGX_E_DEVICE, "surrogate launch failed");
+        tg = tg_s;
+    }
+    int *iters = stats ? iters_s : nullptr;
+    const int tb = 256;
+    const int blocks = (int)((count + tb - 1) / tb);
+    if (ctx->cfg.dim == 2)
+        hipLaunchKernelGGL(k_thermo<2>, dim3(blocks), dim3(tb), 0, s, u, count, tg, ctx->cfg.T_guess,
+                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, (double *)nullptr, iters,
+                           ctx->flags.p, 0);
+    else
+        hipLaunchKernelGGL(k_thermo<3>, dim3(blocks), dim3(tb), 0, s, u, count, tg, ctx->cfg.T_guess,
+                           ctx->cfg.newton_tol, ctx->cfg.newton_maxit, ctx->mix, T, p, (double *)nullptr, iters,
+                           ctx->flags.p, 0);
+    if (hipGetLastError() != hipSuccess) return set_err_fixed(ctx, DGX_E_DEVICE, "thermo launch failed");
+    if (!stats) return DGX_OK;
+    hipLaunchKernelGGL(k_noalloc_clear, dim3(1), dim3(64), 0, s, acc);
+    hipLaunchKernelGGL(k_noalloc_stats, dim3(blocks), dim3(tb), 0, s, iters_s, count, ctx->cfg.newton_maxit, acc);
+    if (hipGetLastError() != hipSuccess) return set_err_fixed(ctx, DGX_E_DEVICE, "statistics launch failed");
+    unsigned long long h[kNoallocAcc];
+    if (hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_err_fixed(ctx, DGX_E_DEVICE, "statistics copy failed");
+    const int64_t nw = (count + 63) / 64;
+    stats->nodes = count;
+    stats->iters_total = (int64_t)h[0];
+    stats->iters_max = (int32_t)h[4];
+    stats->iters_wave_max_mean = nw ? (double)h[3] / (double)nw : 0.0;
+    stats->nonconverged = (int64_t)h[1];
+    stats->first_bad = h[5] == ~0ull ? -1 : (int64_t)h[5];
+    stats->substeps_total = 0;
+    stats->substeps_max = 0;
+    stats->fallbacks = (int64_t)h[2];
+    if (h[1]) return set_err_fixed(ctx, DGX_E_NOCONV, "nodes did not converge");
+    return DGX_OK;
+}
+
 const char *dgx_last_error(const dgx_ctx *ctx) {
     if (!ctx) return "null context";
-    return ctx->err.c_str();
+    return ctx->err_fixed ? ctx->err_fixed : ctx->err.c_str();
 }
 
 void dgx_destroy(dgx_ctx *ctx) {

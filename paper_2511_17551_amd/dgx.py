@@ -81,6 +81,7 @@ def _load():
         "dgx_limit_positivity": ([vp, vp, vp], C.c_int),
         "dgx_max_dt": ([vp, vp, C.c_double, C.POINTER(C.c_double), vp], C.c_int),
         "dgx_thermo": ([vp, vp, C.c_int64, vp, vp, C.c_int, C.POINTER(dgx_newton_stats), vp], C.c_int),
+        "dgx_thermo_noalloc": ([vp, vp, C.c_int64, vp, vp, C.c_int, C.POINTER(dgx_newton_stats), vp], C.c_int),
         "dgx_chem_step": ([vp, vp, C.c_double, C.c_double, C.c_int, C.POINTER(dgx_newton_stats), vp], C.c_int),
         "dgx_last_alpha": ([vp], vp),
         "dgx_surrogate_set": ([vp, C.POINTER(C.c_float), C.c_size_t], C.c_int),
@@ -111,7 +112,7 @@ def _load():
 
 lib = _load()
 EXPORTED = ("dgx_create", "dgx_set_mesh", "dgx_rhs", "dgx_ssprk3_step", "dgx_limit_positivity", "dgx_max_dt", "dgx_thermo",
-
+            "dgx_thermo_noalloc",
             "dgx_chem_step",
             "dgx_last_alpha", "dgx_surrogate_set", "dgx_surrogate_get", "dgx_surrogate_train",
             "dgx_surrogate_predict", "dgx_surrogate_init", "dgx_surrogate_grad", "dgx_check", "dgx_species_energy", "dgx_mixture_energy", "dgx_kernel_times", "dgx_autotune",
@@ -243,6 +244,26 @@ def dgx_thermo(ctx, u, T, p=None, guess=GUESS_FREESTREAM, nstates=0, stream=None
         return None
     st = dgx_newton_stats()
     rc = lib.dgx_thermo(ctx, _dev(u), int(nstates), _dev(T), _dev(p), int(guess), C.byref(st), _stream(stream))
+    if check:
+        _raise(ctx, rc)
+    return dict(nodes=st.nodes, iters_total=st.iters_total, iters_max=st.iters_max,
+                iters_wave_max_mean=st.iters_wave_max_mean, nonconverged=st.nonconverged,
+                first_bad=st.first_bad, fallbacks=st.fallbacks, rc=rc)
+
+
+NOALLOC_MAX_STATES = 1048576
+
+
+def dgx_thermo_noalloc(ctx, u, T, p=None, guess=GUESS_FREESTREAM, nstates=0, stream=None, check=True, stats=True):
+    """dgx_thermo with its scratch in the library's static device buffer (no
+    allocation; at most NOALLOC_MAX_STATES states)."""
+    if not stats:
+        _raise(ctx, lib.dgx_thermo_noalloc(ctx, _dev(u), int(nstates), _dev(T), _dev(p), int(guess), None,
+                                           _stream(stream)))
+        return None
+    st = dgx_newton_stats()
+    rc = lib.dgx_thermo_noalloc(ctx, _dev(u), int(nstates), _dev(T), _dev(p), int(guess), C.byref(st),
+                                _stream(stream))
     if check:
         _raise(ctx, rc)
     return dict(nodes=st.nodes, iters_total=st.iters_total, iters_max=st.iters_max,
