@@ -144,6 +144,7 @@ struct dgx_ctx {
     int nbc = 0;
     DevBuf<double> geo, Jn, nsub, bc_state, bc_T, T, csnd, alpha, alpha_tmp, alpha_raw, grad, vpart, u1, u2, dtbuf;
     DevBuf<int> nbr, bc_kind, mort, iters, subs;
+    DevBuf<double> mops;
     DevBuf<double> tg;
     DevBuf<double> mflux;
     int nmortar = 0;
@@ -258,8 +259,7 @@ RhsParams base_params(dgx_ctx *ctx) {
     P.kin = ctx->kin_d.p;
     P.mort = ctx->mort.p;
     P.mflux = ctx->mflux.p;
-    std::memcpy(P.Im, ctx->Im, sizeof(P.Im));
-    std::memcpy(P.Pm, ctx->Pm, sizeof(P.Pm));
+    P.mops = ctx->mops.p;
     P.gamma = ctx->cfg.gamma;
     P.R = ctx->cfg.R;
     P.mu = ctx->cfg.mu;
@@ -691,6 +691,11 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
     if (m->nmortar) {
         if ((rc = dalloc(ctx, ctx->mort, (size_t)m->nmortar * (3 + nsub)))) return rc;
         HIPCHK(hipMemcpy(ctx->mort.p, m->mortars, (size_t)m->nmortar * (3 + nsub) * sizeof(int), hipMemcpyHostToDevice));
+        double ops[100];
+        std::memcpy(ops, ctx->Im, sizeof(ctx->Im));
+        std::memcpy(ops + 50, ctx->Pm, sizeof(ctx->Pm));
+        if ((rc = dalloc(ctx, ctx->mops, 100))) return rc;
+        HIPCHK(hipMemcpy(ctx->mops.p, ops, sizeof(ops), hipMemcpyHostToDevice));
         if ((rc = dalloc(ctx, ctx->mflux, (size_t)m->nmortar * nsub * nv * ctx->nf))) return rc;
     }
     // boundary states
@@ -1353,6 +1358,7 @@ void dgx_destroy(dgx_ctx *ctx) {
                               &ctx->dtbuf, &ctx->vpart};
     for (auto *b : bufs) b->release();
     ctx->nbr.release();
+    ctx->mops.release();
     ctx->bc_kind.release();
     ctx->mort.release();
     ctx->mflux.release();

@@ -70,8 +70,8 @@ struct RhsParams {
     const KinC *kin;        // reacting mixture
     const int *mort;        // mortar table [nm][3 + 2^(dim-1)] (eL, fL, eS.., fS)
     const double *mflux;    // mortar sub-face fluxes [nm][2^(dim-1)][nvar][nf]
-    double Im[2][25];       // interpolation to the lower / upper half of a face edge
-    double Pm[2][25];       // L2 projection back from the halves
+    const double *mops;     // mortars: [I, P][lower, upper half][25]: interpolation to the
+                            // halves of a face edge and L2 projection back ([q][j], N+1 wide)
     double gamma, R, mu, kappa;
     int epb;                // elements per block
     int xcd;                // nonzero: XCD-contiguous workgroup numbering (k_rhs, k_grad)

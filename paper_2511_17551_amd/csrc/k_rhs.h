@@ -213,10 +213,19 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
     // indices, so they live in LDS rather than in the kernel arguments
     __shared__ double sDc[N1 * N1];
     __shared__ double sW[N1];
+    // non-conforming variants: the L2 projection from the face halves, read
+    // with per-lane indices
+    __shared__ double sPm[MORT ? 2 * N1 * N1 : 1];
 
     const int tid = threadIdx.x;
     if (tid < N1 * N1) sDc[tid] = 2.0 * P.B.D[tid];
     if (tid < N1) sW[tid] = P.B.w[tid];
+    if constexpr (MORT) {
+        if (tid < 2 * N1 * N1) {
+            const int h = tid / (N1 * N1);
+            sPm[tid] = P.mops[50 + h * 25 + (tid - h * N1 * N1)];
+        }
+    }
     const int NT = P.epb * NN;  // threads that own a node
     const int e0 = (P.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x) * P.epb;
     const int nloc = min(P.epb, P.nelem - e0);
@@ -424,11 +433,11 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
 #pragma unroll 1
                         for (int sb = 0; sb < NSUB; ++sb) {
                             const int a = sb & 1, bsel = sb >> 1;
-#pragma unroll 1
+#pragma unroll 4
                             for (int qq = 0; qq < NF; ++qq) {
                                 const int ja = qq % N1, jb2 = qq / N1;
-                                double w = P.Pm[a][qa * N1 + ja];
-                                if (DIM == 3) w *= P.Pm[bsel][qb * N1 + jb2];
+                                double w = sPm[a * N1 * N1 + qa * N1 + ja];
+                                if (DIM == 3) w *= sPm[bsel * N1 * N1 + qb * N1 + jb2];
 #pragma unroll
                                 for (int v = 0; v < NV; ++v) F[v] = fma(w, mf[(sb * NV + v) * NF + qq], F[v]);
                             }
@@ -780,8 +789,8 @@ __global__ void __launch_bounds__(128) k_mortar(RhsParams P, int nmort) {
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         const int ja = j % N1, jb = j / N1;
-        double w = P.Im[a][qa * N1 + ja];
-        if (DIM == 3) w *= P.Im[bsel][qb * N1 + jb];
+        double w = P.mops[a * 25 + qa * N1 + ja];
+        if (DIM == 3) w *= P.mops[bsel * 25 + qb * N1 + jb];
         const size_t gj = (size_t)eL * NN + line_node<N1, DIM>(d, sideL ? N : 0, j);
 #pragma unroll
         for (int v = 0; v < NV; ++v) ui[v] = fma(w, P.u[v * stride + gj], ui[v]);

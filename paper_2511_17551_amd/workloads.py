@@ -529,7 +529,15 @@ def _periodic_dist(a, b):
     return np.minimum(d, 1.0 - d)
 
 
-def octree_mesh(N, base=16, radii=(0.51, 0.35), centre=(0.5, 0.5, 0.5)):
+def _morton3(i, j, k, bits):
+    """Interleave the bits of i, j, k (i lowest): the Z-order index."""
+    code = 0
+    for b in range(bits):
+        code |= ((i >> b) & 1) << (3 * b) | ((j >> b) & 1) << (3 * b + 1) | ((k >> b) & 1) << (3 * b + 2)
+    return code
+
+
+def octree_mesh(N, base=16, radii=(0.51, 0.35), centre=(0.5, 0.5, 0.5), element_order="morton"):
     """Periodic unit cube, base^3 level-0 hexes, refined 2:1 inside spheres.
 
     A leaf of level L is split into 8 children while L < len(radii) and its
@@ -537,7 +545,10 @@ def octree_mesh(N, base=16, radii=(0.51, 0.35), centre=(0.5, 0.5, 0.5)):
     face balance is enforced.  Returns nodal coordinates, conforming faces
     (+d of eL to -d of eR), mortars (large face, 4 small elements ordered
     s = a + 2b over the two tangential directions in increasing order, small
-    face) and the level of every element.
+    face) and the level of every element.  ``element_order`` "morton" numbers
+    the leaves along the Z-order curve of their corners at the finest level
+    (elements that are close in space, across levels too, are close in
+    memory); "level" numbers them level by level, lexicographically.
     """
     centre = np.asarray(centre, float)
     leaves = set()
@@ -610,7 +621,13 @@ def octree_mesh(N, base=16, radii=(0.51, 0.35), centre=(0.5, 0.5, 0.5)):
                         break
                 if c not in leaves:
                     break
-    order = sorted(leaves)
+    if element_order == "morton":
+        Lmax = max(c[0] for c in leaves)
+        bits = int(base * 2 ** Lmax - 1).bit_length()
+        order = sorted(leaves, key=lambda c: _morton3(c[1] << (Lmax - c[0]), c[2] << (Lmax - c[0]),
+                                                      c[3] << (Lmax - c[0]), bits))
+    else:
+        order = sorted(leaves)
     eid = {c: e for e, c in enumerate(order)}
     xi = _mesh_nodes(N)
     n1 = N + 1
@@ -664,12 +681,12 @@ def density_wave(x):
     return rho, (np.ones_like(rho), 0.5 * np.ones_like(rho), 0.25 * np.ones_like(rho)), np.ones_like(rho)
 
 
-def case_amr(N=3, base=16, radii=(0.51, 0.35), seed=5, centre=None):
+def case_amr(N=3, base=16, radii=(0.51, 0.35), seed=5, centre=None, element_order="morton"):
     """3D Euler density wave on the 2-level non-conforming octree mesh."""
     if centre is None:
         rng = np.random.default_rng(seed)
         centre = rng.uniform(0.35, 0.65, 3)
-    x, faces, mortars, level = octree_mesh(N, base, radii, centre)
+    x, faces, mortars, level = octree_mesh(N, base, radii, centre, element_order)
     cfg = base_cfg(3, N, EQ_EULER)
     rho, v, p = density_wave(x)
     u0 = _pg_conserved(rho, v, p, cfg["gamma"])
@@ -713,11 +730,12 @@ def batch_sizes(seed=55, ncases=16, lo=8, hi=24):
     return [int(v) for v in np.random.default_rng(seed).integers(lo, hi + 1, ncases)]
 
 
-def case_c5(N=3, base=16, radii=(0.51, 0.35), seed=5, batch_seed=55, ncases=16, sizes=None):
+def case_c5(N=3, base=16, radii=(0.51, 0.35), seed=5, batch_seed=55, ncases=16, sizes=None,
+            element_order="morton"):
     """The AMR density wave plus a batch of independent vortex-tube cases in
     one mesh (element ranges in ``mesh.case_offsets``: case 0 is the AMR
     domain)."""
-    amr = case_amr(N, base, radii, seed)
+    amr = case_amr(N, base, radii, seed, element_order=element_order)
     parts = [(amr.mesh.x, amr.mesh.faces, amr.mesh.mortars, amr.u0)]
     sizes = batch_sizes(batch_seed, ncases) if sizes is None else sizes
     for n in sizes:
