@@ -144,7 +144,8 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-ORDER_NAMES = {0: "round_robin", 1: "xcd_contiguous"}
+ORDER_NAMES = {0: "round_robin", 1: "xcd_contiguous", 2: "work_list",
+               4: "round_robin+alt_tiling", 5: "xcd_contiguous+alt_tiling", 6: "work_list+alt_tiling"}
 
 
 def recorded_traffic(workload, order):
@@ -457,6 +458,7 @@ def batch_leg(torch, W, dgx, reps=10):
     u = torch.from_numpy(c.u0).to("cuda")
     dt = dgx.dgx_max_dt(s.ctx, u, 0.3)
     epb, _ = dgx.dgx_autotune(s.ctx, u, reps=5)
+    _, form = dgx.dgx_get_launch(s.ctx)
     s.ssprk3(u, dt, 2)
     e0, e1 = _events(torch)
     torch.cuda.synchronize()
@@ -500,7 +502,7 @@ def batch_leg(torch, W, dgx, reps=10):
                 batched_ms_per_step=round(ms_batched, 4), separate_ms_per_step=round(ms_sep, 4),
                 batched_GDOF_RHS_s=round(3 * dof / (ms_batched * 1e-3) / 1e9, 3),
                 separate_GDOF_RHS_s=round(3 * dof / (ms_sep * 1e-3) / 1e9, 3),
-                elements_per_workgroup=epb)
+                elements_per_workgroup=epb, launch_form=ORDER_NAMES[form])
 
 
 def main():
@@ -518,9 +520,10 @@ def main():
                     help="skip the leg that times each built volume / surface flux on the TGV (Euler)")
     ap.add_argument("--epb", type=int, default=0,
                     help="elements per workgroup to use instead of autotuning (profiling runs)")
-    ap.add_argument("--order", type=int, default=-1, choices=(-1, 0, 1),
-                    help="workgroup numbering of the headline and curved-shock legs instead of the "
-                         "autotuner's (0 round-robin over the XCDs, 1 XCD-contiguous; profiling runs)")
+    ap.add_argument("--order", type=int, default=-1, choices=(-1, 0, 1, 2, 4, 5, 6),
+                    help="launch form of the headline and curved-shock legs instead of the autotuner's "
+                         "(0 round-robin over the XCDs, 1 XCD-contiguous, 2 work-list queue; +4 the "
+                         "alternative LDS tiling; profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write kernel (counter calibration)")
     args = ap.parse_args()

@@ -351,30 +351,41 @@ int dgx_kernel_times(dgx_ctx *ctx, const double *u, int reps, double *ms_out, in
                      char *names_out, size_t names_len, void *stream);
 
 /* Autotuner: for each elements-per-workgroup candidate in {1, 2, 4, 8}
- * that fits (<= 512 threads, <= 64 KB LDS) and each workgroup numbering
- * (round-robin over the 8 XCDs, or XCD-contiguous element ranges), time
+ * that fits (<= 512 threads, <= 64 KB LDS), each launch form
+ * (round-robin over the 8 XCDs, XCD-contiguous element ranges, or the
+ * work-list form of dgx_set_launch) and each LDS tiling built, time
  * `reps` SSPRK3 steps as dgx_ssprk3_step runs them (three fused stages, u0
  * in its own buffer, the positivity limiter when configured; into library
  * scratch with dt = 0, so u is read, not modified) with HIP events on
- * `stream`, and keep the fastest pair; the default numbering (XCD-contiguous
- * while the state takes at most 128 MB, else round-robin) is kept unless
- * the other one is more than 2% faster, since the two can differ little
- * in time on one run and much in HBM traffic.  The winner is cached process-wide under the key
- * (dim, N, equation, fluxes, geometry kind, element count) and reused by
- * later dgx_set_mesh calls with the same key.  *epb_out (may be NULL)
- * receives the elements-per-workgroup choice, ms_out (may be NULL, [4]) each
- * candidate's best average milliseconds per right-hand side over the two
- * numberings (-1 = not run).  Synchronises. */
+ * `stream`, and keep the fastest; the default (numbering XCD-contiguous
+ * while the state takes at most 128 MB, else round-robin; default tiling) is
+ * kept unless another is more than 2% faster, since the numberings can differ
+ * little in time on one run and much in HBM traffic.  The winner is cached
+ * process-wide under the key (dim, N, equation, fluxes, geometry kind,
+ * element count) and reused by later dgx_set_mesh calls with the same key.
+ * *epb_out (may be NULL) receives the elements-per-workgroup choice, ms_out
+ * (may be NULL, [4]) each candidate's best average milliseconds per
+ * right-hand side over the launch forms and tilings (-1 = not run).
+ * Synchronises. */
 int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *ms_out, void *stream);
 
 /* Force the launch shape: elements per workgroup (1, 2, 4 or 8; must fit as
  * above) and the workgroup numbering (order: 0 round-robin over the XCDs,
- * 1 XCD-contiguous element ranges, -1 keep the current one).  The results do
- * not depend on either (bitwise). */
+ * 1 XCD-contiguous element ranges, 2 the work-list form: one launch over a
+ * queue whose items are the 2:1 faces' sub-face fluxes, then the element
+ * chunks, each workgroup claiming the next item from an atomic counter, the
+ * chunks that read sub-face fluxes queued last and waiting until every such
+ * item is done; -1 keep the current one), plus 4 for the alternative LDS
+ * tiling where one is built (the pair and face work items in another number
+ * of chunks: the 3D Navier-Stokes kernel at N = 3 in two, the curved
+ * 5-species kernels at N = 4 in one; DGX_E_INVAL elsewhere).  The results do
+ * not depend on the elements per workgroup or the launch form (bitwise); the
+ * other tiling sums each node's pair fluxes in another order (rounding). */
 int dgx_set_launch(dgx_ctx *ctx, int epb, int order);
 
 /* The current launch shape, as dgx_set_launch takes it: *epb (elements per
- * workgroup) and *order (0 round-robin over the XCDs, 1 XCD-contiguous);
+ * workgroup) and *order (0 round-robin over the XCDs, 1 XCD-contiguous, 2 the
+ * work-list form; plus 4 with the alternative LDS tiling);
  * either pointer may be NULL.  DGX_E_STATE without a mesh. */
 int dgx_get_launch(dgx_ctx *ctx, int *epb, int *order);
 

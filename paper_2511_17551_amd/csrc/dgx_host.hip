@@ -33,15 +33,22 @@ namespace {
 
 // ------------------------------------------------------------------ dispatch
 using RhsLaunch = void (*)(const RhsParams &, int, int, int, size_t, hipStream_t);
+using RhsLaunchP = void (*)(const RhsParams &, int, int, size_t, hipStream_t, const WorkQ &);
 using GradLaunch = void (*)(const RhsParams &, int, int, size_t, hipStream_t);
 // indicator launch: ..., and for mixtures the fused T(e) solve's outputs
 // (T, frozen sound speed; null: T was solved before) and its T0, tol, maxit
 using IndLaunch = void (*)(const RhsParams &, int, double, double, double *, double *, int, int, size_t,
                            hipStream_t, double *, double *, double, double, int);
 
-template <int DIM, int N, int EQ, int VF, int SF, bool CURV, bool MORT>
+template <int DIM, int N, int EQ, int VF, int SF, bool CURV, bool MORT, int CHF>
 void rhs_launch(const RhsParams &P, int mode, int blocks, int threads, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_rhs<DIM, N, EQ, VF, SF, CURV, MORT>), dim3(blocks), dim3(threads), lds, s, P, mode);
+    hipLaunchKernelGGL((k_rhs<DIM, N, EQ, VF, SF, CURV, MORT, CHF>), dim3(blocks), dim3(threads), lds, s, P, mode);
+}
+// The work-list form: one workgroup per queue item.
+template <int DIM, int N, int EQ, int VF, int SF, bool CURV, bool MORT, int CHF>
+void rhs_launch_p(const RhsParams &P, int mode, int threads, size_t lds, hipStream_t s, const WorkQ &Q) {
+    hipLaunchKernelGGL((k_rhs_queue<DIM, N, EQ, VF, SF, CURV, MORT, CHF>), dim3(Q.nmort + Q.nchunks), dim3(threads),
+                       lds, s, P, mode, Q);
 }
 template <int DIM, int N>
 void grad_launch(const RhsParams &P, int blocks, int threads, hipStream_t s, double suthS, double suthT0) {
@@ -60,12 +67,22 @@ struct RhsEntry {
     RhsLaunch fn;
     int slot;  // doubles of LDS per element
     int mort;  // built with non-conforming (mortar) faces
+    RhsLaunchP fnp;  // work-list form
+    int alt;   // 1: the alternative LDS tiling (other work-item chunk count)
 };
 
-#define RHS_ENTRY(D, N, EQ, VF, SF, CV) \
-    {D, N, EQ, VF, SF, CV, &rhs_launch<D, N, EQ, VF, SF, (bool)CV, false>, RhsShape<D, N, EQ, VF, (bool)CV>::SLOT, 0}
-#define RHS_ENTRY_M(D, N, EQ, VF, SF) \
-    {D, N, EQ, VF, SF, 0, &rhs_launch<D, N, EQ, VF, SF, false, true>, RhsShape<D, N, EQ, VF, false>::SLOT, 1}
+#define RHS_ENTRY(D, N, EQ, VF, SF, CV)                                                                             \
+    {D, N, EQ, VF, SF, CV, &rhs_launch<D, N, EQ, VF, SF, (bool)CV, false, 0>, RhsShape<D, N, EQ, VF, (bool)CV>::SLOT, \
+     0, &rhs_launch_p<D, N, EQ, VF, SF, (bool)CV, false, 0>, 0}
+#define RHS_ENTRY_M(D, N, EQ, VF, SF)                                                                          \
+    {D, N, EQ, VF, SF, 0, &rhs_launch<D, N, EQ, VF, SF, false, true, 0>, RhsShape<D, N, EQ, VF, false>::SLOT, 1, \
+     &rhs_launch_p<D, N, EQ, VF, SF, false, true, 0>, 0}
+// the alternative LDS tiling of a configuration: the pair and face work items
+// in CH chunks instead of the default number (2 for the element types whose
+// pair fluxes exceed 1,200 doubles, else 1)
+#define RHS_ENTRY_T(D, N, EQ, VF, SF, CV, CH)                                                                 \
+    {D, N, EQ, VF, SF, CV, &rhs_launch<D, N, EQ, VF, SF, (bool)CV, false, CH>,                                \
+     RhsShape<D, N, EQ, VF, (bool)CV, CH>::SLOT, 0, &rhs_launch_p<D, N, EQ, VF, SF, (bool)CV, false, CH>, 1}
 
 const RhsEntry kRhs[] = {
     // 2D perfect gas (isentropic vortex, O-grid checks)
@@ -98,6 +115,9 @@ const RhsEntry kRhs[] = {
     RHS_ENTRY_M(3, 3, 0, 0, 0), RHS_ENTRY_M(3, 3, 0, 0, 1), RHS_ENTRY_M(3, 4, 0, 0, 0), RHS_ENTRY_M(2, 3, 0, 0, 0),
     // the other volume forms with Rusanov mortar faces
     RHS_ENTRY_M(3, 3, 0, 2, 0), RHS_ENTRY_M(3, 3, 0, 3, 0), RHS_ENTRY_M(3, 3, 0, 4, 0),
+    // alternative tilings: the Navier-Stokes TGV kernel in two chunks, the
+    // curved 5-species kernels in one
+    RHS_ENTRY_T(3, 3, 1, 0, 0, 0, 2), RHS_ENTRY_T(3, 4, 2, 1, 0, 1, 1), RHS_ENTRY_T(3, 4, 2, 1, 2, 1, 1),
 };
 
 struct IndEntry {
@@ -145,6 +165,12 @@ struct dgx_ctx {
     DevBuf<double> geo, Jn, nsub, bc_state, bc_T, T, csnd, alpha, alpha_tmp, alpha_raw, grad, vpart, u1, u2, dtbuf;
     DevBuf<int> nbr, bc_kind, mort, iters, subs;
     DevBuf<double> mops;
+    // work-list launches: queue counters (next item, mortar items done) and,
+    // per elements-per-workgroup candidate 1, 2, 4, 8, the queue order of the
+    // element chunks and which of them read mortar fluxes
+    DevBuf<int> wq_ctr, wq_order[4];
+    DevBuf<unsigned char> wq_waits[4];
+    int wq_nchunks[4] = {}, wq_nfree[4] = {};
     DevBuf<double> tg;
     DevBuf<double> mflux;
     int nmortar = 0;
@@ -154,7 +180,9 @@ struct dgx_ctx {
     DevBuf<unsigned long long> rate;
     // launch configuration (autotuned elements per block)
     int epb = 1;
-    int xcd = 0;  // XCD-contiguous workgroup numbering
+    int xcd = 0;  // launch form: 0 round-robin, 1 XCD-contiguous, 2 work list
+    int tile = 0;  // 1: the alternative LDS tiling (rhs_alt)
+    const RhsEntry *rhs_alt = nullptr;
     const RhsEntry *rhs = nullptr;
     // graph cache for ssprk3
     hipGraphExec_t gexec = nullptr;
@@ -197,9 +225,12 @@ int dalloc(dgx_ctx *ctx, DevBuf<T> &b, size_t n) {
 
 int threads_for(int nn, int epb) { return ((nn * epb + 63) / 64) * 64; }
 
+// the kernel variant of the current LDS tiling
+const RhsEntry *cur_rhs(const dgx_ctx *ctx) { return ctx->tile && ctx->rhs_alt ? ctx->rhs_alt : ctx->rhs; }
+
 // process-wide autotuner cache: configuration key -> elements per workgroup
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune;  // key -> (epb, xcd)
+std::map<std::string, std::pair<int, int>> g_tune;  // key -> (epb, launch form | tiling << 2)
 
 std::string tune_key(const dgx_ctx *ctx);
 bool epb_fits(const dgx_ctx *ctx, int epb);
@@ -265,7 +296,7 @@ RhsParams base_params(dgx_ctx *ctx) {
     P.mu = ctx->cfg.mu;
     P.kappa = ctx->cfg.mu * ctx->cfg.gamma * ctx->cfg.R / ((ctx->cfg.gamma - 1.0) * ctx->cfg.Pr);
     P.epb = ctx->epb;
-    P.xcd = ctx->xcd;
+    P.xcd = ctx->xcd == 1 ? 1 : 0;  // 2: work-list launches (queue order)
     P.flags = ctx->flags.p;
     P.B = ctx->bc;
     P.M = ctx->mix;
@@ -359,16 +390,11 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
         else return set_err(ctx, DGX_E_INVAL, "NS gradients not built for this dim/N");
         tape_mark(tp, "k_grad", s);
     }
-    if (ctx->nmortar) {
-        const int th2 = c.dim == 3 ? 128 : 64;
-        const int key = c.dim * 100 + c.N * 10 + c.surface_flux;
-        switch (key) {
-            case 330: hipLaunchKernelGGL((k_mortar<3, 3, 0>), dim3(ctx->nmortar), dim3(th2), 0, s, P, ctx->nmortar); break;
-            case 331: hipLaunchKernelGGL((k_mortar<3, 3, 1>), dim3(ctx->nmortar), dim3(th2), 0, s, P, ctx->nmortar); break;
-            case 340: hipLaunchKernelGGL((k_mortar<3, 4, 0>), dim3(ctx->nmortar), dim3(th2), 0, s, P, ctx->nmortar); break;
-            case 230: hipLaunchKernelGGL((k_mortar<2, 3, 0>), dim3(ctx->nmortar), dim3(th2), 0, s, P, ctx->nmortar); break;
-            default: return set_err(ctx, DGX_E_INVAL, "no mortar kernel for this configuration");
-        }
+    const bool persist = ctx->xcd == 2;
+    if (ctx->nmortar && !persist) {
+        // the grid form's mortar pass: the work-list kernel with no queue
+        WorkQ Q{nullptr, nullptr, nullptr, nullptr, ctx->nmortar, 0, 0};
+        cur_rhs(ctx)->fnp(P, mode, th, 0, s, Q);
         tape_mark(tp, "k_mortar", s);
     }
     P.out = out;
@@ -376,7 +402,15 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
     P.sa = sa;
     P.sb = sb;
     P.dt = dt;
-    ctx->rhs->fn(P, mode, blocks, th, (size_t)epb * ctx->rhs->slot * sizeof(double), s);
+    if (persist) {
+        const int k = epb == 1 ? 0 : epb == 2 ? 1 : epb == 4 ? 2 : 3;
+        hipLaunchKernelGGL(k_workq_reset, dim3(1), dim3(64), 0, s, ctx->wq_ctr.p, ctx->wq_ctr.p + 1);
+        WorkQ Q{ctx->wq_ctr.p, ctx->wq_ctr.p + 1, ctx->wq_order[k].p, ctx->wq_waits[k].p, ctx->nmortar,
+                ctx->wq_nchunks[k], ctx->wq_nfree[k]};
+        cur_rhs(ctx)->fnp(P, mode, th, (size_t)epb * cur_rhs(ctx)->slot * sizeof(double), s, Q);
+    } else {
+        cur_rhs(ctx)->fn(P, mode, blocks, th, (size_t)epb * cur_rhs(ctx)->slot * sizeof(double), s);
+    }
     tape_mark(tp, "k_rhs", s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_err(ctx, DGX_E_DEVICE, std::string("rhs launch: ") + hipGetErrorString(e));
@@ -400,7 +434,7 @@ bool epb_fits(const dgx_ctx *ctx, int epb) {
         const size_t gslot = std::max<size_t>((size_t)nw * ctx->nn + (size_t)nw * nsf, (size_t)dim * nw * ctx->nn);
         if ((size_t)epb * gslot * sizeof(double) > 64 * 1024) return false;
     }
-    return (size_t)epb * ctx->rhs->slot * sizeof(double) <= 64 * 1024;
+    return (size_t)epb * cur_rhs(ctx)->slot * sizeof(double) <= 64 * 1024;
 }
 
 template <int DIM, int N, bool MIX, bool CURV>
@@ -624,23 +658,54 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
     const int want_m = m->nmortar ? 1 : 0;
     for (const auto &e : kRhs)
         if (e.dim == dim && e.N == N && e.eq == ctx->cfg.equation && e.vf == ctx->cfg.volume_flux &&
-            e.sf == ctx->cfg.surface_flux && e.curv == (affine ? 0 : 1) && e.mort == want_m)
+            e.sf == ctx->cfg.surface_flux && e.curv == (affine ? 0 : 1) && e.mort == want_m && !e.alt)
             sel = &e;
     if (!sel && affine && !want_m)  // fall back to the curved variant (valid for any mesh)
         for (const auto &e : kRhs)
             if (e.dim == dim && e.N == N && e.eq == ctx->cfg.equation && e.vf == ctx->cfg.volume_flux &&
-                e.sf == ctx->cfg.surface_flux && e.curv == 1 && e.mort == 0)
+                e.sf == ctx->cfg.surface_flux && e.curv == 1 && e.mort == 0 && !e.alt)
                 sel = &e, affine = false;
     if (!sel) return set_err(ctx, DGX_E_INVAL, "no kernel variant for this configuration and mesh");
+    const RhsEntry *alt = nullptr;
+    for (const auto &e : kRhs)
+        if (e.alt && e.dim == sel->dim && e.N == sel->N && e.eq == sel->eq && e.vf == sel->vf && e.sf == sel->sf &&
+            e.curv == sel->curv && e.mort == sel->mort)
+            alt = &e;
     clear_graph(ctx);
     ctx->mesh_ok = false;
     ctx->rhs = sel;
+    ctx->rhs_alt = alt;
+    ctx->tile = 0;
     ctx->curved = !affine;
     ctx->nelem = E;
     ctx->nbc = m->nbc;
     int rc;
     if ((rc = dalloc(ctx, ctx->nbr, nbr.size()))) return rc;
     HIPCHK(hipMemcpy(ctx->nbr.p, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice));
+    // work queues: element chunks without non-conforming faces
+    // first, then those that read mortar fluxes
+    if ((rc = dalloc(ctx, ctx->wq_ctr, 2))) return rc;
+    for (int k = 0; k < 4; ++k) {
+        const int epb = 1 << k;
+        const int nch = (E + epb - 1) / epb;
+        std::vector<int> order;
+        std::vector<unsigned char> waits(nch, 0), wq(nch);
+        order.reserve(nch);
+        for (int c = 0; c < nch; ++c) {
+            for (int e = c * epb; e < std::min(E, (c + 1) * epb) && !waits[c]; ++e)
+                for (int f = 0; f < 2 * dim; ++f)
+                    if (nbr[(size_t)e * 2 * dim + f] <= kMortBase) waits[c] = 1;
+            if (!waits[c]) order.push_back(c);
+        }
+        for (int c = 0; c < nch; ++c)
+            if (waits[c]) order.push_back(c);
+        for (int i = 0; i < nch; ++i) wq[i] = waits[order[i]];
+        if ((rc = dalloc(ctx, ctx->wq_order[k], nch)) || (rc = dalloc(ctx, ctx->wq_waits[k], nch))) return rc;
+        HIPCHK(hipMemcpy(ctx->wq_order[k].p, order.data(), nch * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(ctx->wq_waits[k].p, wq.data(), nch, hipMemcpyHostToDevice));
+        ctx->wq_nchunks[k] = nch;
+        ctx->wq_nfree[k] = (int)std::count(waits.begin(), waits.end(), (unsigned char)0);
+    }
     if (affine) {
         const int GA = dim * dim + 1;
         std::vector<double> g((size_t)E * GA);
@@ -747,9 +812,15 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(tune_key(ctx));
-        if (it != g_tune.end() && epb_fits(ctx, it->second.first)) {
-            ctx->epb = it->second.first;
-            ctx->xcd = it->second.second;
+        if (it != g_tune.end()) {
+            const int saved_tile = ctx->tile;
+            ctx->tile = (it->second.second >> 2) && ctx->rhs_alt ? 1 : 0;
+            if (epb_fits(ctx, it->second.first)) {
+                ctx->epb = it->second.first;
+                ctx->xcd = it->second.second & 3;
+            } else {
+                ctx->tile = saved_tile;
+            }
         }
     }
     ctx->mesh_ok = true;
@@ -1106,10 +1177,19 @@ int dgx_kernel_times(dgx_ctx *ctx, const double *u, int reps, double *ms_out, in
 int dgx_set_launch(dgx_ctx *ctx, int epb, int order) {
     int rc = check_ctx(ctx);
     if (rc) return rc;
-    if (!epb_fits(ctx, epb)) return set_err(ctx, DGX_E_INVAL, "elements per workgroup must be 1, 2, 4 or 8 and fit in 512 threads and 64 KB of LDS");
-    if (order < -1 || order > 1) return set_err(ctx, DGX_E_INVAL, "workgroup order must be -1, 0 or 1");
-    const int xcd = order < 0 ? ctx->xcd : order;
-    if (epb != ctx->epb || xcd != ctx->xcd) clear_graph(ctx);
+    if (order < -1 || (order >= 0 && ((order & 3) > 2 || (order >> 2) > 1)))
+        return set_err(ctx, DGX_E_INVAL, "launch order must be -1, or 0, 1, 2 plus 4 for the alternative LDS tiling");
+    const int xcd = order < 0 ? ctx->xcd : (order & 3);
+    const int tile = order < 0 ? ctx->tile : (order >> 2);
+    if (tile && !ctx->rhs_alt)
+        return set_err(ctx, DGX_E_INVAL, "no alternative LDS tiling for this configuration");
+    const int saved_tile = ctx->tile;
+    ctx->tile = tile;
+    if (!epb_fits(ctx, epb)) {
+        ctx->tile = saved_tile;
+        return set_err(ctx, DGX_E_INVAL, "elements per workgroup must be 1, 2, 4 or 8 and fit in 512 threads and 64 KB of LDS");
+    }
+    if (epb != ctx->epb || xcd != ctx->xcd || tile != saved_tile) clear_graph(ctx);
     ctx->epb = epb;
     ctx->xcd = xcd;
     return DGX_OK;
@@ -1119,7 +1199,7 @@ int dgx_get_launch(dgx_ctx *ctx, int *epb, int *order) {
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (epb) *epb = ctx->epb;
-    if (order) *order = ctx->xcd;
+    if (order) *order = ctx->xcd | (ctx->tile << 2);
     return DGX_OK;
 }
 
@@ -1146,24 +1226,30 @@ int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *
         return r;
     };
     const int cand[4] = {1, 2, 4, 8};
-    const int saved = ctx->epb, saved_xcd = ctx->xcd;
+    const int saved = ctx->epb, saved_xcd = ctx->xcd, saved_tile = ctx->tile;
     // the fastest candidate of each numbering; the default numbering (chosen
     // from the state size) is kept unless the other one is faster by more
     // than 2%: run-to-run noise is of that order, while the numberings' HBM
     // traffic can differ by much more (the round-robin order re-reads face
     // neighbours from memory when the state fits the Infinity Cache)
     const int def_xcd = (size_t)ctx->nvar * ctx->nelem * ctx->nn * sizeof(double) <= (size_t)128 << 20;
-    int best_epb[2] = {saved, saved};
-    double best_ms[2] = {1e300, 1e300};
+    // per launch form and tiling (index xm + 3 tile): the best time and its
+    // elements per workgroup
+    int best_epb[6] = {saved, saved, saved, saved, saved, saved};
+    double best_ms[6] = {1e300, 1e300, 1e300, 1e300, 1e300, 1e300};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    for (int i = 0; i < 4 && !rc; ++i) {
+    for (int i = 0; i < 4; ++i)
         if (ms_out) ms_out[i] = -1.0;
+    for (int tl = 0; tl < (ctx->rhs_alt ? 2 : 1) && !rc; ++tl)
+    for (int i = 0; i < 4 && !rc; ++i) {
+        ctx->tile = tl;
         if (!epb_fits(ctx, cand[i])) continue;
         ctx->epb = cand[i];
         // both workgroup numberings (round-robin over the XCDs, XCD-contiguous)
-        for (int xm = 0; xm < 2 && !rc; ++xm) {
+        // and the work-list form
+        for (int xm = 0; xm < 3 && !rc; ++xm) {
             ctx->xcd = xm;
             for (int w = 0; w < 2 && !rc; ++w) rc = step();
             (void)hipEventRecord(e0, s);
@@ -1175,23 +1261,28 @@ int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *
             (void)hipEventElapsedTime(&ms, e0, e1);
             const double avg = ms / (3.0 * reps);  // per right-hand side
             if (ms_out && (ms_out[i] < 0.0 || avg < ms_out[i])) ms_out[i] = avg;
-            if (avg < best_ms[xm]) {
-                best_ms[xm] = avg;
-                best_epb[xm] = cand[i];
+            if (avg < best_ms[xm + 3 * tl]) {
+                best_ms[xm + 3 * tl] = avg;
+                best_epb[xm + 3 * tl] = cand[i];
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    const int best_xcd = best_ms[1 - def_xcd] < 0.98 * best_ms[def_xcd] ? 1 - def_xcd : def_xcd;
-    const int best = best_epb[best_xcd];
+    // the default (numbering from the state size, default tiling) unless
+    // another is faster by more than 2%
+    int bi = def_xcd;
+    for (int k = 0; k < 6; ++k)
+        if (best_ms[k] < 0.98 * best_ms[def_xcd] && best_ms[k] < best_ms[bi]) bi = k;
+    const int best = best_epb[bi], best_xcd = bi % 3, best_tile = bi / 3;
     ctx->epb = rc ? saved : best;
     ctx->xcd = rc ? saved_xcd : best_xcd;
-    if (ctx->epb != saved || ctx->xcd != saved_xcd) clear_graph(ctx);
+    ctx->tile = rc ? saved_tile : best_tile;
+    if (ctx->epb != saved || ctx->xcd != saved_xcd || ctx->tile != saved_tile) clear_graph(ctx);
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[tune_key(ctx)] = std::make_pair(best, best_xcd);
+        g_tune[tune_key(ctx)] = std::make_pair(best, best_xcd | (best_tile << 2));
     }
     if (epb_out) *epb_out = best;
     return DGX_OK;
@@ -1359,6 +1450,11 @@ void dgx_destroy(dgx_ctx *ctx) {
     for (auto *b : bufs) b->release();
     ctx->nbr.release();
     ctx->mops.release();
+    ctx->wq_ctr.release();
+    for (int k = 0; k < 4; ++k) {
+        ctx->wq_order[k].release();
+        ctx->wq_waits[k].release();
+    }
     ctx->bc_kind.release();
     ctx->mort.release();
     ctx->mflux.release();

@@ -117,7 +117,9 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-template <int DIM, int N, int EQ, int VF, bool CURV>
+// CHF: work-item chunks of the pair and face phases (the LDS tiling): 0 the
+// default rule below, else that many chunks
+template <int DIM, int N, int EQ, int VF, bool CURV, int CHF = 0>
 struct RhsShape {
     static constexpr int N1 = N + 1;
     static constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
@@ -135,7 +137,7 @@ struct RhsShape {
     static constexpr int NSF = 2 * DIM * NF; // face nodes
     // large element types handle their pair and face work items in two
     // chunks, which halves the flux buffer (LDS bounds their occupancy)
-    static constexpr int NCH = PD * NV > 1200 ? 2 : 1;
+    static constexpr int NCH = CHF ? CHF : (PD * NV > 1200 ? 2 : 1);
     static constexpr int PDC = (PD + NCH - 1) / NCH;    // pairs per chunk
     static constexpr int NSFC = (NSF + NCH - 1) / NCH;  // face nodes per chunk
     // the volume pair fluxes are stored pair-major (a pair's NV fluxes are
@@ -195,9 +197,10 @@ __device__ __forceinline__ void lds_state(const double *su, const double *sq, in
     }
 }
 
-template <int DIM, int N, int EQ, int VF, int SF, bool CURV, bool MORT = false>
-__global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
-    using S = RhsShape<DIM, N, EQ, VF, CURV>;
+// One workgroup's chunk of the right-hand side: elements e0 .. e0 + epb - 1.
+template <int DIM, int N, int EQ, int VF, int SF, bool CURV, bool MORT, int CHF = 0>
+__device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) {
+    using S = RhsShape<DIM, N, EQ, VF, CURV, CHF>;
     constexpr int N1 = S::N1, NN = S::NN, NF = S::NF, NV = S::NV, NQ = S::NQ, NW = S::NW;
     constexpr int NPL = S::NPL, PD = S::PD, NFV = S::NFV, NSF = S::NSF;
     constexpr int NCH = S::NCH, PDC = S::PDC, NSFC = S::NSFC, NVP = S::NVP;
@@ -227,7 +230,6 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
         }
     }
     const int NT = P.epb * NN;  // threads that own a node
-    const int e0 = (P.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x) * P.epb;
     const int nloc = min(P.epb, P.nelem - e0);
     int el = tid / NN;
     const int node = tid - el * NN;
@@ -417,7 +419,7 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
                 const int nb = nbf[g];
                 double F[NV];
                 if (MORT && nb <= kMortBase) {
-                    // non-conforming face: sub-face fluxes from k_mortar
+                    // non-conforming face: sub-face fluxes from the mortar items
                     constexpr int NSUB = DIM == 3 ? 4 : 2;
                     const int code = kMortBase - nb;
                     const int m = code >> 3, role = code & 7;
@@ -765,16 +767,14 @@ __global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
 // Riemann flux uses the small element's trace and scaled normal and is
 // oriented along +xi_d (lower-xi state first).  Perfect gas, affine elements.
 template <int DIM, int N, int SF>
-__global__ void __launch_bounds__(128) k_mortar(RhsParams P, int nmort) {
+__device__ __forceinline__ void mortar_item(const RhsParams &P, int m, int t) {
     constexpr int N1 = N + 1;
     constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
     constexpr int NF = NN / N1;
     constexpr int NV = DIM + 2;
     constexpr int NSUB = DIM == 3 ? 4 : 2;
     constexpr int GA = DIM * DIM + 1;
-    const int m = blockIdx.x;
-    const int t = threadIdx.x;
-    if (m >= nmort || t >= NSUB * NF) return;
+    if (t >= NSUB * NF) return;
     const int s = t / NF, q = t - s * NF;
     const int *row = P.mort + (size_t)m * (3 + NSUB);
     const int eL = row[0], fL = row[1], es = row[2 + s], fS = row[2 + NSUB];
@@ -786,7 +786,9 @@ __global__ void __launch_bounds__(128) k_mortar(RhsParams P, int nmort) {
     double ui[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) ui[v] = 0.0;
-#pragma unroll
+    // (partly rolled: in the work-list kernel this code shares the
+    // right-hand side's register budget)
+#pragma unroll 4
     for (int j = 0; j < NF; ++j) {
         const int ja = j % N1, jb = j / N1;
         double w = P.mops[a * 25 + qa * N1 + ja];
@@ -819,6 +821,98 @@ __global__ void __launch_bounds__(128) k_mortar(RhsParams P, int nmort) {
     double *out = const_cast<double *>(P.mflux) + (size_t)m * NSUB * NV * NF;
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[(s * NV + v) * NF + q] = F[v];
+}
+
+
+
+template <int DIM, int N, int EQ, int VF, int SF, bool CURV, bool MORT = false, int CHF = 0>
+__global__ void __launch_bounds__(512) k_rhs(RhsParams P, int mode) {
+    const int e0 = (P.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x) * P.epb;
+    rhs_chunk<DIM, N, EQ, VF, SF, CURV, MORT, CHF>(P, mode, e0);
+}
+
+// Work-list form: one launch over the mortars' sub-face fluxes (the mortar
+// pass, non-conforming meshes) and the element chunks.  The mortar items and
+// the chunks with a non-conforming face form a queue, mortar items first,
+// claimed in order by the first workgroups (an atomic counter, not their
+// block index); a chunk that comes up before every mortar item has finished
+// waits for them.  The other chunks go to the remaining workgroups by block
+// index.  The wait is bounded
+// and cannot deadlock: every mortar item was claimed before the chunk by a
+// workgroup that was already running and finishes it without waiting (should
+// the bound ever be reached the chunk proceeds and the non-physical flag is
+// raised).  Q.next and Q.done must be 0 at launch.  With Q.next null the
+// kernel is the mortar pass of the grid form instead (block b: mortar item b,
+// no element chunks): both forms then evaluate the sub-face fluxes with the
+// same compiled code, bitwise alike.  (A persistent form, a
+// grid of resident workgroups looping over the queue, was measured: the loop
+// lets the compiler keep hoisted kernel-argument tables in registers, 215-256
+// VGPRs, or 0.5-1.6 KB of spills per lane when held to the grid form's five
+// waves; one item per workgroup keeps the grid form's registers.)
+struct WorkQ {
+    int *next;          // next item to claim
+    int *done;          // mortar items finished
+    const int *order;   // [nchunks] element chunk of queue position
+    const unsigned char *waits;  // [nchunks] 1: the chunk reads mortar fluxes
+    int nmort, nchunks;
+    int nfree;          // chunks order[0 .. nfree-1] read no mortar fluxes
+};
+
+template <int DIM, int N, int EQ, int VF, int SF, bool CURV, bool MORT = false, int CHF = 0>
+__global__ void __launch_bounds__(512) k_rhs_queue(RhsParams P, int mode, WorkQ Q) {
+    __shared__ int s_item;
+    if (Q.next == nullptr) {
+        if constexpr (MORT) {
+            if ((int)blockIdx.x < Q.nmort) mortar_item<DIM, N, SF>(P, blockIdx.x, threadIdx.x);
+        }
+        return;
+    }
+    // blocks 0 .. nq-1 claim the queue's mortar items and then the chunks
+    // that read them; the blocks after take the other chunks directly (no
+    // counter: a single address claimed by every block serialises them)
+    const int nq = Q.nmort + Q.nchunks - Q.nfree;
+    const int b = blockIdx.x;
+    if (b >= nq) {
+        if (b - nq < Q.nfree) rhs_chunk<DIM, N, EQ, VF, SF, CURV, MORT, CHF>(P, mode, Q.order[b - nq] * P.epb);
+        return;
+    }
+    if (threadIdx.x == 0) s_item = atomicAdd(Q.next, 1);
+    __syncthreads();
+    const int item = s_item < Q.nmort ? s_item : s_item + Q.nfree;  // queue position -> item
+    if (item >= Q.nmort + Q.nchunks) return;
+    if (MORT && item < Q.nmort) {
+        if constexpr (MORT) mortar_item<DIM, N, SF>(P, item, threadIdx.x);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();  // the sub-face fluxes before the count
+            atomicAdd(Q.done, 1);
+        }
+        return;
+    }
+    const int k = item - Q.nmort;
+    if (MORT && Q.waits[k]) {
+        if (threadIdx.x == 0) {
+            // poll without ordering (an acquire per poll would invalidate the
+            // caches every time), then one acquire fence
+            int spins = 0;
+            while (__hip_atomic_load(Q.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < Q.nmort &&
+                   spins < (1 << 24)) {
+                __builtin_amdgcn_s_sleep(2);
+                ++spins;
+            }
+            if (spins >= (1 << 24)) atomicOr(P.flags, FLAG_NONPHYS);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+    }
+    rhs_chunk<DIM, N, EQ, VF, SF, CURV, MORT, CHF>(P, mode, Q.order[k] * P.epb);
+}
+
+__global__ void k_workq_reset(int *next, int *done) {
+    if (threadIdx.x == 0) {
+        *next = 0;
+        *done = 0;
+    }
 }
 
 }  // namespace dgx

@@ -389,13 +389,13 @@ def dgx_autotune(ctx, u, reps=10, stream=None):
 
 
 def dgx_set_launch(ctx, epb, order=-1):
-    """Elements per workgroup and workgroup numbering (0 round-robin over the
-    XCDs, 1 XCD-contiguous, -1 keep)."""
+    """Elements per workgroup and launch form (0 round-robin over the XCDs,
+    1 XCD-contiguous, 2 work-list queue, -1 keep)."""
     _raise(ctx, lib.dgx_set_launch(ctx, int(epb), int(order)))
 
 
 def dgx_get_launch(ctx):
-    """(elements per workgroup, workgroup numbering) in use."""
+    """(elements per workgroup, launch form 0/1/2) in use."""
     epb, order = C.c_int(), C.c_int()
     _raise(ctx, lib.dgx_get_launch(ctx, C.byref(epb), C.byref(order)))
     return epb.value, order.value
