@@ -72,11 +72,12 @@ class Operator:
         return self.mix.state(u, self.dim, T)
 
     # volume and surface flux choices (the library's DGX_VF_* / DGX_SF_*
-    # numbering); "kg" / "pirozzoli" as a surface flux serve the oracle's
+    # numbering); "kg" / "pirozzoli" / "morinishi" as a surface flux serve the oracle's
     # own kinetic-energy checks
-    VOLUME = {0: gas.ranocha, 1: gas.ducros, 2: gas.kennedy_gruber, 3: gas.pirozzoli, 4: gas.central}
+    VOLUME = {0: gas.ranocha, 1: gas.ducros, 2: gas.kennedy_gruber, 3: gas.pirozzoli, 4: gas.central,
+              5: gas.morinishi}
     SURFACE = {0: gas.rusanov, 1: gas.ranocha, 2: gas.hll, 3: gas.hllc, "kg": gas.kennedy_gruber,
-               "pirozzoli": gas.pirozzoli}
+               "pirozzoli": gas.pirozzoli, "morinishi": gas.morinishi}
 
     def volume_flux(self, sL, sR, n):
         return self.VOLUME[self.cfg["volume_flux"]](sL, sR, n)

@@ -112,16 +112,25 @@ def ducros(sL, sR, n):
     return np.stack(rows, 0)
 
 
+def _mass_rows(sL, sR, f_rho):
+    """Mass rows of a split form: the total mass flux f_rho, or for a mixture
+    that flux times the averaged mass fractions {{rho_s/rho}} (the species
+    rows then add up to f_rho)."""
+    if not sL["mix"]:
+        return [f_rho]
+    return [f_rho * 0.5 * (a / sL["rho"] + b / sR["rho"]) for a, b in zip(sL["rs"], sR["rs"])]
+
+
 def kennedy_gruber(sL, sR, n):
-    """Kennedy-Gruber split form as a two-point flux (perfect gas), one of the
-    split forms the paper lists as interchangeable volume fluxes (Sec.
-    Methodology, after Eq. conssymm): mass {{rho}}{{v.n}}, momentum that mass
-    flux times {{v}} plus {{p}} n, energy that mass flux times {{E/rho}} plus
-    {{p}}{{v.n}}."""
+    """Kennedy-Gruber split form as a two-point flux, one of the split forms
+    the paper lists as interchangeable volume fluxes (Sec. Methodology, after
+    Eq. conssymm): mass {{rho}}{{v.n}} (mixtures: species that times
+    {{rho_s/rho}}), momentum that mass flux times {{v}} plus {{p}} n, energy
+    that mass flux times {{E/rho}} plus {{p}}{{v.n}}."""
     vn = dot(0.5 * (sL["v"] + sR["v"]), n)
     pbar = 0.5 * (sL["p"] + sR["p"])
     f_rho = 0.5 * (sL["rho"] + sR["rho"]) * vn
-    rows = [f_rho]
+    rows = _mass_rows(sL, sR, f_rho)
     for c in range(sL["v"].shape[0]):
         rows.append(f_rho * 0.5 * (sL["v"][c] + sR["v"][c]) + pbar * n[c])
     e_bar = 0.5 * (sL["rhoE"] / sL["rho"] + sR["rhoE"] / sR["rho"])
@@ -130,17 +139,38 @@ def kennedy_gruber(sL, sR, n):
 
 
 def pirozzoli(sL, sR, n):
-    """Pirozzoli split form as a two-point flux (perfect gas), listed beside
-    Kennedy-Gruber (Sec. Methodology): mass and momentum as Kennedy-Gruber,
-    energy the mass flux times {{h}}, h = (E + p)/rho per node."""
+    """Pirozzoli split form as a two-point flux, listed beside Kennedy-Gruber
+    (Sec. Methodology): mass and momentum as Kennedy-Gruber, energy the mass
+    flux times {{h}}, h = (E + p)/rho per node."""
     vn = dot(0.5 * (sL["v"] + sR["v"]), n)
     pbar = 0.5 * (sL["p"] + sR["p"])
     f_rho = 0.5 * (sL["rho"] + sR["rho"]) * vn
-    rows = [f_rho]
+    rows = _mass_rows(sL, sR, f_rho)
     for c in range(sL["v"].shape[0]):
         rows.append(f_rho * 0.5 * (sL["v"][c] + sR["v"][c]) + pbar * n[c])
     h_bar = 0.5 * ((sL["rhoE"] + sL["p"]) / sL["rho"] + (sR["rhoE"] + sR["p"]) / sR["rho"])
     rows.append(f_rho * h_bar)
+    return np.stack(rows, 0)
+
+
+def morinishi(sL, sR, n):
+    """Morinishi's skew-symmetric splitting as a two-point flux (perfect gas),
+    named beside the other split forms (Sec. Methodology): the mass flux is
+    the average of the momenta, {{rho v}}.n; momentum that flux times {{v}}
+    plus {{p}} n; energy that flux times the internal energy {{p/((gamma-1)
+    rho)}} plus the kinetic energy of the two velocities v_L.v_R/2, plus the
+    pressure work {{p v}}.n."""
+    g = sL["gamma"]
+    mL, mR = sL["rho"] * sL["v"], sR["rho"] * sR["v"]
+    f_rho = dot(0.5 * (mL + mR), n)
+    pbar = 0.5 * (sL["p"] + sR["p"])
+    rows = [f_rho]
+    for c in range(sL["v"].shape[0]):
+        rows.append(f_rho * 0.5 * (sL["v"][c] + sR["v"][c]) + pbar * n[c])
+    e_int = 0.5 * (sL["p"] / sL["rho"] + sR["p"] / sR["rho"]) / (g - 1.0)
+    kin = 0.5 * dot(sL["v"], sR["v"])
+    pv = dot(0.5 * (sL["p"] * sL["v"] + sR["p"] * sR["v"]), n)
+    rows.append(f_rho * (e_int + kin) + pv)
     return np.stack(rows, 0)
 
 
@@ -169,7 +199,9 @@ def central(sL, sR, n):
 
 def hllc(sL, sR, n):
     """HLLC Riemann flux (named among the interface solvers, Sec.
-    Methodology), perfect gas, Davis bounds as in hll, on the unit normal
+    Methodology), perfect gas or mixture (frozen sound speed; the species
+    densities of a star state scale like its total density), Davis bounds as
+    in hll, on the unit normal
     n/|n| and scaled by |n|.  Contact speed
     S* = (p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R))
          / (rho_L (S_L - u_L) - rho_R (S_R - u_R)),
@@ -187,7 +219,8 @@ def hllc(sL, sR, n):
 
     def star(st, S, u):
         fac = st["rho"] * (S - u) / (S - Ss)
-        rows = [fac]
+        # mixtures: each species density scales like the total density
+        rows = [fac * rs / st["rho"] for rs in st["rs"]] if st["mix"] else [fac]
         rows += [fac * (st["v"][c] + (Ss - u) * nh[c]) for c in range(st["v"].shape[0])]
         rows.append(fac * (st["rhoE"] / st["rho"] + (Ss - u) * (Ss + st["p"] / (st["rho"] * (S - u)))))
         return np.stack(rows, 0)

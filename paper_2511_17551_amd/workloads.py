@@ -47,13 +47,14 @@ EQ_REACT_MIX = 3   # as above plus Arrhenius species sources
 
 VF_RANOCHA = 0     # entropy-conservative two-point flux
 VF_DUCROS = 1      # Ducros split-form two-point flux
-VF_KENNEDY_GRUBER = 2  # Kennedy-Gruber split form (perfect gas)
-VF_PIROZZOLI = 3   # Pirozzoli split form (perfect gas)
-VF_CENTRAL = 4     # standard-DG form: mean of the physical fluxes (perfect gas)
+VF_KENNEDY_GRUBER = 2  # Kennedy-Gruber split form
+VF_PIROZZOLI = 3   # Pirozzoli split form
+VF_CENTRAL = 4     # standard-DG form: mean of the physical fluxes
+VF_MORINISHI = 5   # Morinishi's skew-symmetric splitting (perfect gas)
 SF_RUSANOV = 0     # local Lax-Friedrichs surface flux
 SF_RANOCHA = 1     # EC flux at faces (entropy-conservation checks only)
 SF_HLL = 2         # HLL with Davis wave-speed bounds
-SF_HLLC = 3        # HLLC, Davis bounds and Toro's contact speed (perfect gas)
+SF_HLLC = 3        # HLLC, Davis bounds and Toro's contact speed
 
 IND_RHO_P = 0      # shock indicator variable rho*p
 IND_P = 1          # shock indicator variable p
@@ -343,6 +344,40 @@ def curved_periodic_case(n=3, N=3, eq=EQ_EULER, amp=0.1, seed=7, **kw):
     mesh = Mesh(3, N, x, faces, bfaces, np.zeros((0, 7), np.int32),
                 np.zeros(0, np.int32), np.zeros((0, 5)))
     return Case("curved_periodic", cfg, mesh, u0)
+
+
+def curved_periodic_mixture_case(energy, n=2, N=4, seed=5, T0=2000.0, p0=1.0e4, uniform_p=False,
+                                 **kw):
+    """Frozen 5-species air on the curved unit cube, periodic in all
+    directions: mass fractions near (0.7, 0.2, 0.04, 0.03, 0.03) with smooth
+    seeded variations of a few percent, density and velocity (a third of the
+    sound speed) varying smoothly, T around ``T0``.  With ``uniform_p`` the
+    temperature follows the density so that p = ``p0`` at every node.
+    ``energy(rho_s, T)`` supplies the thermal energy density."""
+    sp = Species()
+    x, faces, bfaces = structured_mesh(3, N, (n, n, n), (0.0,) * 3, (1.0,) * 3, (True,) * 3,
+                                       lambda X: curved_map(X, 0.1))
+    Y0 = np.array([0.7, 0.2, 0.04, 0.03, 0.03])
+    Y = Y0[:, None, None] * (1.0 + smooth_perturbation(x, seed, amp=0.3))
+    Y = Y / Y.sum(0)[None]
+    rng = np.random.default_rng(seed + 1)
+    k = rng.integers(1, 3, size=(3, 3))
+    ph = rng.uniform(0, 2 * math.pi, 3)
+    arg = [2 * math.pi * (k[i, 0] * x[0] + k[i, 1] * x[1] + k[i, 2] * x[2]) + ph[i] for i in range(3)]
+    Rmix = (Y * (sp.Ru / sp.W)[:, None, None]).sum(0)
+    if uniform_p:
+        rho = p0 / (Rmix * T0) * (1.0 + 0.3 * np.sin(arg[0]))
+        T = p0 / (rho * Rmix)
+    else:
+        T = T0 * (1.0 + 0.2 * np.cos(arg[1]))
+        rho = p0 / (Rmix * T0) * (1.0 + 0.3 * np.sin(arg[0]))
+    a = math.sqrt(1.3 * float(Rmix.mean()) * T0)
+    vel = (a * (0.3 + 0.1 * np.cos(arg[1])), a * (-0.2 + 0.1 * np.sin(arg[2])), a * 0.1 * np.cos(arg[0]))
+    u0 = mixture_state(Y, rho, vel, T, energy)
+    mesh = Mesh(3, N, x, faces, bfaces, np.zeros((0, 7), np.int32),
+                np.zeros(0, np.int32), np.zeros((0, 10)))
+    cfg = base_cfg(3, N, EQ_EULER_MIX, T_guess=T0, **kw)
+    return Case("curved_periodic_air5", cfg, mesh, u0, species=sp, extra=dict(T=T))
 
 
 def curved_channel_case(n=3, N=3, mach=2.0, amp=0.1, seed=7, **kw):

@@ -1,5 +1,6 @@
-"""Pins of the oracle's Kennedy-Gruber and Pirozzoli two-point fluxes and its
-HLL Riemann flux.
+"""Pins of the oracle's Kennedy-Gruber, Pirozzoli and Morinishi two-point
+fluxes (perfect gas and, except Morinishi, the 5-species mixture) and its HLL
+and HLLC Riemann fluxes.
 
 * Split forms: consistency (equal states give the physical flux f(u).n),
   symmetry in the two states, and the two forms coincide when density and
@@ -10,6 +11,15 @@ HLL Riemann flux.
   sum J w (v . dm/dt - |v|^2/2 drho/dt) vanishes to rounding.  A momentum
   flux averaged as {{rho v}} instead of {{rho}}{{v}}, planted in the oracle,
   breaks that by many orders of magnitude (the check can fail).
+  Morinishi's form passes the same checks (its mass flux is {{rho v}}.n,
+  its momentum still that flux times {{v}} plus {{p}} n).
+* Mixtures: a mixture whose mass is all in one species gives the
+  perfect-gas rows of the same state in that species' row and zeros in the
+  others (Kennedy-Gruber, Pirozzoli, central, HLLC), which pins the species
+  indexing; the species rows add up to the total mass flux; the split forms
+  are consistent, symmetric and kinetic-energy preserving on a periodic
+  curved mixture field at uniform pressure; HLLC resolves a contact between
+  different compositions and temperatures exactly.
 * HLL: consistency; pure upwinding when both wave-speed bounds have one sign
   (f_L for supersonic flow along n, f_R against it); and in the subsonic
   branch the flux equals both f_L + S_L (u* - u_L) and f_R + S_R (u* - u_R)
@@ -37,7 +47,7 @@ def test_split_forms_consistency_and_symmetry():
     n = rng.normal(size=(3, 400))
     fphys = gas.physical_flux(s, n)
     scale = np.abs(fphys).max()
-    for flux in (gas.kennedy_gruber, gas.pirozzoli):
+    for flux in (gas.kennedy_gruber, gas.pirozzoli, gas.morinishi):
         assert np.abs(flux(s, s, n) - fphys).max() < 1e-13 * scale
         assert np.abs(flux(s, s2, n) - flux(s2, s, n)).max() < 1e-13 * scale
 
@@ -70,7 +80,7 @@ def kinetic_energy_rate(vf, sf):
 
 
 def test_split_forms_preserve_kinetic_energy():
-    for vf, sf in ((W.VF_KENNEDY_GRUBER, "kg"), (W.VF_PIROZZOLI, "pirozzoli")):
+    for vf, sf in ((W.VF_KENNEDY_GRUBER, "kg"), (W.VF_PIROZZOLI, "pirozzoli"), (W.VF_MORINISHI, "morinishi")):
         tot, scale = kinetic_energy_rate(vf, sf)
         assert tot < 1e-13 * scale, (vf, tot, scale)
 
@@ -202,3 +212,125 @@ def test_hllc_consistency_upwinding_and_exact_contact():
     pn = a["p"] * n
     assert np.abs(F[0]).max() < 1e-13 * np.abs(pn).max() and np.abs(F[4]).max() < 1e-13 * np.abs(pn).max()
     assert np.abs(F[1:4] - pn).max() < 1e-13 * np.abs(pn).max()
+
+
+def test_morinishi_mass_flux_is_the_mean_momentum():
+    """Morinishi's mass row is {{rho v}}.n, which differs from the
+    Kennedy-Gruber {{rho}}{{v}}.n by (rho_L - rho_R)(v_L - v_R).n/4; the two
+    coincide when either density or velocity is equal on both sides."""
+    rng = np.random.default_rng(17)
+    a, b = states(rng, 300), states(rng, 300)
+    n = rng.normal(size=(3, 300))
+    d = gas.morinishi(a, b, n)[0] - gas.kennedy_gruber(a, b, n)[0]
+    ref = 0.25 * (a["rho"] - b["rho"]) * gas.dot(a["v"] - b["v"], n)
+    assert np.abs(d - ref).max() < 1e-13 * np.abs(gas.kennedy_gruber(a, b, n)[0]).max()
+
+
+def mixture_states(rng, m, mix, p=None, vmax=400.0):
+    """Mixture states with random compositions, T in 300-8000 K and either
+    random pressures or the pressures ``p``."""
+    Y = rng.uniform(0.01, 1.0, (5, m))
+    Y /= Y.sum(0)
+    T = rng.uniform(300.0, 8000.0, m)
+    Rmix = (Y * mix.Rs[:, None]).sum(0)
+    if p is None:
+        p = rng.uniform(1e3, 1e5, m)
+    rho = p / (Rmix * T)
+    v = rng.uniform(-vmax, vmax, (3, m))
+    rs = Y * rho
+    u = np.concatenate([rs, rho * v, (mix.rho_e(rs, T) + 0.5 * rho * (v * v).sum(0))[None]])
+    return mix.state(u, 3, T)
+
+
+def _mixture():
+    from oracle.thermo import Mixture
+    return Mixture(W.Species())
+
+
+def test_mixture_fluxes_with_one_species_are_the_gas_fluxes():
+    rng = np.random.default_rng(18)
+    a, b = states(rng, 300), states(rng, 300)
+    n = rng.normal(size=(3, 300))
+    for slot in (0, 3):
+        def as_mixture(st):
+            rs = np.zeros((5,) + st["rho"].shape)
+            rs[slot] = st["rho"]
+            return dict(st, rs=rs, mix=True)
+        am, bm = as_mixture(a), as_mixture(b)
+        for flux in (gas.kennedy_gruber, gas.pirozzoli, gas.central, gas.hllc):
+            f, fm = flux(a, b, n), flux(am, bm, n)
+            assert fm.shape[0] == 9
+            scale = np.abs(f).max()
+            assert np.abs(fm[slot] - f[0]).max() < 1e-14 * scale, (flux, slot)
+            assert np.abs(np.delete(fm[:5], slot, 0)).max() == 0.0, (flux, slot)
+            assert np.abs(fm[5:] - f[1:]).max() < 1e-14 * scale, (flux, slot)
+
+
+def test_mixture_split_forms_consistency_symmetry_and_mass_sum():
+    mix = _mixture()
+    rng = np.random.default_rng(19)
+    s, s2 = mixture_states(rng, 400, mix), mixture_states(rng, 400, mix)
+    n = rng.normal(size=(3, 400))
+    fphys = gas.physical_flux(s, n)
+    for flux in (gas.kennedy_gruber, gas.pirozzoli):
+        f = flux(s, s2, n)
+        scale = np.abs(f).max(1, keepdims=True)
+        assert np.all(np.abs(flux(s, s, n) - fphys) <= 1e-13 * np.abs(fphys).max(1, keepdims=True))
+        assert np.all(np.abs(f - flux(s2, s, n)) <= 1e-13 * scale)
+        f_rho = 0.5 * (s["rho"] + s2["rho"]) * gas.dot(0.5 * (s["v"] + s2["v"]), n)
+        assert np.abs(f[:5].sum(0) - f_rho).max() < 1e-13 * np.abs(f_rho).max()
+
+
+def test_mixture_split_forms_preserve_kinetic_energy():
+    mix = _mixture()
+    for vf, sf in ((W.VF_KENNEDY_GRUBER, "kg"), (W.VF_PIROZZOLI, "pirozzoli")):
+        c = W.curved_periodic_mixture_case(lambda rs, T: mix.rho_e(rs, T), n=2, N=3, uniform_p=True,
+                                           volume_flux=vf, surface_flux=sf)
+        op = Operator(c.cfg, c.mesh, species=c.species)
+        u = c.u0
+        du = op.rhs(u)
+        rho = u[:5].sum(0)
+        v = u[5:8] / rho
+        w = np.einsum("i,j,k->kji", op.b.w, op.b.w, op.b.w).reshape(-1)
+        dens = ((v * du[5:8]).sum(0) - 0.5 * (v * v).sum(0) * du[:5].sum(0)) * op.J * w
+        assert abs(dens.sum()) < 1e-13 * np.abs(dens).sum(), (vf, abs(dens.sum()), np.abs(dens).sum())
+
+
+def test_mixture_hllc_consistency_upwinding_and_exact_contact():
+    mix = _mixture()
+    rng = np.random.default_rng(20)
+    s, s2 = mixture_states(rng, 400, mix), mixture_states(rng, 400, mix)
+    n = rng.normal(size=(3, 400))
+    fphys = gas.physical_flux(s, n)
+    assert np.all(np.abs(gas.hllc(s, s, n) - fphys) <= 1e-13 * np.abs(fphys).max(1, keepdims=True))
+    nh = n / np.sqrt((n * n).sum(0))
+    # both states moved faster than their sound speeds along +n / -n
+    shift = 1.5 * max((np.sqrt((st["v"] ** 2).sum(0)) + st["c"]).max() for st in (s, s2))
+    for sign, pick in ((1.0, 0), (-1.0, 1)):
+        ab = []
+        for st in (s, s2):
+            v = st["v"] + sign * shift * nh
+            u = np.concatenate([st["rs"], st["rho"] * v,
+                                (st["rhoE"] - 0.5 * st["rho"] * (st["v"] ** 2).sum(0)
+                                 + 0.5 * st["rho"] * (v * v).sum(0))[None]])
+            ab.append(mix.state(u, 3, st["T"]))
+        f = gas.physical_flux(ab[pick], n)
+        assert np.all(np.abs(gas.hllc(ab[0], ab[1], n) - f) <= 1e-13 * np.abs(f).max(1, keepdims=True))
+    # a contact between different compositions and temperatures at one
+    # pressure and one normal velocity: HLLC returns the upwind flux, species
+    # rows included; HLL smears it
+    for un, pick in ((150.0, 0), (-150.0, 1)):
+        p = rng.uniform(1e3, 1e5, 300)
+        a, b = mixture_states(rng, 300, mix, p=p), mixture_states(rng, 300, mix, p=p)
+        m = rng.normal(size=(3, 300))
+        mh = m / np.sqrt((m * m).sum(0))
+        out = []
+        for st in (a, b):
+            v = st["v"] - (st["v"] * mh).sum(0) * mh + un * mh
+            u = np.concatenate([st["rs"], st["rho"] * v,
+                                (mix.rho_e(st["rs"], st["T"]) + 0.5 * st["rho"] * (v * v).sum(0))[None]])
+            out.append(mix.state(u, 3, st["T"]))
+        f = gas.physical_flux(out[pick], m)
+        scale = np.abs(f).max(1, keepdims=True)
+        assert np.all(np.abs(gas.hllc(out[0], out[1], m) - f) <= 1e-12 * scale)
+        assert np.any(np.abs(gas.hll(out[0], out[1], m) - f) > 1e-2 * scale)
