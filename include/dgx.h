@@ -60,28 +60,34 @@ extern "C" {
 /* two-point volume fluxes (Eq. fluxdiffcons) */
 #define DGX_VF_RANOCHA 0    /* entropy-conservative (perfect gas only) */
 #define DGX_VF_DUCROS 1     /* Ducros split form                       */
-#define DGX_VF_KENNEDY_GRUBER 2  /* Kennedy-Gruber split form (perfect gas) */
-#define DGX_VF_PIROZZOLI 3  /* Pirozzoli split form (perfect gas)      */
-#define DGX_VF_CENTRAL 4    /* standard-DG form, (f_L + f_R).n/2 (perfect gas) */
+#define DGX_VF_KENNEDY_GRUBER 2  /* Kennedy-Gruber split form          */
+#define DGX_VF_PIROZZOLI 3  /* Pirozzoli split form                    */
+#define DGX_VF_CENTRAL 4    /* standard-DG form, (f_L + f_R).n/2       */
+#define DGX_VF_MORINISHI 5  /* Morinishi split form (perfect gas only) */
 /* surface fluxes (Eqs. riemann_problem1-3) */
 #define DGX_SF_RUSANOV 0    /* local Lax-Friedrichs                     */
-#define DGX_SF_RANOCHA 1    /* EC flux at faces (entropy checks)        */
+#define DGX_SF_RANOCHA 1    /* EC flux at faces (entropy checks, perfect gas) */
 #define DGX_SF_HLL 2        /* HLL, Davis wave-speed bounds             */
-#define DGX_SF_HLLC 3       /* HLLC, Toro's contact speed (perfect gas)   */
+#define DGX_SF_HLLC 3       /* HLLC, Toro's contact speed               */
 /* The split forms listed in the Methodology section as interchangeable
- * volume fluxes (Kennedy-Gruber: energy {{rho}}{{v.n}}{{E/rho}} +
- * {{p}}{{v.n}}; Pirozzoli: {{rho}}{{v.n}}{{(E+p)/rho}}; both with momentum
- * {{rho}}{{v.n}}{{v}} + {{p}} n; the standard-DG form (f_L + f_R).n/2) and
- * the HLL and HLLC interface fluxes are built for
- * the 3D perfect-gas Euler equations at N = 3 (affine and curved elements,
- * conforming meshes; the three volume forms also on 2:1 non-conforming
- * meshes with Rusanov faces), at N = 4 (curved kernels, which also take
- * affine meshes), for 3D Navier-Stokes at N = 3 (affine elements) and for
- * the 2D Euler equations at N = 3 (affine elements).  HLL is also built for
- * the frozen 5-species equations at N = 4 on curved elements (frozen sound
- * speed in the wave-speed bounds).  Every other combination of equation, degree,
- * dimension and flux that the library was not built with makes dgx_create
- * return DGX_E_INVAL. */
+ * volume fluxes, with {{a}} = (a_L + a_R)/2: Kennedy-Gruber (mass flux
+ * f = {{rho}}{{v.n}}, momentum f {{v}} + {{p}} n, energy f {{E/rho}} +
+ * {{p}}{{v.n}}), Pirozzoli (energy f {{(E+p)/rho}}), Morinishi (f =
+ * {{rho v}}.n, energy f ({{p/((gamma-1) rho)}} + v_L.v_R/2) + {{p v}}.n);
+ * for mixtures the species rows of Kennedy-Gruber and Pirozzoli are
+ * f {{rho_s/rho}}.  The standard-DG form is (f_L + f_R).n/2.  These and the
+ * HLL and HLLC interface fluxes are built for the 3D perfect-gas Euler
+ * equations at N = 3 (affine and curved elements, conforming meshes; the
+ * volume forms also on 2:1 non-conforming meshes with Rusanov faces), at
+ * N = 4 (curved kernels, which also take affine meshes), for 3D
+ * Navier-Stokes at N = 3 (affine elements) and for the 2D Euler equations at
+ * N = 3 (affine elements).  For the frozen 5-species equations at N = 4 on
+ * curved elements the Kennedy-Gruber, Pirozzoli and standard-DG forms are
+ * built with Rusanov faces, and HLL and HLLC faces with the Ducros form (the
+ * frozen sound speed in the wave-speed bounds; the species densities of an
+ * HLLC star state scale like its total density).  Every other combination
+ * of equation, degree, dimension and flux that the library was not built
+ * with makes dgx_create return DGX_E_INVAL. */
 /* boundary kinds (weak, through the surface flux with an external state) */
 #define DGX_BC_DIRICHLET 0
 #define DGX_BC_OUTFLOW 1

@@ -110,11 +110,18 @@ const RhsEntry kRhs[] = {
     // mixtures
     RHS_ENTRY(3, 4, 2, 1, 0, 1), RHS_ENTRY(3, 3, 2, 1, 0, 1), RHS_ENTRY(2, 3, 2, 1, 0, 1),
     RHS_ENTRY(3, 4, 2, 1, 2, 1),  // HLL faces on the curved 5-species shock
+    // the other volume forms and HLLC faces for the curved 5-species equations
+    RHS_ENTRY(3, 4, 2, 2, 0, 1), RHS_ENTRY(3, 4, 2, 3, 0, 1), RHS_ENTRY(3, 4, 2, 4, 0, 1),
+    RHS_ENTRY(3, 4, 2, 1, 3, 1),
+    // Morinishi's form (perfect gas)
+    RHS_ENTRY(3, 3, 0, 5, 0, 0), RHS_ENTRY(3, 3, 0, 5, 0, 1), RHS_ENTRY(3, 4, 0, 5, 0, 1),
+    RHS_ENTRY(2, 3, 0, 5, 0, 0), RHS_ENTRY(3, 3, 1, 5, 0, 0),
     RHS_ENTRY(2, 3, 3, 1, 0, 1), RHS_ENTRY(2, 3, 3, 1, 0, 0),
     // non-conforming (mortar) meshes
     RHS_ENTRY_M(3, 3, 0, 0, 0), RHS_ENTRY_M(3, 3, 0, 0, 1), RHS_ENTRY_M(3, 4, 0, 0, 0), RHS_ENTRY_M(2, 3, 0, 0, 0),
     // the other volume forms with Rusanov mortar faces
     RHS_ENTRY_M(3, 3, 0, 2, 0), RHS_ENTRY_M(3, 3, 0, 3, 0), RHS_ENTRY_M(3, 3, 0, 4, 0),
+    RHS_ENTRY_M(3, 3, 0, 5, 0),
     // alternative tilings: the Navier-Stokes TGV kernel in two chunks, the
     // curved 5-species kernels in one
     RHS_ENTRY_T(3, 3, 1, 0, 0, 0, 2), RHS_ENTRY_T(3, 4, 2, 1, 0, 1, 1), RHS_ENTRY_T(3, 4, 2, 1, 2, 1, 1),
@@ -486,8 +493,8 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
         return DGX_E_INVAL;
     const bool mix = cfg->equation >= DGX_EQ_EULER_MIX;
     if (mix && (!cfg->species || cfg->species->nspecies != 5)) return DGX_E_INVAL;
-    if (mix && cfg->volume_flux != DGX_VF_DUCROS) return DGX_E_INVAL;
-    if (mix && cfg->surface_flux != DGX_SF_RUSANOV && cfg->surface_flux != DGX_SF_HLL) return DGX_E_INVAL;
+    if (mix && (cfg->volume_flux == DGX_VF_RANOCHA || cfg->volume_flux == DGX_VF_MORINISHI)) return DGX_E_INVAL;
+    if (mix && cfg->surface_flux == DGX_SF_RANOCHA) return DGX_E_INVAL;
     if (cfg->equation == DGX_EQ_REACT_MIX && !cfg->reactions) return DGX_E_INVAL;
     if (mix && cfg->reactions) {
         const dgx_reactions *r = cfg->reactions;

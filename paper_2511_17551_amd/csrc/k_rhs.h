@@ -483,9 +483,8 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                     if (side) hll<DIM, MIX>(own, ext, nrm, F);
                     else hll<DIM, MIX>(ext, own, nrm, F);
                 } else if constexpr (SF == 3) {
-                    static_assert(!MIX, "HLLC is perfect-gas only");
-                    if (side) hllc<DIM>(own, ext, nrm, F);
-                    else hllc<DIM>(ext, own, nrm, F);
+                    if (side) hllc<DIM, MIX>(own, ext, nrm, F);
+                    else hllc<DIM, MIX>(ext, own, nrm, F);
                 } else {
                     if (side) ranocha_state<DIM, MIX>(own, ext, nrm, gamma, F);
                     else ranocha_state<DIM, MIX>(ext, own, nrm, gamma, F);
@@ -641,8 +640,7 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                         } else if constexpr (VF == 4) {
                             central_state<DIM, MIX>(A, B, nbar, F);
                         } else {
-                            static_assert(!MIX, "split forms other than Ducros are perfect-gas only");
-                            split_form_state<DIM, VF == 3>(A, B, nbar, F);
+                            split_form_state<DIM, MIX, VF == 5 ? 2 : VF - 2>(A, B, nbar, gm1_inv, F);
                         }
                     }
 #pragma unroll
@@ -814,6 +812,9 @@ __device__ __forceinline__ void mortar_item(const RhsParams &P, int m, int t) {
     } else if constexpr (SF == 2) {
         if (sideL) hll<DIM, false>(A, B, nrm, F);
         else hll<DIM, false>(B, A, nrm, F);
+    } else if constexpr (SF == 3) {
+        if (sideL) hllc<DIM, false>(A, B, nrm, F);
+        else hllc<DIM, false>(B, A, nrm, F);
     } else {
         if (sideL) ranocha_state<DIM, false>(A, B, nrm, P.gamma, F);
         else ranocha_state<DIM, false>(B, A, nrm, P.gamma, F);

@@ -271,15 +271,18 @@ __device__ __forceinline__ void hll(const St<DIM, MIX> &L, const St<DIM, MIX> &R
     }
 }
 
-// HLLC flux (perfect gas), the HLL bounds with Toro's contact speed
+// HLLC flux, the HLL bounds with Toro's contact speed
 // S* = (p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R))
 //      / (rho_L (S_L - u_L) - rho_R (S_R - u_R)) on the unit normal, and the
 // star states rho_K (S_K - u_K)/(S_K - S*) (1, v_K + (S* - u_K) n,
-// E_K/rho_K + (S* - u_K)(S* + p_K/(rho_K (S_K - u_K)))); scaled by |n|.
-template <int DIM>
-__device__ __forceinline__ void hllc(const St<DIM, false> &L, const St<DIM, false> &R, const double *n,
+// E_K/rho_K + (S* - u_K)(S* + p_K/(rho_K (S_K - u_K)))); scaled by |n|.  For
+// a mixture c is the frozen sound speed and the species densities of a star
+// state scale like its total density.
+template <int DIM, bool MIX>
+__device__ __forceinline__ void hllc(const St<DIM, MIX> &L, const St<DIM, MIX> &R, const double *n,
                                      double *F) {
-    constexpr int NV = DIM + 2;
+    constexpr int off = MIX ? kNS : 1;
+    constexpr int NV = off + DIM + 1;
     const double nn = wave_sqrt(dotn<DIM>(n, n));
     const double inn = rcp(nn);
     double nh[DIM];
@@ -288,24 +291,29 @@ __device__ __forceinline__ void hllc(const St<DIM, false> &L, const St<DIM, fals
     const double uL = dotn<DIM>(L.v, nh), uR = dotn<DIM>(R.v, nh);
     const double sL = fmin(uL - L.c, uR - R.c);
     const double sR = fmax(uL + L.c, uR + R.c);
-    const St<DIM, false> &K = sL >= 0.0 ? L : R;  // the upwind state when 0 is outside the fan
+    const St<DIM, MIX> &K = sL >= 0.0 ? L : R;  // the upwind state when 0 is outside the fan
     if (sL >= 0.0 || sR <= 0.0) {
-        phys_flux<DIM, false>(K, n, F);
+        phys_flux<DIM, MIX>(K, n, F);
         return;
     }
     const double mL = L.rho * (sL - uL), mR = R.rho * (sR - uR);
     const double ss = (R.p - L.p + mL * uL - mR * uR) / (mL - mR);
     const bool left = ss >= 0.0;
-    const St<DIM, false> &S = left ? L : R;
+    const St<DIM, MIX> &S = left ? L : R;
     const double sk = left ? sL : sR, uk = left ? uL : uR, mk = left ? mL : mR;
     double f[NV], u[NV], us[NV];
-    phys_flux<DIM, false>(S, nh, f);
-    cons_of<DIM, false>(S, u);
+    phys_flux<DIM, MIX>(S, nh, f);
+    cons_of<DIM, MIX>(S, u);
     const double fac = mk / (sk - ss);
-    us[0] = fac;
+    if constexpr (MIX) {
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) us[1 + c] = fac * (S.v[c] + (ss - uk) * nh[c]);
-    us[1 + DIM] = fac * (S.rhoE / S.rho + (ss - uk) * (ss + S.p / mk));
+        for (int k = 0; k < kNS; ++k) us[k] = fac * (S.rs[k] / S.rho);
+    } else {
+        us[0] = fac;
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) us[off + c] = fac * (S.v[c] + (ss - uk) * nh[c]);
+    us[off + DIM] = fac * (S.rhoE / S.rho + (ss - uk) * (ss + S.p / mk));
 #pragma unroll
     for (int k = 0; k < NV; ++k) F[k] = (f[k] + sk * (us[k] - u[k])) * nn;
 }
@@ -363,30 +371,54 @@ __device__ __forceinline__ void ranocha_state(const St<DIM, MIX> &L, const St<DI
     ranocha_prims<DIM>(L.rho, L.v, L.p, bL, R.rho, R.v, R.p, bR, n, 1.0 / (gamma - 1.0), F);
 }
 
-// Ducros split-form flux: {{rho_s}} {{v}}.n, {{m}} {{v}}.n + {{p}} n, ({{rhoE}} + {{p}}) {{v}}.n
-// Kennedy-Gruber (PIRO false) and Pirozzoli (PIRO true) split forms as
-// two-point fluxes, perfect gas: mass flux {{rho}}{{v.n}}, momentum that
-// mass flux times {{v}} plus {{p}} n; energy that mass flux times {{E/rho}}
-// plus {{p}}{{v.n}} (Kennedy-Gruber) or times {{(E + p)/rho}} (Pirozzoli).
-template <int DIM, bool PIRO>
-__device__ __forceinline__ void split_form_state(const St<DIM, false> &L, const St<DIM, false> &R,
-                                                 const double *n, double *F) {
+// Split forms as two-point fluxes with arithmetic means {{a}} = (a_L + a_R)/2.
+// FORM 0 Kennedy-Gruber and 1 Pirozzoli: mass flux f = {{rho}}{{v.n}}
+// (mixtures: species rows f {{rho_s/rho}}), momentum f {{v}} + {{p}} n,
+// energy f {{E/rho}} + {{p}}{{v.n}} (Kennedy-Gruber) or f {{(E + p)/rho}}
+// (Pirozzoli).  FORM 2 Morinishi (perfect gas): f = {{rho v}}.n, momentum as
+// above, energy f ({{p/((gamma-1) rho)}} + v_L.v_R/2) + {{p v}}.n.
+template <int DIM, bool MIX, int FORM>
+__device__ __forceinline__ void split_form_state(const St<DIM, MIX> &L, const St<DIM, MIX> &R,
+                                                 const double *n, double gm1_inv, double *F) {
+    static_assert(!(MIX && FORM == 2), "Morinishi's form is perfect-gas only");
+    constexpr int off = MIX ? kNS : 1;
     double vb[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) vb[c] = 0.5 * (L.v[c] + R.v[c]);
     const double vn = dotn<DIM>(vb, n);
     const double pbar = 0.5 * (L.p + R.p);
-    const double fm = 0.5 * (L.rho + R.rho) * vn;
-    F[0] = fm;
+    const double iL = 1.0 / L.rho, iR = 1.0 / R.rho;
+    double fm;
+    if constexpr (FORM == 2) {
+        double mb[DIM];
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) F[1 + c] = fm * vb[c] + pbar * n[c];
-    if constexpr (PIRO) {
-        F[1 + DIM] = fm * (0.5 * ((L.rhoE + L.p) / L.rho + (R.rhoE + R.p) / R.rho));
+        for (int c = 0; c < DIM; ++c) mb[c] = 0.5 * (L.rho * L.v[c] + R.rho * R.v[c]);
+        fm = dotn<DIM>(mb, n);
     } else {
-        F[1 + DIM] = fm * (0.5 * (L.rhoE / L.rho + R.rhoE / R.rho)) + pbar * vn;
+        fm = 0.5 * (L.rho + R.rho) * vn;
+    }
+    if constexpr (MIX) {
+#pragma unroll
+        for (int k = 0; k < kNS; ++k) F[k] = fm * (0.5 * (L.rs[k] * iL + R.rs[k] * iR));
+    } else {
+        F[0] = fm;
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) F[off + c] = fm * vb[c] + pbar * n[c];
+    if constexpr (FORM == 2) {
+        const double eint = 0.5 * (L.p * iL + R.p * iR) * gm1_inv;
+        double pv[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) pv[c] = 0.5 * (L.p * L.v[c] + R.p * R.v[c]);
+        F[off + DIM] = fm * (eint + 0.5 * dotn<DIM>(L.v, R.v)) + dotn<DIM>(pv, n);
+    } else if constexpr (FORM == 1) {
+        F[off + DIM] = fm * (0.5 * ((L.rhoE + L.p) * iL + (R.rhoE + R.p) * iR));
+    } else {
+        F[off + DIM] = fm * (0.5 * (L.rhoE * iL + R.rhoE * iR)) + pbar * vn;
     }
 }
 
+// Ducros split-form flux: {{rho_s}} {{v}}.n, {{m}} {{v}}.n + {{p}} n, ({{rhoE}} + {{p}}) {{v}}.n
 template <int DIM, bool MIX>
 __device__ __forceinline__ void ducros_state(const St<DIM, MIX> &L, const St<DIM, MIX> &R,
                                              const double *n, double *F) {

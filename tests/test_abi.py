@@ -92,12 +92,15 @@ def bad_configs():
         ("negative viscosity", dict(pg, mu=-1.0), None, None),
         ("mixture without species", mix, None, None),
         ("mixture with the Ranocha flux", dict(mix, volume_flux=W.VF_RANOCHA), sp, None),
-        ("mixture with the Kennedy-Gruber flux", dict(mix, volume_flux=W.VF_KENNEDY_GRUBER), sp, None),
+        ("mixture with the Morinishi flux", dict(mix, volume_flux=W.VF_MORINISHI), sp, None),
+        ("mixture with the Ranocha surface flux", dict(mix, surface_flux=W.SF_RANOCHA), sp, None),
+        ("mixture at N = 3 with the Kennedy-Gruber flux (not built)",
+         dict(mix, N=3, volume_flux=W.VF_KENNEDY_GRUBER), sp, None),
         ("reacting mixture with the HLL flux (not built)", dict(react, surface_flux=W.SF_HLL), sp, table()),
         ("Navier-Stokes at N = 4 with the Pirozzoli flux (not built)", dict(pg, N=4, volume_flux=W.VF_PIROZZOLI), None, None),
-        ("volume flux 5", dict(pg, eq=W.EQ_EULER, volume_flux=5), None, None),
+        ("volume flux 6", dict(pg, eq=W.EQ_EULER, volume_flux=6), None, None),
         ("surface flux 4", dict(pg, eq=W.EQ_EULER, surface_flux=4), None, None),
-        ("mixture with the HLLC flux", dict(mix, surface_flux=W.SF_HLLC), sp, None),
+        ("mixture at N = 3 with the HLLC flux (not built)", dict(mix, N=3, surface_flux=W.SF_HLLC), sp, None),
         ("negative Sutherland constant", dict(pg, sutherland_S=-1.0), None, None),
         ("Sutherland law without a reference temperature", dict(pg, sutherland_S=110.0, sutherland_T0=0.0), None, None),
         ("reacting mixture without reactions", react, sp, None),

@@ -41,9 +41,9 @@ def test_small_amr_rhs(dgx, sf):
     assert e < RHS_TOL
 
 
-@pytest.mark.parametrize("vf", [W.VF_KENNEDY_GRUBER, W.VF_PIROZZOLI, W.VF_CENTRAL])
+@pytest.mark.parametrize("vf", [W.VF_KENNEDY_GRUBER, W.VF_PIROZZOLI, W.VF_CENTRAL, W.VF_MORINISHI])
 def test_small_amr_rhs_other_volume_forms(dgx, vf):
-    """The Kennedy-Gruber, Pirozzoli and standard-DG volume forms on the
+    """The Kennedy-Gruber, Pirozzoli, Morinishi and standard-DG volume forms on the
     2:1 non-conforming mesh (Rusanov faces and mortars)."""
     c = W.case_amr(base=4, radii=(0.4, 0.25), centre=(0.45, 0.5, 0.55))
     c.cfg["volume_flux"] = vf

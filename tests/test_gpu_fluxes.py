@@ -1,5 +1,5 @@
-"""The Kennedy-Gruber, Pirozzoli and standard-DG (central) volume fluxes and
-the HLL and HLLC surface fluxes on the GPU, against the oracle (right-hand
+"""The Kennedy-Gruber, Pirozzoli, Morinishi and standard-DG (central) volume
+fluxes and the HLL and HLLC surface fluxes on the GPU, against the oracle (right-hand
 side, one SSPRK3 step).
 
 * Affine 3^3 periodic Taylor-Green state (3D Euler, N = 3) and the curved
@@ -15,7 +15,14 @@ side, one SSPRK3 step).
   new volume and surface fluxes, the curved periodic state at N = 4 with
   each of them (Ducros volume flux with the HLL / HLLC faces), and the 2D
   isentropic vortex with each.
-* HLL faces on the curved 5-species Mach-3 shock (3^3 elements, N = 4).
+* HLL and HLLC faces on the curved 5-species Mach-3 shock (3^3 elements,
+  N = 4), and the Kennedy-Gruber form there with Rusanov faces.
+* The curved periodic 5-species field (2^3 elements, N = 4) with the
+  Kennedy-Gruber, Pirozzoli and central forms and with HLLC faces; its
+  composition varies by tens of percent, so a species row that averages the
+  wrong quantity fails the bound.
+* Morinishi's form on the Taylor-Green state (Euler and Navier-Stokes), the
+  curved periodic state at N = 3 and 4 and the 2D vortex.
 * One SSPRK3 step with Kennedy-Gruber on the curved mesh.
 
 The Taylor-Green density is uniform, where the Kennedy-Gruber and Pirozzoli
@@ -72,14 +79,24 @@ def vortex(vf, sf):
     return c
 
 
-def shock_hll():
-    """The curved 5-species Mach-3 shock (3^3 elements, N = 4, Ducros volume
-    flux, shocked elements blended) with HLL faces."""
+def shock_hll(sf=W.SF_HLL, vf=W.VF_DUCROS):
+    """The curved 5-species Mach-3 shock (3^3 elements, N = 4, shocked
+    elements blended) with HLL faces and the Ducros volume flux, or the
+    fluxes given."""
     from oracle.thermo import Mixture
     mix = Mixture(W.Species())
     c = W.case_c3(lambda rs, T: mix.rho_e(rs, T), lambda rs, T: mix.rho_cv(rs, T), n=3)
-    c.cfg = dict(c.cfg, surface_flux=W.SF_HLL)
+    c.cfg = dict(c.cfg, surface_flux=sf, volume_flux=vf)
     return c
+
+
+def air5_periodic(vf, sf=W.SF_RUSANOV):
+    """Frozen 5-species air on the curved periodic 2^3 mesh (N = 4): smooth
+    composition, density, temperature and velocity fields."""
+    from oracle.thermo import Mixture
+    mix = Mixture(W.Species())
+    return W.curved_periodic_mixture_case(lambda rs, T: mix.rho_e(rs, T), n=2, N=4,
+                                          volume_flux=vf, surface_flux=sf)
 
 
 CASES = [
@@ -114,6 +131,17 @@ CASES = [
     ("vortex2d_hll", lambda: vortex(W.VF_RANOCHA, W.SF_HLL)),
     ("vortex2d_hllc", lambda: vortex(W.VF_RANOCHA, W.SF_HLLC)),
     ("curved_air5_shock_hll", lambda: shock_hll()),
+    ("curved_air5_shock_hllc", lambda: shock_hll(W.SF_HLLC)),
+    ("curved_air5_shock_kennedy_gruber", lambda: shock_hll(W.SF_RUSANOV, W.VF_KENNEDY_GRUBER)),
+    ("curved_air5_kennedy_gruber", lambda: air5_periodic(W.VF_KENNEDY_GRUBER)),
+    ("curved_air5_pirozzoli", lambda: air5_periodic(W.VF_PIROZZOLI)),
+    ("curved_air5_central", lambda: air5_periodic(W.VF_CENTRAL)),
+    ("curved_air5_ducros_hllc", lambda: air5_periodic(W.VF_DUCROS, W.SF_HLLC)),
+    ("tgv_morinishi", lambda: tgv_euler(W.VF_MORINISHI, W.SF_RUSANOV)),
+    ("curved_morinishi", lambda: W.curved_periodic_case(n=2, N=3, volume_flux=W.VF_MORINISHI)),
+    ("curved_N4_morinishi", lambda: W.curved_periodic_case(n=2, N=4, volume_flux=W.VF_MORINISHI)),
+    ("tgv_ns_morinishi", lambda: tgv_ns(W.VF_MORINISHI, W.SF_RUSANOV)),
+    ("vortex2d_morinishi", lambda: vortex(W.VF_MORINISHI, W.SF_RUSANOV)),
 ]
 
 
