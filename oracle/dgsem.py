@@ -39,7 +39,7 @@ from .thermo import Mixture
 from .kinetics import Kinetics
 
 EQ_EULER, EQ_NS, EQ_EULER_MIX, EQ_REACT_MIX = 0, 1, 2, 3
-BC_DIRICHLET, BC_OUTFLOW, BC_SLIPWALL = 0, 1, 2
+BC_DIRICHLET, BC_OUTFLOW, BC_SLIPWALL, BC_WALL_ISOTHERMAL, BC_WALL_ADIABATIC = 0, 1, 2, 3, 4
 
 
 class Operator:
@@ -163,11 +163,17 @@ class Operator:
             return self.states(ue)
         if kind == BC_OUTFLOW:
             return s_int
-        # slip wall: mirror the momentum about the face
-        nh = n / np.sqrt(gas.dot(n, n))
         ue = u_int.copy()
         off = 5 if self.mix is not None else 1
         m = u_int[off:off + self.dim]
+        if kind in (BC_WALL_ISOTHERMAL, BC_WALL_ADIABATIC):
+            # no-slip wall: the advective flux sees the state with the whole
+            # velocity reversed (same density and energy), which carries no
+            # mass or energy through the face
+            ue[off:off + self.dim] = -m
+            return self.states(ue, T_int)
+        # slip wall: mirror the momentum about the face
+        nh = n / np.sqrt(gas.dot(n, n))
         mn = gas.dot(m, nh)
         ue[off:off + self.dim] = m - 2.0 * mn * nh
         return self.states(ue, T_int)

@@ -39,6 +39,8 @@ import numpy as np
 BC_DIRICHLET = 0   # external state is a fixed conserved state
 BC_OUTFLOW = 1     # external state equals the interior state
 BC_SLIPWALL = 2    # mirror the normal velocity
+BC_WALL_ISOTHERMAL = 3  # no-slip wall at the temperature bc_state[bc][0]
+BC_WALL_ADIABATIC = 4   # no-slip wall without heat flux
 
 EQ_EULER = 0       # perfect-gas Euler
 EQ_NS = 1          # perfect-gas Navier-Stokes (BR1 viscous terms)
@@ -714,6 +716,58 @@ def density_wave(x):
     """rho = 1 + 0.5 sin(2 pi (x + y + z)), v = (1, 0.5, 0.25), p = 1."""
     rho = 1.0 + 0.5 * np.sin(2.0 * math.pi * (x[0] + x[1] + x[2]))
     return rho, (np.ones_like(rho), 0.5 * np.ones_like(rho), 0.25 * np.ones_like(rho)), np.ones_like(rho)
+
+
+def cut_periodic(N, x, faces, direction, bc_lo, bc_hi):
+    """Turn the faces that close a periodic direction into boundary faces:
+    the element face at the low end (-direction) gets boundary ``bc_lo``,
+    the one at the high end boundary ``bc_hi``.  Returns (faces, bfaces)."""
+    dim = x.shape[0]
+    n1 = N + 1
+    nidx = np.stack(np.unravel_index(np.arange(n1 ** dim), (n1,) * dim)[::-1], 0)
+    d = direction
+    lo_node = int(np.flatnonzero(nidx[d] == 0)[0])
+    hi_node = int(np.flatnonzero(nidx[d] == N)[0])
+    keep, bf = [], []
+    for row in faces:
+        eL, fL, eR, fR = (int(v) for v in row)
+        if fL == 2 * d + 1 and abs(x[d][eL, hi_node] - x[d][eR, lo_node]) > 1e-9:
+            bf.append((eL, fL, bc_hi))
+            bf.append((eR, fR, bc_lo))
+        else:
+            keep.append(row)
+    return np.asarray(keep, np.int32).reshape(-1, 4), np.asarray(bf, np.int32).reshape(-1, 3)
+
+
+def wall_channel_case(N=3, base=4, radii=(0.3,), centre=(0.5, 0.5, 0.5), T_lo=1.2, T_hi=None, seed=9,
+                      mu=2e-3, element_order="morton", **kw):
+    """Navier-Stokes flow between no-slip walls on the 2:1 octree mesh of the
+    unit cube: y = 0 is an isothermal wall at ``T_lo``, y = 1 an isothermal
+    wall at ``T_hi`` (or an adiabatic wall when ``T_hi`` is None); x and z
+    are periodic.  The state is a perturbed shear flow that vanishes at the
+    walls: u = 0.3 sin(pi y), v and w small smooth modes, T varying between
+    the walls, density 1 (Mach about 0.3, R = 1, gamma = 1.4)."""
+    x, faces, mortars, level = octree_mesh(N, base, radii, centre, element_order)
+    faces, bfaces = cut_periodic(N, x, faces, 1, 0, 1)
+    cfg = base_cfg(3, N, EQ_NS, mu=mu, **kw)
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, 3, size=(3, 2))
+    ph = rng.uniform(0, 2 * math.pi, 3)
+    sy = np.sin(math.pi * x[1])
+    vel = (0.3 * sy + 0.05 * sy * np.cos(2 * math.pi * (k[0, 0] * x[0] + k[0, 1] * x[2]) + ph[0]),
+           0.05 * sy * np.sin(2 * math.pi * (k[1, 0] * x[0] + k[1, 1] * x[2]) + ph[1]),
+           0.05 * sy * np.cos(2 * math.pi * (k[2, 0] * x[0] + k[2, 1] * x[2]) + ph[2]))
+    T_top = T_hi if T_hi is not None else T_lo
+    T = T_lo + (T_top - T_lo) * x[1] + 0.1 * sy
+    rho = np.ones_like(T)
+    u0 = _pg_conserved(rho, vel, rho * cfg["R"] * T, cfg["gamma"])
+    kinds = np.array([BC_WALL_ISOTHERMAL, BC_WALL_ISOTHERMAL if T_hi is not None else BC_WALL_ADIABATIC],
+                     np.int32)
+    bc_state = np.zeros((2, 5))
+    bc_state[0, 0] = T_lo
+    bc_state[1, 0] = T_hi if T_hi is not None else 0.0
+    mesh = Mesh(3, N, x, faces, bfaces, mortars, kinds, bc_state, level=level)
+    return Case("wall_channel_ns", cfg, mesh, u0)
 
 
 def case_amr(N=3, base=16, radii=(0.51, 0.35), seed=5, centre=None, element_order="morton"):
