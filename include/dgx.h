@@ -85,13 +85,29 @@ extern "C" {
  * curved elements the Kennedy-Gruber, Pirozzoli and standard-DG forms are
  * built with Rusanov faces, and HLL and HLLC faces with the Ducros form (the
  * frozen sound speed in the wave-speed bounds; the species densities of an
- * HLLC star state scale like its total density).  Every other combination
- * of equation, degree, dimension and flux that the library was not built
- * with makes dgx_create return DGX_E_INVAL. */
+ * HLLC star state scale like its total density).  The 3D Navier-Stokes
+ * equations with the entropy-conservative volume flux and Rusanov faces are
+ * also built for curved elements at N = 3 and 4 and for 2:1 non-conforming
+ * affine meshes at N = 3 (viscous mortars: the gradients' interface values
+ * and the viscous fluxes are averaged on each sub-face and projected back to
+ * the large face like the advective flux); Navier-Stokes meshes may carry
+ * boundary faces of every kind.  Every other combination of equation,
+ * degree, dimension and flux that the library was not built with makes
+ * dgx_create (or dgx_set_mesh, for the mesh-dependent variants) return
+ * DGX_E_INVAL. */
 /* boundary kinds (weak, through the surface flux with an external state) */
 #define DGX_BC_DIRICHLET 0
 #define DGX_BC_OUTFLOW 1
 #define DGX_BC_SLIPWALL 2
+/* No-slip walls (Sec. Results: adiabatic and isothermal walls).  The
+ * advective flux sees the interior state with the whole velocity reversed;
+ * for DGX_EQ_NS the gradients take the wall value W* = (0, T_wall) or
+ * (0, T) and the viscous wall flux is F_v(W*, grad W).n, without heat flux
+ * at an adiabatic wall.  T_wall is bc_state[bc][0] (the rest of the row is
+ * ignored).  Other boundaries of DGX_EQ_NS take W* as the mean of the
+ * interior and the external state's (v, T) and the same flux rule. */
+#define DGX_BC_WALL_ISOTHERMAL 3
+#define DGX_BC_WALL_ADIABATIC 4
 /* shock-indicator quantity */
 #define DGX_IND_RHO_P 0
 #define DGX_IND_P 1
@@ -177,7 +193,8 @@ typedef struct dgx_mesh {
     const int32_t *mortars;   /* [nmortar][3 + 2^(dim-1)] */
     int nbc;
     const int32_t *bc_kind;   /* [nbc] DGX_BC_*           */
-    const double *bc_state;   /* [nbc][nvar] conserved external states */
+    const double *bc_state;   /* [nbc][nvar] conserved external states
+                                 (isothermal walls: T_wall in column 0) */
 } dgx_mesh;
 
 typedef struct dgx_newton_stats {

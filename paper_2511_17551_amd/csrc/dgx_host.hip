@@ -50,10 +50,21 @@ void rhs_launch_p(const RhsParams &P, int mode, int threads, size_t lds, hipStre
     hipLaunchKernelGGL((k_rhs_queue<DIM, N, EQ, VF, SF, CURV, MORT, CHF>), dim3(Q.nmort + Q.nchunks), dim3(threads),
                        lds, s, P, mode, Q);
 }
-template <int DIM, int N>
+template <int DIM, int N, bool CURV, bool OPEN>
 void grad_launch(const RhsParams &P, int blocks, int threads, hipStream_t s, double suthS, double suthT0) {
-    const size_t lds = (size_t)P.epb * GradShape<DIM, N>::SLOT * sizeof(double);
-    hipLaunchKernelGGL((k_grad<DIM, N>), dim3(blocks), dim3(threads), lds, s, P, suthS, suthT0);
+    const size_t lds = (size_t)P.epb * GradShape<DIM, N, OPEN>::SLOT * sizeof(double);
+    hipLaunchKernelGGL((k_grad<DIM, N, CURV, OPEN>), dim3(blocks), dim3(threads), lds, s, P, suthS, suthT0);
+}
+template <int DIM, int N>
+void grad_launch_any(const RhsParams &P, bool curv, bool open, int blocks, int threads, hipStream_t s, double suthS,
+                     double suthT0) {
+    if (curv) {
+        if (open) grad_launch<DIM, N, true, true>(P, blocks, threads, s, suthS, suthT0);
+        else grad_launch<DIM, N, true, false>(P, blocks, threads, s, suthS, suthT0);
+    } else {
+        if (open) grad_launch<DIM, N, false, true>(P, blocks, threads, s, suthS, suthT0);
+        else grad_launch<DIM, N, false, false>(P, blocks, threads, s, suthS, suthT0);
+    }
 }
 template <int DIM, int N, bool MIX>
 void ind_launch(const RhsParams &P, int iv, double amax, double amin, double *a, double *araw, int blocks,
@@ -113,6 +124,8 @@ const RhsEntry kRhs[] = {
     // the other volume forms and HLLC faces for the curved 5-species equations
     RHS_ENTRY(3, 4, 2, 2, 0, 1), RHS_ENTRY(3, 4, 2, 3, 0, 1), RHS_ENTRY(3, 4, 2, 4, 0, 1),
     RHS_ENTRY(3, 4, 2, 1, 3, 1),
+    // Navier-Stokes on curved elements
+    RHS_ENTRY(3, 3, 1, 0, 0, 1), RHS_ENTRY(3, 4, 1, 0, 0, 1),
     // Morinishi's form (perfect gas)
     RHS_ENTRY(3, 3, 0, 5, 0, 0), RHS_ENTRY(3, 3, 0, 5, 0, 1), RHS_ENTRY(3, 4, 0, 5, 0, 1),
     RHS_ENTRY(2, 3, 0, 5, 0, 0), RHS_ENTRY(3, 3, 1, 5, 0, 0),
@@ -122,6 +135,8 @@ const RhsEntry kRhs[] = {
     // the other volume forms with Rusanov mortar faces
     RHS_ENTRY_M(3, 3, 0, 2, 0), RHS_ENTRY_M(3, 3, 0, 3, 0), RHS_ENTRY_M(3, 3, 0, 4, 0),
     RHS_ENTRY_M(3, 3, 0, 5, 0),
+    // Navier-Stokes with viscous mortars
+    RHS_ENTRY_M(3, 3, 1, 0, 0),
     // alternative tilings: the Navier-Stokes TGV kernel in two chunks, the
     // curved 5-species kernels in one
     RHS_ENTRY_T(3, 3, 1, 0, 0, 0, 2), RHS_ENTRY_T(3, 4, 2, 1, 0, 1, 1), RHS_ENTRY_T(3, 4, 2, 1, 2, 1, 1),
@@ -180,6 +195,8 @@ struct dgx_ctx {
     int wq_nchunks[4] = {}, wq_nfree[4] = {};
     DevBuf<double> tg;
     DevBuf<double> mflux;
+    DevBuf<double> mgw;  // NS on mortars: sub-face gradient values W*_s
+    bool open = false;   // the mesh has boundary or mortar faces
     int nmortar = 0;
     double Im[2][25] = {}, Pm[2][25] = {};
     DevBuf<KinC> kin_d;
@@ -298,6 +315,7 @@ RhsParams base_params(dgx_ctx *ctx) {
     P.mort = ctx->mort.p;
     P.mflux = ctx->mflux.p;
     P.mops = ctx->mops.p;
+    P.mgw = ctx->mgw.p;
     P.gamma = ctx->cfg.gamma;
     P.R = ctx->cfg.R;
     P.mu = ctx->cfg.mu;
@@ -387,13 +405,28 @@ int enqueue_rhs(dgx_ctx *ctx, const double *u, double *out, int mode, const doub
         tape_mark(tp, fuse_T ? "k_indicator_T" : "k_indicator", s);
     }
     if (c.equation == DGX_EQ_NS) {
+        if (ctx->nmortar) {
+            RhsParams M = P;
+            M.out = ctx->mgw.p;
+            const int nsub = c.dim == 3 ? 4 : 2;
+            const int items = ctx->nmortar * nsub * ctx->nf;
+            if (c.dim == 3 && c.N == 3)
+                hipLaunchKernelGGL((k_mortar_grad<3, 3>), dim3((items + 255) / 256), dim3(256), 0, s, M, ctx->nmortar);
+            else if (c.dim == 3 && c.N == 4)
+                hipLaunchKernelGGL((k_mortar_grad<3, 4>), dim3((items + 255) / 256), dim3(256), 0, s, M, ctx->nmortar);
+            else if (c.dim == 2 && c.N == 3)
+                hipLaunchKernelGGL((k_mortar_grad<2, 3>), dim3((items + 255) / 256), dim3(256), 0, s, M, ctx->nmortar);
+            else return set_err(ctx, DGX_E_INVAL, "NS mortar gradients not built for this dim/N");
+            tape_mark(tp, "k_mortar_grad", s);
+        }
         RhsParams G = P;
         G.out = ctx->vpart.p;
         G.out2 = ctx->grad.p;
         const double sS = c.sutherland_S, sT = c.sutherland_T0;
-        if (c.dim == 3 && c.N == 3) grad_launch<3, 3>(G, blocks, th, s, sS, sT);
-        else if (c.dim == 3 && c.N == 4) grad_launch<3, 4>(G, blocks, th, s, sS, sT);
-        else if (c.dim == 2 && c.N == 3) grad_launch<2, 3>(G, blocks, th, s, sS, sT);
+        const bool cv = ctx->curved, op = ctx->open;
+        if (c.dim == 3 && c.N == 3) grad_launch_any<3, 3>(G, cv, op, blocks, th, s, sS, sT);
+        else if (c.dim == 3 && c.N == 4) grad_launch_any<3, 4>(G, cv, op, blocks, th, s, sS, sT);
+        else if (c.dim == 2 && c.N == 3) grad_launch_any<2, 3>(G, cv, op, blocks, th, s, sS, sT);
         else return set_err(ctx, DGX_E_INVAL, "NS gradients not built for this dim/N");
         tape_mark(tp, "k_grad", s);
     }
@@ -438,7 +471,8 @@ bool epb_fits(const dgx_ctx *ctx, int epb) {
         // the gradient kernel's slot (GradShape): own W and face traces, then
         // the contravariant fluxes of all directions
         const int dim = ctx->cfg.dim, nw = dim + 1, nsf = 2 * dim * ctx->nf;
-        const size_t gslot = std::max<size_t>((size_t)nw * ctx->nn + (size_t)nw * nsf, (size_t)dim * nw * ctx->nn);
+        const size_t g0 = (size_t)nw * ctx->nn + (size_t)nw * nsf, gt = (size_t)dim * nw * ctx->nn;
+        const size_t gslot = ctx->open ? g0 + gt : std::max(g0, gt);
         if ((size_t)epb * gslot * sizeof(double) > 64 * 1024) return false;
     }
     return (size_t)epb * cur_rhs(ctx)->slot * sizeof(double) <= 64 * 1024;
@@ -600,8 +634,8 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         m->nbc < 0 || (m->nbc && (!m->bc_kind || !m->bc_state)))
         return set_err(ctx, DGX_E_INVAL, "bad mesh tables");
     if (m->nmortar < 0 || (m->nmortar && !m->mortars)) return set_err(ctx, DGX_E_INVAL, "bad mortar table");
-    if (m->nmortar && ctx->cfg.equation != DGX_EQ_EULER)
-        return set_err(ctx, DGX_E_INVAL, "mortars are supported for the perfect-gas Euler equations");
+    if (m->nmortar && ctx->cfg.equation != DGX_EQ_EULER && ctx->cfg.equation != DGX_EQ_NS)
+        return set_err(ctx, DGX_E_INVAL, "mortars are supported for the perfect-gas equations");
     // connectivity (every check below runs before the context changes, so a
     // rejected mesh leaves the previous one in place)
     std::vector<int> nbr((size_t)E * 2 * dim, INT_MIN);
@@ -633,9 +667,8 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
     }
     for (size_t i = 0; i < nbr.size(); ++i)
         if (nbr[i] == INT_MIN) return set_err(ctx, DGX_E_INVAL, "element face without neighbour or boundary");
-    if (ctx->cfg.equation == DGX_EQ_NS && m->nbface) return set_err(ctx, DGX_E_INVAL, "NS supports periodic meshes only");
     for (int b = 0; b < m->nbc; ++b)
-        if (m->bc_kind[b] < 0 || m->bc_kind[b] > 2) return set_err(ctx, DGX_E_INVAL, "bad boundary kind");
+        if (m->bc_kind[b] < 0 || m->bc_kind[b] > 4) return set_err(ctx, DGX_E_INVAL, "bad boundary kind");
     // geometry
     std::vector<double> Ja((size_t)dim * dim * E * nn), Jv((size_t)E * nn);
     std::vector<double> jae(dim * dim * nn), je(nn);
@@ -658,7 +691,6 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         }
         if (dev > 1e-12 * mx) affine = false;
     }
-    if (ctx->cfg.equation == DGX_EQ_NS && !affine) return set_err(ctx, DGX_E_INVAL, "NS needs affine elements");
     if (m->nmortar && !affine) return set_err(ctx, DGX_E_INVAL, "mortars need affine elements");
     // pick the kernel variant for this geometry
     const RhsEntry *sel = nullptr;
@@ -684,6 +716,7 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
     ctx->rhs_alt = alt;
     ctx->tile = 0;
     ctx->curved = !affine;
+    ctx->open = m->nbface > 0 || m->nmortar > 0;
     ctx->nelem = E;
     ctx->nbc = m->nbc;
     int rc;
@@ -769,6 +802,9 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         if ((rc = dalloc(ctx, ctx->mops, 100))) return rc;
         HIPCHK(hipMemcpy(ctx->mops.p, ops, sizeof(ops), hipMemcpyHostToDevice));
         if ((rc = dalloc(ctx, ctx->mflux, (size_t)m->nmortar * nsub * nv * ctx->nf))) return rc;
+        if (ctx->cfg.equation == DGX_EQ_NS &&
+            (rc = dalloc(ctx, ctx->mgw, (size_t)m->nmortar * nsub * (dim + 1) * ctx->nf)))
+            return rc;
     }
     // boundary states
     if (m->nbc) {
@@ -1465,6 +1501,7 @@ void dgx_destroy(dgx_ctx *ctx) {
     ctx->bc_kind.release();
     ctx->mort.release();
     ctx->mflux.release();
+    ctx->mgw.release();
     ctx->iters.release();
     ctx->subs.release();
     ctx->tg.release();

@@ -72,6 +72,7 @@ struct RhsParams {
     const double *mflux;    // mortar sub-face fluxes [nm][2^(dim-1)][nvar][nf]
     const double *mops;     // mortars: [I, P][lower, upper half][25]: interpolation to the
                             // halves of a face edge and L2 projection back ([q][j], N+1 wide)
+    const double *mgw;      // NS on mortars: sub-face gradient values W*_s [nm][2^(dim-1)][dim+1][nf]
     double gamma, R, mu, kappa;
     int epb;                // elements per block
     int xcd;                // nonzero: XCD-contiguous workgroup numbering (k_rhs, k_grad)

@@ -7,41 +7,76 @@
 namespace dgx {
 
 // BR1 viscous terms, element-local part (Sec. Methodology, Viscous Fluxes,
-// Eqs. auxil and auxstrongf; Appendix, Transport, Eq. stress).
+// Eqs. auxil and auxstrongf; Appendix, Transport, Eq. stress; Sec. New
+// Developments, gradient and viscous-flux patching across interfaces and
+// mortars; Sec. Results, weak boundaries with the external state averaged
+// with the interior one for the viscous terms).
 //
 // Per element: gradients q = (1/J) sum_d Ja^d [D_d W + lift(W* - W)] of
-// W = (v, T = p/(rho R)) with W* = (W_own + W_nbr)/2, the nodal viscous flux
-// F_v[c] = (tau_{.c}, (tau v)_c + kappa dT/dx_c) and its contravariant form
-// Ft^d = Ja^d . F_v.  The divergence with the averaged interface flux,
-//   (1/J) [ sum_d D_d Ft^d + (Ft* - Ft_own)/w_N |_{xi_d = 1} - (Ft* - Ft_own)/w_0 |_{xi_d = -1} ],
-//   Ft* = (Ft_own + Ft_nbr) / 2,
-// is split into what this element knows (written to P.out, [dim+1][E][nn]:
-// everything except +-Ft_nbr/(2w)) and the face values Ft^d at its face nodes
-// (written to P.grad as [E][2 dim][dim+1][nf]) that its neighbours add.
-// Affine elements (Ja^d constant); on a conforming face of two affine
-// elements Ja^d of both sides is the area vector of the shared face.
-template <int DIM, int N>
+// W = (v, T = p/(rho R)), the nodal viscous flux F_v[c] = (tau_{.c},
+// (tau v)_c + kappa dT/dx_c) and its contravariant form Ft^d = Ja^d . F_v.
+// Interface values W*: (W_own + W_nbr)/2 on conforming faces; on a mortar
+// face the small side's W*_s from the mortar gradient pass, the large side
+// sum_s (P_a x P_b) W*_s; on a boundary face the mean with the external
+// state (Dirichlet: the boundary state; outflow: W* = W; slip wall: the
+// mirrored velocity), (0, T_wall) at an isothermal and (0, T) at an
+// adiabatic no-slip wall.  The divergence with the interface flux F*,
+//   (1/J) [ sum_d D_d Ft^d + (F* - Ft_own)/w_N |_{xi_d = 1} - (F* - Ft_own)/w_0 |_{xi_d = -1} ],
+// is split into what this element knows (written to P.out, [dim+1][E][nn])
+// and the face values Ft^d at its face nodes (written to P.grad as
+// [E][2 dim][dim+1][nf]): on conforming and mortar faces F* is completed
+// by the right-hand side kernel (the neighbour's half, or the mortar's
+// averaged sub-face fluxes), on boundary faces F* = F_v(W*, q).n (viscosity
+// at the temperature of W*; no heat flux at an adiabatic wall) is applied
+// here.  CURV: nodal metric terms; OPEN: the mesh has boundary or mortar
+// faces (the face values W* stay in LDS for the boundary fluxes).
+template <int DIM, int N, bool OPEN = false>
 struct GradShape {
     static constexpr int N1 = N + 1;
     static constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
     static constexpr int NF = NN / N1;
     static constexpr int NW = DIM + 1;
     static constexpr int NSF = 2 * DIM * NF;
-    // own W and the neighbours' face traces of W; later the contravariant
-    // viscous fluxes of all directions
+    // own W and the neighbours' face traces of W (or the face values W*);
+    // then the contravariant viscous fluxes of all directions, over the
+    // traces, or after them when those are still needed
     static constexpr int SLOT0 = NW * NN + NW * NSF;
-    static constexpr int SLOT = SLOT0 > DIM * NW * NN ? SLOT0 : DIM * NW * NN;
+    static constexpr int OFF_T = OPEN ? SLOT0 : 0;
+    static constexpr int SLOT = OPEN ? SLOT0 + DIM * NW * NN : (SLOT0 > DIM * NW * NN ? SLOT0 : DIM * NW * NN);
 };
+
+// Viscous flux F_v[c] (momentum, energy rows) of velocity v, gradients q,
+// viscosity mu and conductivity kappa.
+template <int DIM>
+__device__ __forceinline__ void visc_flux(const double *v, const double (*q)[DIM + 1], double mu, double kappa,
+                                          double (*Fv)[DIM + 1]) {
+    double div = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) div += q[k][k];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        double en = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double t = mu * (q[c][k] + q[k][c]);
+            if (k == c) t -= (2.0 / 3.0) * mu * div;
+            en = fma(t, v[k], en);
+            Fv[c][k] = t;
+        }
+        Fv[c][DIM] = en + kappa * q[c][DIM];
+    }
+}
 
 // suthS > 0: Sutherland's law mu(T) = mu (T/T0)^(3/2) (T0 + S)/(T + S)
 // (Eq. sutherland) at every node, the conductivity scaled alike (constant
 // Pr); suthS = 0: constant mu.
-template <int DIM, int N>
+template <int DIM, int N, bool CURV = false, bool OPEN = false>
 __global__ void __launch_bounds__(512) k_grad(RhsParams P, double suthS, double suthT0) {
-    using S = GradShape<DIM, N>;
+    using S = GradShape<DIM, N, OPEN>;
     constexpr int N1 = N + 1, NN = S::NN, NF = S::NF, NW = S::NW, NSF = S::NSF;
     constexpr int NV = DIM + 2;
     constexpr int GA = DIM * DIM + 1;
+    constexpr int NSUB = DIM == 3 ? 4 : 2;
     extern __shared__ double smem[];
     __shared__ double sD[N1 * N1];  // read with per-lane indices
     const int tid = threadIdx.x;
@@ -70,17 +105,37 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P, double suthS, double 
         const double p = (P.gamma - 1.0) * (u[1 + DIM] - 0.5 * u[0] * v2);
         W[DIM] = p * ir / P.R;
     };
+    auto transport = [&](double T, double &mu, double &kappa) {
+        mu = P.mu;
+        kappa = P.kappa;
+        if (suthS > 0.0) {
+            const double th = T / suthT0;
+            const double f = th * sqrt(th) * (suthT0 + suthS) / (T + suthS);
+            mu *= f;
+            kappa *= f;
+        }
+    };
+    // scaled normal Ja^d at node nd of element ee
+    auto normal = [&](int ee, int d, int nd, double *n) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+            n[c] = CURV ? P.geo[(size_t)(d * DIM + c) * stride + (size_t)ee * NN + nd]
+                        : P.geo[(size_t)ee * GA + d * DIM + c];
+    };
 
-    // Neighbour face traces: one item per face node of every element of the
-    // workgroup, spread over all threads; all loads are issued up front.
+    // Neighbour face traces (or, on an open mesh, the own trace at boundary
+    // faces): one item per face node of every element of the workgroup,
+    // spread over all threads; all loads are issued up front.
     constexpr int RF = (NSF + NN - 1) / NN;
     const Spread spf = spread_phase(tid, NT, P.epb * NSF, 0);
     double un[RF][NV];
-    int slot[RF];
+    int slot[RF], code[RF], item[RF];
 #pragma unroll
     for (int r = 0; r < RF; ++r) {
         const int it = r * NT + spf.t;
         slot[r] = -1;
+        code[r] = 0;
+        item[r] = 0;
 #pragma unroll
         for (int v = 0; v < NV; ++v) un[r][v] = 1.0;
         if (tid < NT && it < nloc * NSF) {
@@ -90,10 +145,19 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P, double suthS, double 
             const int q = fi - f * NF;
             const int d = f >> 1, side = f & 1;
             const int nb = P.nbr[(e0 + ei) * 2 * DIM + f];
-            const unsigned gj = (unsigned)nb * NN + line_node<N1, DIM>(d, side ? 0 : N, q);
+            code[r] = nb;
+            item[r] = it;
+            slot[r] = ei * S::SLOT + NW * NN + fi;
+            unsigned gj;
+            if (!OPEN || nb >= 0) {
+                gj = (unsigned)nb * NN + line_node<N1, DIM>(d, side ? 0 : N, q);
+            } else if (nb > kMortBase) {
+                gj = (unsigned)(e0 + ei) * NN + line_node<N1, DIM>(d, side ? N : 0, q);
+            } else {
+                continue;  // mortar face: W* from the mortar gradient pass
+            }
 #pragma unroll
             for (int v = 0; v < NV; ++v) un[r][v] = (P.u + (size_t)v * stride)[gj];
-            slot[r] = ei * S::SLOT + NW * NN + fi;
         }
     }
     double Wo[NW];
@@ -110,22 +174,101 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P, double suthS, double 
     }
 #pragma unroll
     for (int r = 0; r < RF; ++r) {
-        if (slot[r] >= 0) {
-            double Wn[NW];
+        if (slot[r] < 0) continue;
+        double Wn[NW];
+        const int nb = code[r];
+        if (!OPEN || nb >= 0) {
             prim(un[r], Wn);
+        } else {
+            const int ei = item[r] / NSF;
+            const int fi = item[r] - ei * NSF;
+            const int f = fi / NF;
+            const int q = fi - f * NF;
+            const int d = f >> 1;
+            if (nb > kMortBase) {
+                // boundary face: W* from the own trace and the boundary kind
+                const int bc = -1 - nb;
+                const int kind = P.bc_kind[bc];
+                double Wf[NW];
+                prim(un[r], Wf);
+                if (kind == 0) {
+                    double ue[NV], We[NW];
 #pragma unroll
-            for (int w = 0; w < NW; ++w) smem[slot[r] + w * NSF] = Wn[w];
+                    for (int v = 0; v < NV; ++v) ue[v] = P.bc_state[bc * NV + v];
+                    prim(ue, We);
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) Wn[w] = 0.5 * (Wf[w] + We[w]);
+                } else if (kind == 1) {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) Wn[w] = Wf[w];
+                } else if (kind == 2) {
+                    double n[DIM];
+                    normal(e0 + ei, d, line_node<N1, DIM>(d, (f & 1) ? N : 0, q), n);
+                    const double vn = dotn<DIM>(Wf, n) / dotn<DIM>(n, n);
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) Wn[c] = Wf[c] - vn * n[c];
+                    Wn[DIM] = Wf[DIM];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) Wn[c] = 0.0;
+                    Wn[DIM] = kind == 3 ? P.bc_state[bc * NV] : Wf[DIM];
+                }
+            } else {
+                const int mc = kMortBase - nb;
+                const int m = mc >> 3, role = mc & 7;
+                const double *mg = P.mgw + (size_t)m * NSUB * NW * NF;
+                if (role < NSUB) {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) Wn[w] = mg[(role * NW + w) * NF + q];
+                } else {
+                    // large side: sum_s (P_a x P_b) W*_s
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) Wn[w] = 0.0;
+                    const int qa = q % N1, qb = q / N1;
+#pragma unroll 1
+                    for (int sb = 0; sb < NSUB; ++sb) {
+                        const int a = sb & 1, bsel = sb >> 1;
+#pragma unroll 1
+                        for (int j = 0; j < NF; ++j) {
+                            const int ja = j % N1, jb = j / N1;
+                            double wt = P.mops[50 + a * 25 + qa * N1 + ja];
+                            if (DIM == 3) wt *= P.mops[50 + bsel * 25 + qb * N1 + jb];
+#pragma unroll
+                            for (int w = 0; w < NW; ++w) Wn[w] = fma(wt, mg[(sb * NW + w) * NF + j], Wn[w]);
+                        }
+                    }
+                }
+            }
         }
+#pragma unroll
+        for (int w = 0; w < NW; ++w) smem[slot[r] + w * NSF] = Wn[w];
     }
     __syncthreads();
     // with a multiple of 64 nodes per element every wave holds one element:
     // its metric terms then live in scalar registers
     const int eu = (NN % 64 == 0) ? __builtin_amdgcn_readfirstlane(e) : e;
-    const double *g = P.geo + (size_t)eu * GA;
     double Ja[DIM * DIM];
+    double iJ;
+    if constexpr (CURV) {
 #pragma unroll
-    for (int k = 0; k < DIM * DIM; ++k) Ja[k] = g[k];
-    const double iJ = 1.0 / g[DIM * DIM];
+        for (int k = 0; k < DIM * DIM; ++k) Ja[k] = P.geo[(size_t)k * stride + gi];
+        iJ = 1.0 / P.Jn[gi];
+    } else {
+        const double *g = P.geo + (size_t)eu * GA;
+#pragma unroll
+        for (int k = 0; k < DIM * DIM; ++k) Ja[k] = g[k];
+        iJ = 1.0 / g[DIM * DIM];
+    }
+    // face codes of this node's faces (open meshes)
+    int fcode[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        fcode[d] = 0;
+        if constexpr (OPEN) {
+            const int a = node_pos<N1>(node, d);
+            if (valid && (a == 0 || a == N)) fcode[d] = P.nbr[(size_t)e * 2 * DIM + 2 * d + (a == N ? 1 : 0)];
+        }
+    }
     double q[DIM][NW];
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
@@ -150,9 +293,10 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P, double suthS, double 
                 const int side = (a == N) ? 1 : 0;
                 const int fi = (2 * d + side) * NF + l;
                 const double sc = side ? 1.0 / P.B.w[N] : -1.0 / P.B.w[0];
+                const bool star = OPEN && fcode[d] < 0;  // the trace slot holds W* itself
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
-                    const double ws = 0.5 * (Wo[w] + sn[w * NSF + fi]);
+                    const double ws = star ? sn[w * NSF + fi] : 0.5 * (Wo[w] + sn[w * NSF + fi]);
                     dW[w] = fma(sc, ws - Wo[w], dW[w]);
                 }
             }
@@ -169,28 +313,9 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P, double suthS, double 
     // nodal viscous flux
     double Fv[DIM][NW];
     {
-        double mu = P.mu, kappa = P.kappa;
-        if (suthS > 0.0) {
-            const double th = Wo[DIM] / suthT0;
-            const double f = th * sqrt(th) * (suthT0 + suthS) / (Wo[DIM] + suthS);
-            mu *= f;
-            kappa *= f;
-        }
-        double div = 0.0;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) div += q[k][k];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            double en = 0.0;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                double t = mu * (q[c][k] + q[k][c]);
-                if (k == c) t -= (2.0 / 3.0) * mu * div;
-                en = fma(t, Wo[k], en);
-                Fv[c][k] = t;
-            }
-            Fv[c][DIM] = en + kappa * q[c][DIM];
-        }
+        double mu, kappa;
+        transport(Wo[DIM], mu, kappa);
+        visc_flux<DIM>(Wo, q, mu, kappa, Fv);
     }
     // divergence: volume part and the element's own half of the face terms.
     // All directions' contravariant fluxes go to LDS at once.
@@ -198,8 +323,8 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P, double suthS, double 
 #pragma unroll
     for (int k = 0; k < NW; ++k) vis[k] = 0.0;
     double *ff = P.out2;
-    double *ft = smem + el * S::SLOT;  // [DIM][NW][NN]
-    __syncthreads();  // the gradient's readers of sw and sn are done
+    double *ft = smem + el * S::SLOT + S::OFF_T;  // [DIM][NW][NN]
+    if (!OPEN) __syncthreads();  // the gradient's readers of sw and sn are done
     if (valid) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
@@ -226,13 +351,36 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P, double suthS, double 
             }
             if (a == 0 || a == N) {
                 const int side = (a == N) ? 1 : 0;
-                const double sc = side ? -0.5 / P.B.w[N] : 0.5 / P.B.w[0];
                 double *fo = ff + ((size_t)e * 2 * DIM + 2 * d + side) * NW * NF + l;
+                if (OPEN && fcode[d] < 0 && fcode[d] > kMortBase) {
+                    // boundary face: F* = F_v(W*, q).n, applied in full here
+                    const int bc = -1 - fcode[d];
+                    const int kind = P.bc_kind[bc];
+                    const int fi = (2 * d + side) * NF + l;
+                    double Wb[NW], mu, kappa, Fb[DIM][NW];
 #pragma unroll
-                for (int k = 0; k < NW; ++k) {
-                    const double Ftk = ft[(d * NW + k) * NN + node];
-                    vis[k] = fma(sc, Ftk, vis[k]);
-                    fo[k * NF] = Ftk;
+                    for (int w = 0; w < NW; ++w) Wb[w] = sn[w * NSF + fi];
+                    transport(Wb[DIM], mu, kappa);
+                    visc_flux<DIM>(Wb, q, mu, kind == 4 ? 0.0 : kappa, Fb);
+                    const double sc = side ? 1.0 / P.B.w[N] : -1.0 / P.B.w[0];
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) {
+                        double Fs = 0.0;
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) Fs = fma(Ja[d * DIM + c], Fb[c][k], Fs);
+                        if (kind == 4 && k == DIM) Fs = 0.0;
+                        const double Ftk = ft[(d * NW + k) * NN + node];
+                        vis[k] = fma(sc, Fs - Ftk, vis[k]);
+                        fo[k * NF] = Ftk;
+                    }
+                } else {
+                    const double sc = side ? -0.5 / P.B.w[N] : 0.5 / P.B.w[0];
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) {
+                        const double Ftk = ft[(d * NW + k) * NN + node];
+                        vis[k] = fma(sc, Ftk, vis[k]);
+                        fo[k * NF] = Ftk;
+                    }
                 }
             }
         }
@@ -241,6 +389,63 @@ __global__ void __launch_bounds__(512) k_grad(RhsParams P, double suthS, double 
 #pragma unroll
         for (int k = 0; k < NW; ++k) (P.out + (size_t)k * stride)[gi] = vis[k] * iJ;
     }
+}
+
+// Mortar gradient pass (BR1 on 2:1 meshes): one thread per small-face node
+// of every mortar sub-face.  The large element's conserved trace is
+// interpolated to the node (I_a x I_b), W* = (W_small + W(I u_large))/2 is
+// written to P.out as [nm][2^(dim-1)][dim+1][nf] for the gradient kernel
+// (the small side reads it, the large side projects it back).  Perfect gas,
+// affine elements.
+template <int DIM, int N>
+__global__ void __launch_bounds__(256) k_mortar_grad(RhsParams P, int nmort) {
+    constexpr int N1 = N + 1;
+    constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+    constexpr int NF = NN / N1;
+    constexpr int NV = DIM + 2, NW = DIM + 1;
+    constexpr int NSUB = DIM == 3 ? 4 : 2;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nmort * NSUB * NF) return;
+    const int m = t / (NSUB * NF);
+    const int r = t - m * NSUB * NF;
+    const int s = r / NF, q = r - s * NF;
+    const int *row = P.mort + (size_t)m * (3 + NSUB);
+    const int eL = row[0], fL = row[1], es = row[2 + s], fS = row[2 + NSUB];
+    const int d = fL >> 1, sideL = fL & 1;
+    const size_t stride = (size_t)P.nelem * NN;
+    const int a = s & 1, bsel = s >> 1;
+    const int qa = q % N1, qb = q / N1;
+    double ui[NV], us[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ui[v] = 0.0;
+    for (int j = 0; j < NF; ++j) {
+        const int ja = j % N1, jb = j / N1;
+        double w = P.mops[a * 25 + qa * N1 + ja];
+        if (DIM == 3) w *= P.mops[bsel * 25 + qb * N1 + jb];
+        const size_t gj = (size_t)eL * NN + line_node<N1, DIM>(d, sideL ? N : 0, j);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ui[v] = fma(w, P.u[v * stride + gj], ui[v]);
+    }
+    const size_t gs = (size_t)es * NN + line_node<N1, DIM>(d, (fS & 1) ? N : 0, q);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) us[v] = P.u[v * stride + gs];
+    double Wi[NW], Ws[NW];
+    auto prim = [&](const double *u, double *W) {
+        const double ir = rcp(u[0]);
+        double v2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            W[c] = u[1 + c] * ir;
+            v2 = fma(W[c], W[c], v2);
+        }
+        const double p = (P.gamma - 1.0) * (u[1 + DIM] - 0.5 * u[0] * v2);
+        W[DIM] = p * ir / P.R;
+    };
+    prim(ui, Wi);
+    prim(us, Ws);
+    double *o = P.out + (size_t)m * NSUB * NW * NF;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) o[(s * NW + w) * NF + q] = 0.5 * (Ws[w] + Wi[w]);
 }
 
 // The per-node T(e) solve (Appendix, Thermodynamics) of a conserved state

@@ -447,6 +447,13 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
 #pragma unroll
                         for (int v = 0; v < NV; ++v) F[v] *= (double)NSUB;
                     }
+                    if constexpr (EQ == 1) {
+                        // the mortar flux carries the whole viscous F*; the
+                        // gradient kernel took the own half of Ft off already
+                        const double *fo = P.grad + ((size_t)(e0 + ei) * 2 * DIM + f) * NW * NF + q;
+#pragma unroll
+                        for (int k = 0; k < NW; ++k) F[1 + k] += 0.5 * fo[k * NF];
+                    }
 #pragma unroll
                     for (int v = 0; v < NV; ++v) ebuf[v * NSFC + jb] = F[v];
                     continue;
@@ -467,6 +474,11 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                         make_state<DIM, MIX>(ue, MIX ? P.bc_T[bc] : 0.0, gamma, P.M, ext);
                     } else if (kind == 1) {
                         ext = own;
+                    } else if (kind >= 3) {
+                        // no-slip wall: the whole velocity reversed
+                        ext = own;
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) ext.v[c] = -own.v[c];
                     } else {
                         // slip wall: mirror the velocity about the face (T and p unchanged)
                         const double inn = rcp(dotn<DIM>(nrm, nrm));
@@ -493,7 +505,8 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                     // BR1 interface flux {{F_v}}: the element's own half is in
                     // the gradient kernel's output, the neighbour's half enters
                     // with the inviscid flux (F* - F_v/2 on the momentum and
-                    // energy rows; periodic meshes only, so nb >= 0 here).
+                    // energy rows; at boundary faces ftr is 0: the gradient
+                    // kernel applied the whole viscous boundary flux).
 #pragma unroll
                     for (int k = 0; k < NW; ++k) F[1 + k] -= 0.5 * ftr[g][k];
                 }
@@ -764,7 +777,7 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
 // large element's face trace is interpolated to the node with I_a x I_b, the
 // Riemann flux uses the small element's trace and scaled normal and is
 // oriented along +xi_d (lower-xi state first).  Perfect gas, affine elements.
-template <int DIM, int N, int SF>
+template <int DIM, int N, int SF, int EQ = 0>
 __device__ __forceinline__ void mortar_item(const RhsParams &P, int m, int t) {
     constexpr int N1 = N + 1;
     constexpr int NN = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
@@ -819,6 +832,28 @@ __device__ __forceinline__ void mortar_item(const RhsParams &P, int m, int t) {
         if (sideL) ranocha_state<DIM, false>(A, B, nrm, P.gamma, F);
         else ranocha_state<DIM, false>(B, A, nrm, P.gamma, F);
     }
+    if constexpr (EQ == 1) {
+        // BR1 viscous sub-face flux, the mean of the small side's Ft and the
+        // large side's interpolated Ft scaled to the small normal (affine:
+        // the large element's Ja^d is 2^(dim-1) times the small one's); the
+        // stored flux is the advective minus the viscous one
+        constexpr int NW = DIM + 1;
+        const double *fs = P.grad + ((size_t)es * 2 * DIM + fS) * NW * NF + q;
+        const double *fl = P.grad + ((size_t)eL * 2 * DIM + fL) * NW * NF;
+        double fi[NW];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) fi[k] = 0.0;
+#pragma unroll 4
+        for (int j = 0; j < NF; ++j) {
+            const int ja = j % N1, jb = j / N1;
+            double w = P.mops[a * 25 + qa * N1 + ja];
+            if (DIM == 3) w *= P.mops[bsel * 25 + qb * N1 + jb];
+#pragma unroll
+            for (int k = 0; k < NW; ++k) fi[k] = fma(w, fl[k * NF + j], fi[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < NW; ++k) F[1 + k] -= 0.5 * (fs[k * NF] + fi[k] * (1.0 / NSUB));
+    }
     double *out = const_cast<double *>(P.mflux) + (size_t)m * NSUB * NV * NF;
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[(s * NV + v) * NF + q] = F[v];
@@ -864,7 +899,7 @@ __global__ void __launch_bounds__(512) k_rhs_queue(RhsParams P, int mode, WorkQ 
     __shared__ int s_item;
     if (Q.next == nullptr) {
         if constexpr (MORT) {
-            if ((int)blockIdx.x < Q.nmort) mortar_item<DIM, N, SF>(P, blockIdx.x, threadIdx.x);
+            if ((int)blockIdx.x < Q.nmort) mortar_item<DIM, N, SF, EQ>(P, blockIdx.x, threadIdx.x);
         }
         return;
     }
@@ -882,7 +917,7 @@ __global__ void __launch_bounds__(512) k_rhs_queue(RhsParams P, int mode, WorkQ 
     const int item = s_item < Q.nmort ? s_item : s_item + Q.nfree;  // queue position -> item
     if (item >= Q.nmort + Q.nchunks) return;
     if (MORT && item < Q.nmort) {
-        if constexpr (MORT) mortar_item<DIM, N, SF>(P, item, threadIdx.x);
+        if constexpr (MORT) mortar_item<DIM, N, SF, EQ>(P, item, threadIdx.x);
         __syncthreads();
         if (threadIdx.x == 0) {
             __threadfence();  // the sub-face fluxes before the count

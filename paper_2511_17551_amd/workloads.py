@@ -744,9 +744,11 @@ def wall_channel_case(N=3, base=4, radii=(0.3,), centre=(0.5, 0.5, 0.5), T_lo=1.
     """Navier-Stokes flow between no-slip walls on the 2:1 octree mesh of the
     unit cube: y = 0 is an isothermal wall at ``T_lo``, y = 1 an isothermal
     wall at ``T_hi`` (or an adiabatic wall when ``T_hi`` is None); x and z
-    are periodic.  The state is a perturbed shear flow that vanishes at the
-    walls: u = 0.3 sin(pi y), v and w small smooth modes, T varying between
-    the walls, density 1 (Mach about 0.3, R = 1, gamma = 1.4)."""
+    are periodic.  The state is a perturbed shear flow, u = 0.3 sin(pi y)
+    plus small smooth modes in all three components, and T between the wall
+    temperatures with a bump and a mode, density 1 (Mach about 0.3, R = 1,
+    gamma = 1.4); the modes do not vanish at the walls, so the walls act on
+    the velocity and temperature traces."""
     x, faces, mortars, level = octree_mesh(N, base, radii, centre, element_order)
     faces, bfaces = cut_periodic(N, x, faces, 1, 0, 1)
     cfg = base_cfg(3, N, EQ_NS, mu=mu, **kw)
@@ -754,11 +756,10 @@ def wall_channel_case(N=3, base=4, radii=(0.3,), centre=(0.5, 0.5, 0.5), T_lo=1.
     k = rng.integers(1, 3, size=(3, 2))
     ph = rng.uniform(0, 2 * math.pi, 3)
     sy = np.sin(math.pi * x[1])
-    vel = (0.3 * sy + 0.05 * sy * np.cos(2 * math.pi * (k[0, 0] * x[0] + k[0, 1] * x[2]) + ph[0]),
-           0.05 * sy * np.sin(2 * math.pi * (k[1, 0] * x[0] + k[1, 1] * x[2]) + ph[1]),
-           0.05 * sy * np.cos(2 * math.pi * (k[2, 0] * x[0] + k[2, 1] * x[2]) + ph[2]))
+    mode = [np.cos(2 * math.pi * (k[i, 0] * x[0] + k[i, 1] * x[2]) + ph[i]) for i in range(3)]
+    vel = (0.3 * sy + 0.05 * mode[0], 0.05 * mode[1], 0.05 * mode[2])
     T_top = T_hi if T_hi is not None else T_lo
-    T = T_lo + (T_top - T_lo) * x[1] + 0.1 * sy
+    T = T_lo + (T_top - T_lo) * x[1] + 0.1 * sy + 0.05 * mode[1] * mode[2]
     rho = np.ones_like(T)
     u0 = _pg_conserved(rho, vel, rho * cfg["R"] * T, cfg["gamma"])
     kinds = np.array([BC_WALL_ISOTHERMAL, BC_WALL_ISOTHERMAL if T_hi is not None else BC_WALL_ADIABATIC],

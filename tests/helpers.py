@@ -73,3 +73,15 @@ def oracle_dt(op, u, cfl):
         Ja = op.Ja[d]
         lam = lam + np.abs(gas.dot(s["v"], Ja)) + s["c"] * np.sqrt(gas.dot(Ja, Ja))
     return float(cfl * 2.0 / ((op.N + 1) * np.max(lam / op.J)))
+
+
+def oracle_dt_ns(op, u, cfl=0.5, vcfl=0.2):
+    """Time step of the Navier-Stokes runs: the smaller of the advective
+    rule of oracle_dt and the diffusive bound vcfl dx^2 / nu_eff, with the
+    node spacing dx = 4 J_min^(1/3) / (N+1)^2 and nu_eff = mu gamma / (Pr
+    rho_min)."""
+    s = op.states(u)
+    cfg = op.cfg
+    dx = 4.0 * float(op.J.min()) ** (1.0 / 3.0) / (op.N + 1) ** 2
+    nu = cfg["mu"] * cfg["gamma"] / (cfg["Pr"] * float(s["rho"].min()))
+    return min(oracle_dt(op, u, cfl), vcfl * dx * dx / nu)
