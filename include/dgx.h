@@ -220,6 +220,62 @@ typedef struct dgx_ctx dgx_ctx;  /* opaque */
  * (dim not 2/3, N not 3/4, EC flux with a mixture, NS with a mixture). */
 int dgx_create(const dgx_config *cfg, dgx_ctx **out);
 
+/* ---- Dynamic AMR on a periodic octree (Sec. New Developments: elements
+ * split into 8, 2:1 mortars; Sec. Results, AMR Taylor-Green case: an
+ * indicator on a derived variable and three levels with two thresholds). */
+#define DGX_AMR_LOEHNER 0            /* Loehner's weighted second-derivative estimate */
+#define DGX_AMR_HENNEMANN_GASSNER 1  /* modal-energy coefficient in [0, 1]           */
+#define DGX_AMR_VAR_DENSITY 0
+#define DGX_AMR_VAR_PRESSURE 1
+#define DGX_AMR_VAR_DENSITY_PRESSURE 2
+#define DGX_AMR_VAR_VELOCITY 3       /* velocity magnitude */
+
+typedef struct dgx_amr_controller {
+    int base_level, med_level, max_level;  /* 0 <= base <= med <= max <= 12 */
+    double med_threshold, max_threshold;   /* med_threshold <= max_threshold */
+} dgx_amr_controller;
+
+/* Mesh of an octree over the periodic unit cube: base^3 level-0 cells,
+ * leaves[nleaf][4] = (level, i, j, k) with 0 <= i, j, k < base 2^level
+ * (base <= 64, level <= 12).  The leaves must fill the cube without overlap
+ * and be 2:1 balanced (face neighbours differ by at most one level), else
+ * DGX_E_INVAL.  The library orders the elements along the Z-order curve of
+ * the leaves' lower corners (dgx_get_octree returns that order) and builds
+ * affine elements, conforming faces and mortars.  3D perfect-gas equations
+ * only.  Synchronous; replaces the current mesh like dgx_set_mesh. */
+int dgx_set_octree(dgx_ctx *ctx, int base, int nleaf, const int32_t *leaves);
+
+/* The octree leaves in element order, leaves_out[nmax][4]; returns the
+ * element count (leaves_out may be NULL to query it), DGX_E_STATE without an
+ * octree mesh, DGX_E_INVAL when nmax is too small. */
+int dgx_get_octree(const dgx_ctx *ctx, int32_t *leaves_out, int nmax);
+
+/* Refinement indicator per element into device ind[nelem] from the device
+ * state u.  DGX_AMR_LOEHNER: the variable is sampled at N+1 equidistant
+ * points per direction and the element takes the largest
+ * |f+ - 2 f0 + f-| / (|f+ - f0| + |f0 - f-| + 0.2 (|f+| + 2|f0| + |f-|))
+ * over the interior samples of all lines.  DGX_AMR_HENNEMANN_GASSNER: the
+ * blending coefficient of the shock indicator (modal energy of the highest
+ * modes) with alpha_max = 1, alpha_min = 1e-4.  Enqueued on stream. */
+int dgx_amr_indicator(dgx_ctx *ctx, const double *u, int kind, int variable, double *ind, void *stream);
+
+/* One adaptation pass from host indicator values ind[nelem]: target level
+ * max_level where ind >= max_threshold, med_level where ind >=
+ * med_threshold, else base_level; leaves below their target are split once,
+ * leaves are split further until 2:1 balanced, families of 8 unsplit
+ * siblings whose targets are all below their level merge unless the parent
+ * would face a leaf two levels finer.  Writes the new element count and
+ * keeps the plan until dgx_amr_apply.  Host only. */
+int dgx_amr_plan(dgx_ctx *ctx, const double *ind, const dgx_amr_controller *c, int *nelem_new);
+
+/* Applies the planned adaptation: u_new (device [nvar][nelem_new][nn], not
+ * aliasing u_old) receives the state of the new elements (kept elements
+ * copied, split ones interpolated from their parent, merged ones the L2
+ * projection of their children), then the context switches to the new
+ * mesh.  Synchronises stream.  On an error after the transfer the context is
+ * left without a mesh (DGX_E_STATE until one is set). */
+int dgx_amr_apply(dgx_ctx *ctx, const double *u_old, double *u_new, void *stream);
+
 /* Upload a mesh: the library computes its own LGL operators, metric terms
  * (2D cross form, 3D conservative curl form), Jacobians, face normals and
  * subcell normals (Eqs. mapp, mapped_equation, jacobian).  May be called

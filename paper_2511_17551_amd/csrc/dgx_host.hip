@@ -14,6 +14,8 @@
 
 #include "../../include/dgx.h"
 #include "host_geometry.h"
+#include "host_octree.h"
+#include "k_amr.h"
 #include "k_aux.h"
 #include "k_chem.h"
 #include "surrogate.h"
@@ -196,6 +198,13 @@ struct dgx_ctx {
     DevBuf<double> tg;
     DevBuf<double> mflux;
     DevBuf<double> mgw;  // NS on mortars: sub-face gradient values W*_s
+    // dynamic AMR: the octree leaves in element order, a pending adaptation
+    // (new leaves and transfer rows), the transfer and sampling operators
+    int oct_base = 0;
+    std::vector<OctLeaf> oct, oct_new;
+    std::vector<int32_t> oct_tab;
+    DevBuf<int> amr_tab;
+    DevBuf<double> amr_ops, amr_eq;
     bool open = false;   // the mesh has boundary or mortar faces
     int nmortar = 0;
     double Im[2][25] = {}, Pm[2][25] = {};
@@ -867,6 +876,11 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         }
     }
     ctx->mesh_ok = true;
+    // a mesh from the caller replaces any octree (dgx_set_octree and
+    // dgx_amr_apply record theirs after this call)
+    ctx->oct.clear();
+    ctx->oct_new.clear();
+    ctx->oct_tab.clear();
     return DGX_OK;
 }
 
@@ -1477,6 +1491,175 @@ int dgx_thermo_noalloc(dgx_ctx *ctx, const double *u, int64_t nstates, double *T
     return DGX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// dynamic AMR on a periodic octree
+}  // extern "C"
+
+namespace {
+
+// Builds the mesh of the leaves (element order as given) on the periodic
+// unit cube and uploads it.
+int oct_upload(dgx_ctx *ctx, int base, const std::vector<OctLeaf> &order) {
+    OctTree t;
+    t.base = base;
+    for (auto &c : order) t.leaves.insert(oct_key(c));
+    std::vector<int32_t> faces, morts;
+    oct_tables(t, order, faces, morts);
+    const int n1 = ctx->N1, nn = ctx->nn, E = (int)order.size();
+    std::vector<double> x((size_t)3 * E * nn);
+    for (int e = 0; e < E; ++e) {
+        const OctLeaf &c = order[e];
+        const double h = 1.0 / (double)(base << c.L);
+        const int cc[3] = {c.i, c.j, c.k};
+        for (int n = 0; n < nn; ++n) {
+            const int idx[3] = {n % n1, (n / n1) % n1, n / (n1 * n1)};
+            for (int d = 0; d < 3; ++d)
+                x[((size_t)d * E + e) * nn + n] = h * (cc[d] + 0.5 * (ctx->basis.x[idx[d]] + 1.0));
+        }
+    }
+    dgx_mesh m{};
+    m.nelem = E;
+    m.x = x.data();
+    m.nface = (int)(faces.size() / 4);
+    m.faces = faces.data();
+    m.nmortar = (int)(morts.size() / 7);
+    m.mortars = morts.data();
+    return dgx_set_mesh(ctx, &m);
+}
+
+// operators of the transfer (half-interval interpolation and L2 projection)
+// and of Loehner's equidistant sampling
+int amr_ops_upload(dgx_ctx *ctx) {
+    const int n1 = ctx->N1;
+    double ops[100];
+    std::memcpy(ops, ctx->Im, sizeof(ctx->Im));
+    std::memcpy(ops + 50, ctx->Pm, sizeof(ctx->Pm));
+    std::vector<double> eq((size_t)n1 * n1);
+    for (int a = 0; a < n1; ++a) {
+        const double y = -1.0 + 2.0 * a / (n1 - 1);
+        for (int j = 0; j < n1; ++j) {
+            double l = 1.0;
+            for (int m = 0; m < n1; ++m)
+                if (m != j) l *= (y - ctx->basis.x[m]) / (ctx->basis.x[j] - ctx->basis.x[m]);
+            eq[(size_t)a * n1 + j] = l;
+        }
+    }
+    int rc;
+    if ((rc = dalloc(ctx, ctx->amr_ops, 100))) return rc;
+    if ((rc = dalloc(ctx, ctx->amr_eq, eq.size()))) return rc;
+    HIPCHK(hipMemcpy(ctx->amr_ops.p, ops, sizeof(ops), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->amr_eq.p, eq.data(), eq.size() * sizeof(double), hipMemcpyHostToDevice));
+    return DGX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgx_set_octree(dgx_ctx *ctx, int base, int nleaf, const int32_t *leaves) {
+    if (!ctx || nleaf <= 0 || !leaves) return set_err(ctx, DGX_E_INVAL, "bad octree");
+    if (ctx->cfg.dim != 3 || ctx->cfg.equation >= DGX_EQ_EULER_MIX)
+        return set_err(ctx, DGX_E_INVAL, "octree meshes are built for the 3D perfect-gas equations");
+    std::vector<OctLeaf> v(nleaf);
+    for (int e = 0; e < nleaf; ++e) v[e] = {leaves[4 * e], leaves[4 * e + 1], leaves[4 * e + 2], leaves[4 * e + 3]};
+    OctTree t;
+    const std::string err = oct_check(base, v, t);
+    if (!err.empty()) return set_err(ctx, DGX_E_INVAL, err);
+    morton_sort(v);
+    int rc;
+    if ((rc = amr_ops_upload(ctx))) return rc;
+    if ((rc = oct_upload(ctx, base, v))) return rc;
+    ctx->oct_base = base;
+    ctx->oct = v;
+    ctx->oct_new.clear();
+    ctx->oct_tab.clear();
+    return DGX_OK;
+}
+
+int dgx_get_octree(const dgx_ctx *ctx, int32_t *leaves_out, int nmax) {
+    if (!ctx || ctx->oct.empty()) return DGX_E_STATE;
+    const int n = (int)ctx->oct.size();
+    if (leaves_out) {
+        if (nmax < n) return DGX_E_INVAL;
+        for (int e = 0; e < n; ++e) {
+            leaves_out[4 * e] = ctx->oct[e].L;
+            leaves_out[4 * e + 1] = ctx->oct[e].i;
+            leaves_out[4 * e + 2] = ctx->oct[e].j;
+            leaves_out[4 * e + 3] = ctx->oct[e].k;
+        }
+    }
+    return n;
+}
+
+int dgx_amr_indicator(dgx_ctx *ctx, const double *u, int kind, int variable, double *ind, void *stream) {
+    if (!ctx || !u || !ind) return set_err(ctx, DGX_E_INVAL, "null argument");
+    if (ctx->oct.empty() || !ctx->mesh_ok) return set_err(ctx, DGX_E_STATE, "no octree mesh");
+    if (kind < 0 || kind > 1 || variable < 0 || variable > 3) return set_err(ctx, DGX_E_INVAL, "bad indicator");
+    hipStream_t s = (hipStream_t)stream;
+    const int E = ctx->nelem;
+    if (ctx->cfg.N == 3)
+        hipLaunchKernelGGL(k_amr_indicator<3>, dim3(E), dim3(64), 0, s, u, E, ctx->cfg.gamma, kind, variable,
+                           ctx->amr_eq.p, ctx->bc, ind);
+    else
+        hipLaunchKernelGGL(k_amr_indicator<4>, dim3(E), dim3(128), 0, s, u, E, ctx->cfg.gamma, kind, variable,
+                           ctx->amr_eq.p, ctx->bc, ind);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_err(ctx, DGX_E_DEVICE, std::string("indicator launch: ") + hipGetErrorString(e));
+    return DGX_OK;
+}
+
+int dgx_amr_plan(dgx_ctx *ctx, const double *ind, const dgx_amr_controller *c, int *nelem_new) {
+    if (!ctx || !ind || !c || !nelem_new) return set_err(ctx, DGX_E_INVAL, "null argument");
+    if (ctx->oct.empty()) return set_err(ctx, DGX_E_STATE, "no octree mesh");
+    if (c->base_level < 0 || c->med_level < c->base_level || c->max_level < c->med_level ||
+        c->max_level > kOctMaxLevel || !(c->med_threshold <= c->max_threshold))
+        return set_err(ctx, DGX_E_INVAL, "bad AMR controller");
+    const int E = (int)ctx->oct.size();
+    std::vector<int> target(E);
+    for (int e = 0; e < E; ++e) {
+        if (!std::isfinite(ind[e])) return set_err(ctx, DGX_E_INVAL, "non-finite indicator value");
+        target[e] = ind[e] >= c->max_threshold ? c->max_level
+                    : ind[e] >= c->med_threshold ? c->med_level
+                                                 : c->base_level;
+    }
+    std::vector<OctLeaf> nv;
+    std::vector<int32_t> tab;
+    const std::string err = oct_adapt(ctx->oct_base, ctx->oct, target.data(), nv, tab);
+    if (!err.empty()) return set_err(ctx, DGX_E_INVAL, err);
+    ctx->oct_new = std::move(nv);
+    ctx->oct_tab = std::move(tab);
+    *nelem_new = (int)ctx->oct_new.size();
+    return DGX_OK;
+}
+
+int dgx_amr_apply(dgx_ctx *ctx, const double *u_old, double *u_new, void *stream) {
+    if (!ctx || !u_old || !u_new) return set_err(ctx, DGX_E_INVAL, "null argument");
+    if (ctx->oct_new.empty()) return set_err(ctx, DGX_E_STATE, "no pending adaptation");
+    if (u_old == u_new) return set_err(ctx, DGX_E_INVAL, "u_old and u_new must not alias");
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if ((rc = dalloc(ctx, ctx->amr_tab, ctx->oct_tab.size()))) return rc;
+    HIPCHK(hipMemcpy(ctx->amr_tab.p, ctx->oct_tab.data(), ctx->oct_tab.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice));
+    const int nold = (int)ctx->oct.size(), nnew = (int)ctx->oct_new.size();
+    const int items = nnew * ctx->nn;
+    if (ctx->cfg.N == 3)
+        hipLaunchKernelGGL(k_amr_transfer<3>, dim3((items + 255) / 256), dim3(256), 0, s, u_old, nold, u_new, nnew,
+                           ctx->nvar, ctx->amr_tab.p, ctx->amr_ops.p);
+    else
+        hipLaunchKernelGGL(k_amr_transfer<4>, dim3((items + 255) / 256), dim3(256), 0, s, u_old, nold, u_new, nnew,
+                           ctx->nvar, ctx->amr_tab.p, ctx->amr_ops.p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_err(ctx, DGX_E_DEVICE, std::string("transfer launch: ") + hipGetErrorString(e));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<OctLeaf> nv = std::move(ctx->oct_new);
+    ctx->oct_new.clear();
+    ctx->oct_tab.clear();
+    if ((rc = oct_upload(ctx, ctx->oct_base, nv))) return rc;
+    ctx->oct = std::move(nv);
+    return DGX_OK;
+}
+
 const char *dgx_last_error(const dgx_ctx *ctx) {
     if (!ctx) return "null context";
     return ctx->err_fixed ? ctx->err_fixed : ctx->err.c_str();
@@ -1502,6 +1685,9 @@ void dgx_destroy(dgx_ctx *ctx) {
     ctx->mort.release();
     ctx->mflux.release();
     ctx->mgw.release();
+    ctx->amr_tab.release();
+    ctx->amr_ops.release();
+    ctx->amr_eq.release();
     ctx->iters.release();
     ctx->subs.release();
     ctx->tg.release();

@@ -62,6 +62,11 @@ class dgx_mesh(C.Structure):
                 ("bc_kind", C.POINTER(C.c_int32)), ("bc_state", C.POINTER(C.c_double))]
 
 
+class dgx_amr_controller(C.Structure):
+    _fields_ = [("base_level", C.c_int), ("med_level", C.c_int), ("max_level", C.c_int),
+                ("med_threshold", C.c_double), ("max_threshold", C.c_double)]
+
+
 class dgx_newton_stats(C.Structure):
     _fields_ = [("nodes", C.c_int64), ("iters_total", C.c_int64), ("iters_max", C.c_int32),
                 ("iters_wave_max_mean", C.c_double), ("nonconverged", C.c_int64), ("first_bad", C.c_int64),
@@ -100,6 +105,11 @@ def _load():
         "dgx_autotune": ([vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), vp], C.c_int),
         "dgx_set_launch": ([vp, C.c_int, C.c_int], C.c_int),
         "dgx_get_launch": ([vp, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "dgx_set_octree": ([vp, C.c_int, C.c_int, C.POINTER(C.c_int32)], C.c_int),
+        "dgx_get_octree": ([vp, C.POINTER(C.c_int32), C.c_int], C.c_int),
+        "dgx_amr_indicator": ([vp, vp, C.c_int, C.c_int, vp, vp], C.c_int),
+        "dgx_amr_plan": ([vp, C.POINTER(C.c_double), C.POINTER(dgx_amr_controller), C.POINTER(C.c_int)], C.c_int),
+        "dgx_amr_apply": ([vp, vp, vp, vp], C.c_int),
         "dgx_last_error": ([vp], C.c_char_p),
         "dgx_destroy": ([vp], None),
     }
@@ -116,7 +126,8 @@ EXPORTED = ("dgx_create", "dgx_set_mesh", "dgx_rhs", "dgx_ssprk3_step", "dgx_lim
             "dgx_chem_step",
             "dgx_last_alpha", "dgx_surrogate_set", "dgx_surrogate_get", "dgx_surrogate_train",
             "dgx_surrogate_predict", "dgx_surrogate_init", "dgx_surrogate_grad", "dgx_check", "dgx_species_energy", "dgx_mixture_energy", "dgx_kernel_times", "dgx_autotune",
-            "dgx_set_launch", "dgx_get_launch", "dgx_last_error", "dgx_destroy")
+            "dgx_set_launch", "dgx_get_launch", "dgx_set_octree", "dgx_get_octree", "dgx_amr_indicator",
+            "dgx_amr_plan", "dgx_amr_apply", "dgx_last_error", "dgx_destroy")
 
 
 def _ptr(a, ctype=C.c_double):
@@ -217,6 +228,39 @@ def dgx_set_mesh(ctx, mesh):
     m.nmortar, m.mortars = mort.shape[0], _ptr(mort, C.c_int32)
     m.nbc, m.bc_kind, m.bc_state = kind.shape[0], _ptr(kind, C.c_int32), _ptr(state)
     _raise(ctx, lib.dgx_set_mesh(ctx, C.byref(m)))
+
+
+def dgx_set_octree(ctx, base, leaves):
+    lv = np.ascontiguousarray(leaves, np.int32).reshape(-1, 4)
+    _raise(ctx, lib.dgx_set_octree(ctx, int(base), lv.shape[0], _ptr(lv, C.c_int32)))
+
+
+def dgx_get_octree(ctx):
+    n = lib.dgx_get_octree(ctx, None, 0)
+    if n < 0:
+        _raise(ctx, n)
+    out = np.empty((n, 4), np.int32)
+    rc = lib.dgx_get_octree(ctx, _ptr(out, C.c_int32), n)
+    if rc < 0:
+        _raise(ctx, rc)
+    return out
+
+
+def dgx_amr_indicator(ctx, u, kind, variable, ind, stream=None):
+    _raise(ctx, lib.dgx_amr_indicator(ctx, _dev(u), int(kind), int(variable), _dev(ind), _stream(stream)))
+
+
+def dgx_amr_plan(ctx, ind, controller):
+    ind = np.ascontiguousarray(ind, np.float64)
+    c = dgx_amr_controller(*[int(controller[k]) for k in ("base_level", "med_level", "max_level")],
+                           float(controller["med_threshold"]), float(controller["max_threshold"]))
+    n = C.c_int()
+    _raise(ctx, lib.dgx_amr_plan(ctx, _ptr(ind), C.byref(c), C.byref(n)))
+    return n.value
+
+
+def dgx_amr_apply(ctx, u_old, u_new, stream=None):
+    _raise(ctx, lib.dgx_amr_apply(ctx, _dev(u_old), _dev(u_new), _stream(stream)))
 
 
 def dgx_rhs(ctx, u, t, du, stream=None):
@@ -436,6 +480,30 @@ class Solver:
 
     def check(self):
         dgx_check(self.ctx)
+
+    # dynamic AMR (octree meshes)
+    def set_octree(self, base, leaves):
+        """Replace the mesh by the octree's; returns the leaves in element order."""
+        dgx_set_octree(self.ctx, base, leaves)
+        return self.octree()
+
+    def octree(self):
+        return dgx_get_octree(self.ctx)
+
+    def amr_indicator(self, u, kind, variable):
+        import torch
+        ind = torch.empty(u.shape[1], dtype=torch.float64, device=u.device)
+        dgx_amr_indicator(self.ctx, u, kind, variable, ind)
+        return ind
+
+    def amr_adapt(self, u, ind, controller):
+        """One adaptation pass from host indicator values; returns the state
+        on the new mesh (a new tensor)."""
+        import torch
+        n = dgx_amr_plan(self.ctx, ind, controller)
+        out = torch.empty((u.shape[0], n, u.shape[2]), dtype=u.dtype, device=u.device)
+        dgx_amr_apply(self.ctx, u, out)
+        return out
 
     def close(self):
         if self.ctx:

@@ -712,6 +712,16 @@ def octree_mesh(N, base=16, radii=(0.51, 0.35), centre=(0.5, 0.5, 0.5), element_
     return x, np.asarray(faces, np.int32).reshape(-1, 4), np.asarray(mortars, np.int32).reshape(-1, 7), level
 
 
+def blob_state(x, centre=(0.4, 0.55, 0.45), width=0.1, amp=0.8, vel=(1.0, 0.5, 0.25), gamma=1.4):
+    """A Gaussian density pulse on the periodic unit cube carried by a uniform
+    flow at uniform pressure: rho = 1 + amp exp(-|x - centre|^2 / width^2)
+    (periodic distance), p = 1."""
+    d = (np.moveaxis(x, 0, -1) - np.asarray(centre) + 0.5) % 1.0 - 0.5
+    rho = 1.0 + amp * np.exp(-(d * d).sum(-1) / width ** 2)
+    v = tuple(np.full_like(rho, c) for c in vel)
+    return _pg_conserved(rho, v, np.ones_like(rho), gamma)
+
+
 def density_wave(x):
     """rho = 1 + 0.5 sin(2 pi (x + y + z)), v = (1, 0.5, 0.25), p = 1."""
     rho = 1.0 + 0.5 * np.sin(2.0 * math.pi * (x[0] + x[1] + x[2]))
