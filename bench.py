@@ -15,6 +15,7 @@ one JSON line (see the keys below).  The oracle (NumPy) is timed on the same
 import argparse
 import hashlib
 import json
+import math
 
 import numpy as np
 import os
@@ -511,7 +512,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--repeats", type=int, default=5,
-                    help="timed runs of --steps steps each; the median is reported")
+                    help="timed runs of --steps steps each (at least this many, more when --steps is "
+                         "small: enough that all repeats together last about 0.5 s, at most 50); the "
+                         "median is reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the mixture legs (curved N=4 shock, reacting cylinder)")
     ap.add_argument("--no-thermo", action="store_true", help="skip the surrogate vs plain T(e) leg")
@@ -567,11 +570,19 @@ def main():
     solver.ssprk3(u, dt, max(args.warmup, 1))
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    # `repeats` timed runs of exactly `steps` steps each (200 steps take
-    # ~0.11 s), each bracketed by device synchronisation; the median run is
-    # the headline
+    # timed runs of exactly `steps` steps each (200 steps take ~0.11 s),
+    # each bracketed by device synchronisation; the median run is the
+    # headline
     reps_ms, walls = [], []
-    for _ in range(max(1, args.repeats)):
+    # number of repeats: at least --repeats, and enough that the repeats
+    # together last about 0.5 s (a 20-step repeat lasts ~11 ms), estimated
+    # from one untimed repeat
+    t0 = time.perf_counter()
+    solver.ssprk3(u, dt, args.steps)
+    torch.cuda.synchronize()
+    est = time.perf_counter() - t0
+    nrep = min(50, max(args.repeats, int(math.ceil(0.5 / max(est, 1e-6)))))
+    for _ in range(max(1, nrep)):
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()

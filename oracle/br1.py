@@ -34,7 +34,9 @@ Readings:
   W* = (0, T_wall) (isothermal, T_wall = bc_state[bc][0]) or (0, T)
   (adiabatic).  The viscous boundary flux is F_v(W*, Q).n with the
   interior gradient Q (viscosity at the temperature of W*); at an
-  adiabatic wall its energy row is zero (no heat flux, no work).
+  adiabatic wall its energy row is zero (no heat flux, no work).  At a
+  slip wall this rule keeps the interior shear stress; no closed form pins
+  it (parity unpinned there).
 * Mortars: the large side's conserved trace is interpolated to each
   sub-face (the operators of oracle.mortar); there W* = (W_small +
   W(I_s u_large))/2, and the large side takes W*_L = sum_s (P_a x P_b) W*_s.

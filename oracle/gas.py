@@ -159,7 +159,9 @@ def morinishi(sL, sR, n):
     the average of the momenta, {{rho v}}.n; momentum that flux times {{v}}
     plus {{p}} n; energy that flux times the internal energy {{p/((gamma-1)
     rho)}} plus the kinetic energy of the two velocities v_L.v_R/2, plus the
-    pressure work {{p v}}.n."""
+    pressure work {{p v}}.n.  Parity unpinned beyond consistency, symmetry,
+    kinetic-energy preservation and the mass row: the kinetic term of the
+    energy row (v_L.v_R/2 rather than, say, {{|v|^2}}/2) is a reading."""
     g = sL["gamma"]
     mL, mR = sL["rho"] * sL["v"], sR["rho"] * sR["v"]
     f_rho = dot(0.5 * (mL + mR), n)
