@@ -72,7 +72,8 @@ class Operator:
         return self.mix.state(u, self.dim, T)
 
     # volume and surface flux choices (the library's DGX_VF_* / DGX_SF_*
-    # numbering); "kg" / "pirozzoli" / "morinishi" as a surface flux serve the oracle's
+    # numbering; for mixtures the entropy-conservative choice 0 / 1 is
+    # gas.ec_mixture); "kg" / "pirozzoli" / "morinishi" as a surface flux serve the oracle's
     # own kinetic-energy checks
     VOLUME = {0: gas.ranocha, 1: gas.ducros, 2: gas.kennedy_gruber, 3: gas.pirozzoli, 4: gas.central,
               5: gas.morinishi}
@@ -80,9 +81,13 @@ class Operator:
                "pirozzoli": gas.pirozzoli, "morinishi": gas.morinishi}
 
     def volume_flux(self, sL, sR, n):
+        if self.mix is not None and self.cfg["volume_flux"] == 0:
+            return gas.ec_mixture(sL, sR, n, self.mix)
         return self.VOLUME[self.cfg["volume_flux"]](sL, sR, n)
 
     def surface_flux(self, sL, sR, n):
+        if self.mix is not None and self.cfg["surface_flux"] == 1:
+            return gas.ec_mixture(sL, sR, n, self.mix)
         return self.SURFACE[self.cfg["surface_flux"]](sL, sR, n)
 
     # ------------------------------------------------------------------

@@ -234,6 +234,90 @@ def hllc(sL, sR, n):
     return F * nn
 
 
+def sinhc(z):
+    """sinh(z)/z with its series near 0."""
+    z = np.asarray(z, dtype=float) if np.ndim(z) == 0 else z
+    small = np.abs(z) < 1e-3
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        big = np.sinh(z) / z
+    z2 = z * z
+    return np.where(small, 1.0 + z2 / 6.0 * (1.0 + z2 / 20.0), big)
+
+
+def ec_mixture(sL, sR, n, mix):
+    """Entropy-conservative two-point flux for the RRHO mixture, built from
+    Tadmor's condition (Sec. Methodology, Advective Fluxes) with the mixture
+    entropy -sum rho_s s_s and the entropy variables w_s = (h_s - T s_s -
+    |v|^2/2)/T, w_m = v/T, w_E = -1/T; beta = 1/T.  Reading (the paper
+    derives such fluxes but prints none): species mass fluxes
+    F_s = rho_s^ln {{v}}.n (logarithmic means of the species densities);
+    momentum F_rho {{v}} + p~ n with F_rho = sum_s F_s and
+    p~ = {{sum_s rho_s R_s}} / {{beta}}; energy
+    sum_s e^_s F_s + F_rho (|{{v}}|^2 - {{|v|^2}}/2) + p~ {{v}}.n, where e^_s
+    is the divided difference [[e_s beta - sigma_s]]/[[beta]] of the species'
+    energy and thermal entropy sigma_s(T): for e_s = e0_s + c_s T +
+    R_s theta_s/(exp(theta_s beta) - 1) it is
+    e0_s + c_s / beta^ln + R_s [[ln(1 - exp(-theta_s beta))]]/[[beta]], the
+    last term evaluated as R_s theta_s exp(-theta_s {{beta}})
+    sinhc(theta_s [[beta]]/2) / ln-mean(1 - exp(-theta_s beta)), which tends
+    to e_s(T) as the states meet."""
+    ns = mix.ns
+    bL, bR = 1.0 / sL["T"], 1.0 / sR["T"]
+    bbar = 0.5 * (bL + bR)
+    dB = bR - bL
+    vbar = 0.5 * (sL["v"] + sR["v"])
+    vn = dot(vbar, n)
+    blog = ln_mean(bL, bR)
+    Rs = mix.Rs
+    rows = []
+    F = []
+    for k in range(ns):
+        F.append(ln_mean(sL["rs"][k], sR["rs"][k]) * vn)
+    f_rho = sum(F)
+    rR = lambda st: sum(st["rs"][k] * Rs[k] for k in range(ns))
+    pt = 0.5 * (rR(sL) + rR(sR)) / bbar
+    rows = list(F)
+    for c in range(vbar.shape[0]):
+        rows.append(f_rho * vbar[c] + pt * n[c])
+    energy = f_rho * (dot(vbar, vbar) - 0.25 * (dot(sL["v"], sL["v"]) + dot(sR["v"], sR["v"]))) + pt * vn
+    for k in range(ns):
+        c_k = (2.5 if mix.mol[k] else 1.5) * Rs[k]
+        eh = mix.e0[k] + c_k / blog
+        if mix.mol[k]:
+            th = mix.th[k]
+            yL, yR = -np.expm1(-th * bL), -np.expm1(-th * bR)
+            eh = eh + Rs[k] * th * np.exp(-th * bbar) * sinhc(0.5 * th * dB) / ln_mean(yL, yR)
+        energy = energy + eh * F[k]
+    rows.append(energy)
+    return np.stack(rows, 0)
+
+
+def mixture_entropy_variables(s, mix):
+    """w = dU/du for U = -sum_s rho_s s_s, s_s = c_s ln T + R_s [x/(e^x - 1)
+    - ln(1 - e^-x)] (molecules, x = theta_s/T) - R_s ln rho_s (the additive
+    constants cancel in every jump), h_s = e_s + R_s T."""
+    T = s["T"]
+    e = mix.e_species(T)
+    v2 = dot(s["v"], s["v"])
+    rows = []
+    for k in range(mix.ns):
+        c_k = (2.5 if mix.mol[k] else 1.5) * mix.Rs[k]
+        sk = c_k * np.log(T) - mix.Rs[k] * np.log(s["rs"][k])
+        if mix.mol[k]:
+            x = mix.th[k] / T
+            sk = sk + mix.Rs[k] * (x / np.expm1(x) - np.log(-np.expm1(-x)))
+        rows.append((e[k] + mix.Rs[k] * T - T * sk - 0.5 * v2) / T)
+    for c in range(s["v"].shape[0]):
+        rows.append(s["v"][c] / T)
+    rows.append(-1.0 / T)
+    return np.stack(rows, 0)
+
+
+def mixture_entropy_potential(s, mix, n):
+    """psi = sum_s rho_s R_s v.n (= p v.n / T)."""
+    return sum(s["rs"][k] * mix.Rs[k] for k in range(mix.ns)) * dot(s["v"], n)
+
+
 def entropy_variables(s):
     """w = dU/du for U = -rho s/(gamma-1), s = ln p - gamma ln rho."""
     g = s["gamma"]
