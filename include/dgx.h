@@ -58,7 +58,8 @@ extern "C" {
 #define DGX_EQ_REACT_MIX 3  /* 5-species air, RRHO energies, Arrhenius sources */
 
 /* two-point volume fluxes (Eq. fluxdiffcons) */
-#define DGX_VF_RANOCHA 0    /* entropy-conservative (perfect gas only) */
+#define DGX_VF_RANOCHA 0    /* entropy-conservative: Ranocha's (perfect gas),
+                               the RRHO mixture flux below (mixtures) */
 #define DGX_VF_DUCROS 1     /* Ducros split form                       */
 #define DGX_VF_KENNEDY_GRUBER 2  /* Kennedy-Gruber split form          */
 #define DGX_VF_PIROZZOLI 3  /* Pirozzoli split form                    */
@@ -66,7 +67,7 @@ extern "C" {
 #define DGX_VF_MORINISHI 5  /* Morinishi split form (perfect gas only) */
 /* surface fluxes (Eqs. riemann_problem1-3) */
 #define DGX_SF_RUSANOV 0    /* local Lax-Friedrichs                     */
-#define DGX_SF_RANOCHA 1    /* EC flux at faces (entropy checks, perfect gas) */
+#define DGX_SF_RANOCHA 1    /* the EC flux at faces (entropy checks)    */
 #define DGX_SF_HLL 2        /* HLL, Davis wave-speed bounds             */
 #define DGX_SF_HLLC 3       /* HLLC, Toro's contact speed               */
 /* The split forms listed in the Methodology section as interchangeable
@@ -85,7 +86,14 @@ extern "C" {
  * curved elements the Kennedy-Gruber, Pirozzoli and standard-DG forms are
  * built with Rusanov faces, and HLL and HLLC faces with the Ducros form (the
  * frozen sound speed in the wave-speed bounds; the species densities of an
- * HLLC star state scale like its total density).  The 3D Navier-Stokes
+ * HLLC star state scale like its total density).  The entropy-conservative
+ * mixture flux (Tadmor's condition with the mixture entropy; beta = 1/T):
+ * species rho_s^ln {{v}}.n, momentum F_rho {{v}} + p~ n with
+ * p~ = {{sum rho_s R_s}}/{{beta}}, energy sum_s e^_s F_s + F_rho (|{{v}}|^2
+ * - {{|v|^2}}/2) + p~ {{v}}.n, e^_s = e0_s + c_s/beta^ln + R_s theta_s
+ * exp(-theta_s {{beta}}) sinhc(theta_s [[beta]]/2) / ln-mean(1 -
+ * exp(-theta_s beta)) (molecules), is built for the curved 5-species
+ * kernels at N = 4 with Rusanov or EC faces.  The 3D Navier-Stokes
  * equations with the entropy-conservative volume flux and Rusanov faces are
  * also built for curved elements at N = 3 and 4 and for 2:1 non-conforming
  * affine meshes at N = 3 (viscous mortars: the gradients' interface values

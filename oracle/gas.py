@@ -272,7 +272,10 @@ def ec_mixture(sL, sR, n, mix):
     rows = []
     F = []
     for k in range(ns):
-        F.append(ln_mean(sL["rs"][k], sR["rs"][k]) * vn)
+        a, b = sL["rs"][k], sR["rs"][k]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            m = np.where((a == 0.0) | (b == 0.0), 0.0, ln_mean(a, b))   # the limit at a zero density
+        F.append(m * vn)
     f_rho = sum(F)
     rR = lambda st: sum(st["rs"][k] * Rs[k] for k in range(ns))
     pt = 0.5 * (rR(sL) + rR(sR)) / bbar

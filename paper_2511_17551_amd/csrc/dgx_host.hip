@@ -126,6 +126,8 @@ const RhsEntry kRhs[] = {
     // the other volume forms and HLLC faces for the curved 5-species equations
     RHS_ENTRY(3, 4, 2, 2, 0, 1), RHS_ENTRY(3, 4, 2, 3, 0, 1), RHS_ENTRY(3, 4, 2, 4, 0, 1),
     RHS_ENTRY(3, 4, 2, 1, 3, 1),
+    // the entropy-conservative mixture flux (volume; also at the faces)
+    RHS_ENTRY(3, 4, 2, 0, 0, 1), RHS_ENTRY(3, 4, 2, 0, 1, 1),
     // Navier-Stokes on curved elements
     RHS_ENTRY(3, 3, 1, 0, 0, 1), RHS_ENTRY(3, 4, 1, 0, 0, 1),
     // Morinishi's form (perfect gas)
@@ -536,8 +538,7 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
         return DGX_E_INVAL;
     const bool mix = cfg->equation >= DGX_EQ_EULER_MIX;
     if (mix && (!cfg->species || cfg->species->nspecies != 5)) return DGX_E_INVAL;
-    if (mix && (cfg->volume_flux == DGX_VF_RANOCHA || cfg->volume_flux == DGX_VF_MORINISHI)) return DGX_E_INVAL;
-    if (mix && cfg->surface_flux == DGX_SF_RANOCHA) return DGX_E_INVAL;
+    if (mix && cfg->volume_flux == DGX_VF_MORINISHI) return DGX_E_INVAL;
     if (cfg->equation == DGX_EQ_REACT_MIX && !cfg->reactions) return DGX_E_INVAL;
     if (mix && cfg->reactions) {
         const dgx_reactions *r = cfg->reactions;

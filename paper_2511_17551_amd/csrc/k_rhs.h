@@ -127,7 +127,7 @@ struct RhsShape {
     static constexpr bool MIX = EQ >= 2;
     static constexpr int NV = (MIX ? kNS : 1) + DIM + 1;
     static constexpr int NW = DIM + 1;  // viscous flux components (momentum, energy)
-    static constexpr bool EC = VF == 0;
+    static constexpr bool EC = VF == 0 && !MIX;  // perfect-gas EC flux from staged (rho, v, p, beta)
     // primitives: rho, v, p, rhoE [, c (mixture)] [, beta (EC)]
     static constexpr int NQ = DIM + 3 + (MIX ? 1 : 0) + (EC ? 1 : 0);
     static constexpr int SU = MIX ? kNS * NN : 0;  // species densities
@@ -497,6 +497,9 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                 } else if constexpr (SF == 3) {
                     if (side) hllc<DIM, MIX>(own, ext, nrm, F);
                     else hllc<DIM, MIX>(ext, own, nrm, F);
+                } else if constexpr (MIX) {
+                    if (side) ec_mixture_state<DIM>(own, ext, nrm, P.M, F);
+                    else ec_mixture_state<DIM>(ext, own, nrm, P.M, F);
                 } else {
                     if (side) ranocha_state<DIM, MIX>(own, ext, nrm, gamma, F);
                     else ranocha_state<DIM, MIX>(ext, own, nrm, gamma, F);
@@ -648,7 +651,9 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                         St<DIM, MIX> A, B;
                         lds_state<DIM, MIX>(esu, esq, NN, na, gamma, A);
                         lds_state<DIM, MIX>(esu, esq, NN, nb, gamma, B);
-                        if constexpr (VF == 1) {
+                        if constexpr (VF == 0) {
+                            ec_mixture_state<DIM>(A, B, nbar, P.M, F);
+                        } else if constexpr (VF == 1) {
                             ducros_state<DIM, MIX>(A, B, nbar, F);
                         } else if constexpr (VF == 4) {
                             central_state<DIM, MIX>(A, B, nbar, F);

@@ -418,6 +418,55 @@ __device__ __forceinline__ void split_form_state(const St<DIM, MIX> &L, const St
     }
 }
 
+// sinh(z)/z, with its series near 0
+__device__ __forceinline__ double sinhc(double z) {
+    const double z2 = z * z;
+    if (fabs(z) < 1e-3) return fma(z2 * (1.0 / 6.0), fma(z2, 1.0 / 20.0, 1.0), 1.0);
+    return sinh(z) / z;
+}
+
+// Entropy-conservative flux of the RRHO mixture (Tadmor's condition with
+// the mixture entropy -sum rho_s s_s; beta = 1/T = sum rho_s R_s / p):
+// species fluxes rho_s^ln {{v}}.n (0 where a density is 0, the limit),
+// momentum F_rho {{v}} + p~ n with p~ = {{sum rho_s R_s}}/{{beta}}, energy
+// sum_s e^_s F_s + F_rho (|{{v}}|^2 - {{|v|^2}}/2) + p~ {{v}}.n, with the
+// energy means e^_s = e0_s + c_s / beta^ln (c_s = 3/2 R_s, 5/2 R_s for
+// molecules) + R_s theta_s exp(-theta_s {{beta}}) sinhc(theta_s [[beta]]/2)
+// / ln-mean(1 - exp(-theta_s beta)) for molecules.
+template <int DIM>
+__device__ __forceinline__ void ec_mixture_state(const St<DIM, true> &L, const St<DIM, true> &R, const double *n,
+                                                 const MixC &M, double *F) {
+    const double rRL = mix_rR(M, L.rs), rRR = mix_rR(M, R.rs);
+    const double bL = rRL / L.p, bR = rRR / R.p;
+    const double bbar = 0.5 * (bL + bR), dB = bR - bL;
+    const double iblog = inv_ln_mean(bL, bR);
+    double vb[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) vb[c] = 0.5 * (L.v[c] + R.v[c]);
+    const double vn = dotn<DIM>(vb, n);
+    const double pt = 0.5 * (rRL + rRR) / bbar;
+    double frho = 0.0, en = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNS; ++k) {
+        const double a = L.rs[k], b = R.rs[k];
+        const double m = (a == b) ? a : (a == 0.0 || b == 0.0) ? 0.0 : ln_mean(a, b);
+        const double fk = m * vn;
+        F[k] = fk;
+        frho += fk;
+        double eh = fma(M.mol[k] ? 2.5 * M.Rs[k] : 1.5 * M.Rs[k], iblog, M.e0[k]);
+        if (M.mol[k]) {
+            const double th = M.thv[k];
+            const double yL = -expm1(-th * bL), yR = -expm1(-th * bR);
+            eh += M.Rs[k] * th * exp(-th * bbar) * sinhc(0.5 * th * dB) / ln_mean(yL, yR);
+        }
+        en = fma(eh, fk, en);
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) F[kNS + c] = fma(frho, vb[c], pt * n[c]);
+    const double k2 = dotn<DIM>(vb, vb) - 0.25 * (dotn<DIM>(L.v, L.v) + dotn<DIM>(R.v, R.v));
+    F[kNS + DIM] = en + frho * k2 + pt * vn;
+}
+
 // Ducros split-form flux: {{rho_s}} {{v}}.n, {{m}} {{v}}.n + {{p}} n, ({{rhoE}} + {{p}}) {{v}}.n
 template <int DIM, bool MIX>
 __device__ __forceinline__ void ducros_state(const St<DIM, MIX> &L, const St<DIM, MIX> &R,
