@@ -149,11 +149,12 @@ ORDER_NAMES = {0: "round_robin", 1: "xcd_contiguous", 2: "work_list",
                4: "round_robin+alt_tiling", 5: "xcd_contiguous+alt_tiling", 6: "work_list+alt_tiling"}
 
 
-def recorded_traffic(workload, order):
+def recorded_traffic(workload, order, epb=None):
     """HBM bytes per k_rhs launch (FETCH_SIZE + WRITE_SIZE per dispatch, each
     divided by its copy-kernel calibration factor) of this workload under this
-    workgroup numbering, from the committed counter summary; None when no
-    record matches or it was taken on other kernel sources."""
+    workgroup numbering and elements per workgroup, from the committed
+    counter summary; None when no record matches or it was taken on other
+    kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
@@ -161,7 +162,8 @@ def recorded_traffic(workload, order):
     sha = kernel_source_hash()
     for rec in recs:
         if rec.get("workload") == workload and rec.get("order") == ORDER_NAMES[order] \
-                and rec.get("source_sha1") == sha:
+                and rec.get("source_sha1") == sha \
+                and (epb is None or rec.get("elements_per_workgroup") == epb):
             return float(rec["traffic_bytes_per_launch"])
     return None
 
@@ -367,7 +369,7 @@ def c3_leg(torch, W, dgx, reps=20, order=-1):
                 workgroup_order=ORDER_NAMES[used_order], shocked_elements=shocked, kernel_ms={k: round(v, 5) for k, v in kt.items()},
                 roofline=dict(bound="hbm", kernel="k_rhs", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                               unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), bytes_per_launch=rb,
-                              traffic=recorded_traffic("curved24_N4_air5_mach3_shock", used_order)))
+                              traffic=recorded_traffic("curved24_N4_air5_mach3_shock", used_order, epb)))
 
 
 def euler_bytes_per_launch(nelem, nn, nvar):
@@ -606,7 +608,7 @@ def main():
     gb = grad_bytes_per_launch(nelem, nn, nvar, 3, 4)
     achieved = rb / (k_rhs_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic("tgv3d_ns_32cube_N3", order),
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic("tgv3d_ns_32cube_N3", order, epb),
                 kernel="k_rhs", kernel_ms=round(k_rhs_ms, 5), bytes_per_launch=rb,
                 other_kernels={k: round(v, 5) for k, v in kt.items() if k != "k_rhs"},
                 k_grad_GBs=round(gb / (kt.get("k_grad", float("nan")) * 1e-3) / 1e9, 1))

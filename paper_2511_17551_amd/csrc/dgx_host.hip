@@ -475,6 +475,13 @@ std::string tune_key(const dgx_ctx *ctx) {
            "," + std::to_string(ctx->nelem) + "," + std::to_string(ctx->nmortar > 0);
 }
 
+// default elements per workgroup: about 256 threads within 64 KB of LDS
+int default_epb(int nn, int slot) {
+    int epb = std::max(1, 256 / nn);
+    while (epb > 1 && (size_t)epb * slot * sizeof(double) > 64 * 1024) --epb;
+    return epb;
+}
+
 bool epb_fits(const dgx_ctx *ctx, int epb) {
     if (epb < 1 || epb > 8 || (epb & (epb - 1)) || !ctx->rhs) return false;
     if (threads_for(ctx->nn, epb) > 512) return false;
@@ -856,8 +863,7 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
     }
     // default elements per block: about 256 threads, LDS <= 64 KB; a cached
     // autotuner choice for this configuration wins
-    int epb = std::max(1, 256 / nn);
-    while (epb > 1 && (size_t)epb * sel->slot * sizeof(double) > 64 * 1024) --epb;
+    const int epb = default_epb(nn, sel->slot);
     ctx->epb = epb;
     // XCD-contiguous numbering by default while the state fits well inside
     // the 256 MB Infinity Cache
@@ -1295,6 +1301,10 @@ int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *
     // elements per workgroup
     int best_epb[6] = {saved, saved, saved, saved, saved, saved};
     double best_ms[6] = {1e300, 1e300, 1e300, 1e300, 1e300, 1e300};
+    // the default elements per workgroup, kept within a launch form unless
+    // another count is faster by more than 2% (as for the numbering below)
+    const int def_epb = default_epb(ctx->nn, cur_rhs(ctx)->slot);
+    double def_ms[6] = {1e300, 1e300, 1e300, 1e300, 1e300, 1e300};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1319,6 +1329,7 @@ int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *
             (void)hipEventElapsedTime(&ms, e0, e1);
             const double avg = ms / (3.0 * reps);  // per right-hand side
             if (ms_out && (ms_out[i] < 0.0 || avg < ms_out[i])) ms_out[i] = avg;
+            if (cand[i] == def_epb) def_ms[xm + 3 * tl] = avg;
             if (avg < best_ms[xm + 3 * tl]) {
                 best_ms[xm + 3 * tl] = avg;
                 best_epb[xm + 3 * tl] = cand[i];
@@ -1327,6 +1338,11 @@ int dgx_autotune(dgx_ctx *ctx, const double *u, int reps, int *epb_out, double *
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    for (int k = 0; k < 6; ++k)
+        if (def_ms[k] < 1e300 && !(best_ms[k] < 0.98 * def_ms[k])) {
+            best_ms[k] = def_ms[k];
+            best_epb[k] = def_epb;
+        }
     // the default (numbering from the state size, default tiling) unless
     // another is faster by more than 2%
     int bi = def_xcd;
