@@ -419,6 +419,144 @@ def flux_leg(torch, W, dgx, reps=20):
                 variants=out)
 
 
+def _rhs_rate(torch, dgx, case, reps=10, tune_reps=3):
+    """Autotuned back-to-back right-hand sides of a case: (GDOF-RHS/s,
+    ms per RHS, per-kernel ms, elements per workgroup)."""
+    s = dgx.Solver(case)
+    u = torch.from_numpy(case.u0).to("cuda")
+    du = torch.empty_like(u)
+    epb, _ = dgx.dgx_autotune(s.ctx, u, reps=tune_reps)
+    for _ in range(2):
+        dgx.dgx_rhs(s.ctx, u, 0.0, du)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        dgx.dgx_rhs(s.ctx, u, 0.0, du)
+    e1.record()
+    torch.cuda.synchronize()
+    s.check()
+    ms = e0.elapsed_time(e1) / reps
+    kt = dgx.dgx_kernel_times(s.ctx, u, reps=5)
+    s.close()
+    return round(case.u0.size / (ms * 1e-3) / 1e9, 3), round(ms, 5), {k: round(v, 5) for k, v in kt.items()}, epb
+
+
+def mixture_flux_leg(torch, W, dgx):
+    """The curved 24^3 N = 4 5-species shock with every volume / surface flux
+    built for the mixture: right-hand-side throughput and the k_rhs roofline
+    fraction (the c3 leg's algorithmic bytes)."""
+    probe = W.case_c4(lambda rs, T: 0 * T, lambda rs, T: 1 + 0 * T, nr=4, nth=8)
+    pctx = dgx.dgx_create(probe.cfg, probe.species, probe.reactions)
+    energy, cv = dgx.mixture_energy_fns(pctx)
+    base = W.case_c3(energy, cv)
+    dgx.dgx_destroy(pctx)
+    nvar, nelem, nn = base.u0.shape
+    rb = c3_bytes_per_launch(nelem, nn, nvar, 3)
+    out = {}
+    for name, vf, sf in (("kennedy_gruber_rusanov", W.VF_KENNEDY_GRUBER, W.SF_RUSANOV),
+                         ("pirozzoli_rusanov", W.VF_PIROZZOLI, W.SF_RUSANOV),
+                         ("central_rusanov", W.VF_CENTRAL, W.SF_RUSANOV),
+                         ("entropy_conservative_rusanov", W.VF_RANOCHA, W.SF_RUSANOV),
+                         ("ducros_hll", W.VF_DUCROS, W.SF_HLL),
+                         ("ducros_hllc", W.VF_DUCROS, W.SF_HLLC)):
+        c = W.Case(base.name, dict(base.cfg, volume_flux=vf, surface_flux=sf), base.mesh, base.u0,
+                   species=base.species)
+        v, ms, kt, epb = _rhs_rate(torch, dgx, c)
+        out[name] = dict(value=v, unit="GDOF-RHS/s", ms_per_rhs=ms, kernel_ms=kt, elements_per_workgroup=epb,
+                         roofline_frac=round(rb / (kt["k_rhs"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    return dict(workload="curved24_N4_air5_mach3_shock_rhs", bytes_per_launch=rb, variants=out)
+
+
+def ns_leg(torch, W, dgx):
+    """Navier-Stokes beyond the periodic affine TGV: the curved periodic 24^3
+    mesh at N = 3 and 4, and the wall channel on the 2:1 octree mesh (16^3
+    base, one level inside r = 0.3, isothermal walls, viscous mortars).
+    Right-hand-side throughput; for the curved kernels the k_rhs roofline
+    fraction on per node u 5 + u0 5 + out 5 + local viscous part 4 +
+    nodal metric terms 10 doubles."""
+    out = {}
+    for name, make in (("curved_periodic_24cube_N3", lambda: W.curved_periodic_case(n=24, N=3, eq=W.EQ_NS, mu=1e-3)),
+                       ("curved_periodic_24cube_N4", lambda: W.curved_periodic_case(n=24, N=4, eq=W.EQ_NS, mu=1e-3)),
+                       ("wall_channel_octree16", lambda: W.wall_channel_case(N=3, base=16, radii=(0.3,), T_hi=1.6,
+                                                                             mu=1e-3))):
+        c = make()
+        nvar, nelem, nn = c.u0.shape
+        v, ms, kt, epb = _rhs_rate(torch, dgx, c)
+        rec = dict(value=v, unit="GDOF-RHS/s", ms_per_rhs=ms, kernel_ms=kt, elements=nelem,
+                   mortars=int(len(c.mesh.mortars)), boundary_faces=int(len(c.mesh.bfaces)), elements_per_workgroup=epb)
+        if name.startswith("curved"):
+            rb = nelem * nn * 29 * 8
+            rec["roofline_frac"] = round(rb / (kt["k_rhs"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        out[name] = rec
+    return out
+
+
+def amr_leg(torch, W, dgx, cycles=3, steps=10):
+    """Dynamic AMR: a Gaussian density pulse (width 0.1) carried across the
+    periodic unit cube on an octree of 16^3 level-0 cells, levels 0-2
+    (Loehner's estimate of the density, thresholds 0.01 / 0.03: at this
+    resolution the pulse's estimate peaks near 0.045).  Per cycle: the indicator (GPU), the
+    plan (host), the transfer and mesh upload, then `steps` SSPRK3 steps;
+    the right-hand-side throughput on the final mesh."""
+    import time as _t
+    base = 16
+    leaves = np.array([(0, i, j, k) for k in range(base) for j in range(base) for i in range(base)], np.int32)
+    c0 = W.case_amr(base=4, radii=(0.4,), centre=(0.5, 0.5, 0.5))
+    s = dgx.Solver(c0)
+    order = s.set_octree(base, leaves)
+    N = 3
+    xi = W._mesh_nodes(N)
+
+    def coords(order):
+        n1 = N + 1
+        node = np.arange(n1 ** 3)
+        idx = [node % n1, (node // n1) % n1, node // (n1 * n1)]
+        x = np.empty((3, len(order), n1 ** 3))
+        for e, (L, i, j, k) in enumerate(order):
+            h = 1.0 / (base * 2 ** L)
+            for d, cc in enumerate((i, j, k)):
+                x[d, e] = h * (cc + 0.5 * (xi[idx[d]] + 1.0))
+        return x
+    u = torch.from_numpy(W.blob_state(coords(order))).to("cuda")
+    ctrl = dict(base_level=0, med_level=1, max_level=2, med_threshold=0.01, max_threshold=0.03)
+    recs = []
+    for cyc in range(cycles):
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        ind = s.amr_indicator(u, 0, 0)
+        torch.cuda.synchronize()
+        t1 = _t.perf_counter()
+        ind_h = ind.cpu().numpy()
+        n_new = dgx.dgx_amr_plan(s.ctx, ind_h, ctrl)
+        t2 = _t.perf_counter()
+        un = torch.empty((u.shape[0], n_new, u.shape[2]), dtype=u.dtype, device=u.device)
+        dgx.dgx_amr_apply(s.ctx, u, un)
+        torch.cuda.synchronize()
+        t3 = _t.perf_counter()
+        u = un
+        dt = dgx.dgx_max_dt(s.ctx, u, 0.5)
+        s.ssprk3(u, dt, steps)
+        torch.cuda.synchronize()
+        s.check()
+        lv = np.bincount(s.octree()[:, 0], minlength=3)
+        recs.append(dict(elements=int(n_new), levels=[int(v) for v in lv], indicator_ms=round((t1 - t0) * 1e3, 3),
+                         plan_ms=round((t2 - t1) * 1e3, 3), transfer_and_mesh_ms=round((t3 - t2) * 1e3, 3)))
+    du = torch.empty_like(u)
+    e0, e1 = _events(torch)
+    for _ in range(2):
+        dgx.dgx_rhs(s.ctx, u, 0.0, du)
+    e0.record()
+    for _ in range(10):
+        dgx.dgx_rhs(s.ctx, u, 0.0, du)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    s.close()
+    return dict(workload="octree16_blob_loehner_levels0-2_thresholds0.01-0.03", cycles=recs, final_elements=int(u.shape[1]),
+                rhs_GDOF_RHS_s=round(u.numel() / (ms * 1e-3) / 1e9, 3), ms_per_rhs=round(ms, 5))
+
+
 def c4_leg(torch, W, dgx, reps=20):
     """The 2D reacting 5-species cylinder (64 x 128 O-grid, N = 3, 17
     Arrhenius reactions): back-to-back right-hand sides on the hot, partly
@@ -523,6 +661,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched AMR + cases leg")
     ap.add_argument("--no-fluxes", action="store_true",
                     help="skip the leg that times each built volume / surface flux on the TGV (Euler)")
+    ap.add_argument("--no-widened", action="store_true",
+                    help="skip the legs of the mixture flux variants, Navier-Stokes on curved / wall / "
+                         "mortar meshes and dynamic AMR")
     ap.add_argument("--epb", type=int, default=0,
                     help="elements per workgroup to use instead of autotuning (profiling runs)")
     ap.add_argument("--order", type=int, default=-1, choices=(-1, 0, 1, 2, 4, 5, 6),
@@ -633,6 +774,10 @@ def main():
         out["c4"] = c4_leg(torch, W, dgx)
     if not args.no_fluxes:
         out["fluxes"] = flux_leg(torch, W, dgx)
+    if not args.no_widened:
+        out["mixture_fluxes"] = mixture_flux_leg(torch, W, dgx)
+        out["ns"] = ns_leg(torch, W, dgx)
+        out["amr"] = amr_leg(torch, W, dgx)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
