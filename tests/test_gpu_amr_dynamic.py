@@ -3,7 +3,8 @@ construction, the Loehner and Hennemann-Gassner indicators, one adaptation
 pass (leaves and solution transfer) and cycles of indicator, adaptation and
 time steps on a Gaussian density pulse carried across the periodic unit
 cube (4^3 level-0 cells, levels 0-2, thresholds 0.05 and 0.1 on Loehner's
-estimate of the density).
+estimate of the density), for the Euler and (one pass plus steps) the
+Navier-Stokes equations.
 
 Leaves are integers: the GPU's leaf list (element order) must equal the
 oracle's Morton-ordered list exactly.  To keep the decision in one
@@ -163,3 +164,38 @@ def test_amr_cycles(dgx):
               % (cyc, len(order), np.bincount([o[0] for o in order]), e))
         assert e < 1e-11
     s.close()
+
+
+def test_navier_stokes_adaptation(dgx):
+    """Navier-Stokes on the octree: one adaptation pass (the oracle's
+    indicator values fed to both sides) and 10 SSPRK3 steps with the BR1
+    terms across the new mortars (mu = 0.01)."""
+    from tests.helpers import oracle_dt_ns
+    leaves = amr.morton_order(BASE, uniform_leaves())
+    c0 = oracle_case(leaves)
+    ind = amr.indicator(c0.u0, N, amr.IND_LOEHNER, amr.VAR_DENSITY)
+    new, plan = amr.adapt(BASE, leaves, {c: int(t) for c, t in zip(leaves, amr.controller(ind, 0, 1, 2, 0.05, 0.1))})
+    order = amr.morton_order(BASE, new)
+    ref = amr.transfer(c0.u0, leaves, order, plan, N)
+    base_case = W.case_amr(base=4, radii=(0.4,), centre=(0.5, 0.5, 0.5))
+    base_case.cfg = dict(base_case.cfg, eq=W.EQ_NS, mu=0.01)
+    s = dgx.Solver(base_case)
+    s.set_octree(BASE, np.asarray(leaves, np.int32))
+    u = s.amr_adapt(to_dev(c0.u0), ind, CTRL)
+    s.check()
+    assert [tuple(r) for r in s.octree()] == order
+    c = oracle_case(order)
+    c.cfg = dict(c.cfg, eq=W.EQ_NS, mu=0.01)
+    op = Operator(c.cfg, c.mesh)
+    du = to_host(s.rhs(u))
+    e_rhs = parity_err(du, op.rhs(ref), flux_scale(op, ref))
+    dt = oracle_dt_ns(op, ref)
+    s.ssprk3(u, dt, 10)
+    s.check()
+    got = to_host(u)
+    s.close()
+    r10, _ = ssprk.run(lambda v, t: op.rhs(v, t), ref, 0.0, dt, 10)
+    e = rel_err(got, r10)
+    print("NS on the adapted octree (%d elements, %d mortars): rhs parity %.3e, 10 steps %.3e"
+          % (len(order), len(c.mesh.mortars), e_rhs, e))
+    assert e_rhs < 1e-11 and e < 1e-11
