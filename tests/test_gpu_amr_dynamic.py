@@ -199,3 +199,41 @@ def test_navier_stokes_adaptation(dgx):
     print("NS on the adapted octree (%d elements, %d mortars): rhs parity %.3e, 10 steps %.3e"
           % (len(order), len(c.mesh.mortars), e_rhs, e))
     assert e_rhs < 1e-11 and e < 1e-11
+
+
+def test_octree_and_adaptation_errors(dgx):
+    """Rejected inputs leave the context usable: leaves that overlap, leave a
+    hole, break the 2:1 balance or lie out of range; a bad controller or a
+    non-finite indicator; apply without a plan."""
+    import pytest as _pt
+    leaves = uniform_leaves()
+    s, _ = solver(dgx, leaves)
+    split = [c for c in leaves if c != (0, 1, 1, 1)] + amr.children((0, 1, 1, 1))
+    bad = {
+        "overlap": leaves + [(1, 2, 2, 2)],
+        "hole": leaves[1:],
+        "duplicate": leaves + [leaves[0]],
+        "out of range": leaves[:-1] + [(0, 4, 0, 0)],
+        # a leaf split twice next to unsplit neighbours: 2:1 broken
+        "unbalanced": [c for c in split if c != (1, 2, 2, 2)] + amr.children((1, 2, 2, 2)),
+    }
+    for name, lv in bad.items():
+        with _pt.raises(dgx.DgxError) as ei:
+            s.set_octree(BASE, np.asarray(lv, np.int32))
+        assert ei.value.code == -1, name          # DGX_E_INVAL
+    # the context still holds the last good octree
+    assert len(s.octree()) == 64
+    s.set_octree(BASE, np.asarray(split, np.int32))
+    assert len(s.octree()) == 71
+    ind = np.zeros(71)
+    with _pt.raises(dgx.DgxError):
+        dgx.dgx_amr_plan(s.ctx, ind, dict(CTRL, max_level=1, med_level=2))
+    ind[3] = np.nan
+    with _pt.raises(dgx.DgxError):
+        dgx.dgx_amr_plan(s.ctx, ind, CTRL)
+    import torch
+    u = torch.zeros((5, 71, (N + 1) ** 3), dtype=torch.float64, device="cuda")
+    with _pt.raises(dgx.DgxError) as ei:
+        dgx.dgx_amr_apply(s.ctx, u, torch.empty_like(u))
+    assert ei.value.code == -6                    # DGX_E_STATE
+    s.close()
