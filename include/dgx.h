@@ -280,8 +280,11 @@ int dgx_amr_plan(dgx_ctx *ctx, const double *ind, const dgx_amr_controller *c, i
  * aliasing u_old) receives the state of the new elements (kept elements
  * copied, split ones interpolated from their parent, merged ones the L2
  * projection of their children), then the context switches to the new
- * mesh.  Synchronises stream.  On an error after the transfer the context is
- * left without a mesh (DGX_E_STATE until one is set). */
+ * mesh.  Synchronises stream.  The plan is consumed by the call.  If the new
+ * mesh is rejected by the checks of dgx_set_mesh the context keeps the
+ * previous mesh and octree (u_new then holds the transferred state of a mesh
+ * that was not set); a device failure while setting it up leaves the context
+ * without a mesh (DGX_E_STATE until one is set). */
 int dgx_amr_apply(dgx_ctx *ctx, const double *u_old, double *u_new, void *stream);
 
 /* Upload a mesh: the library computes its own LGL operators, metric terms
