@@ -475,10 +475,12 @@ std::string tune_key(const dgx_ctx *ctx) {
            "," + std::to_string(ctx->nelem) + "," + std::to_string(ctx->nmortar > 0);
 }
 
-// default elements per workgroup: about 256 threads within 64 KB of LDS
+// default elements per workgroup: about 256 threads, within 32 KB of LDS
+// (element types whose slot alone is large, the curved mixture kernels at
+// N = 4, then run one element per workgroup: measured faster than two)
 int default_epb(int nn, int slot) {
     int epb = std::max(1, 256 / nn);
-    while (epb > 1 && (size_t)epb * slot * sizeof(double) > 64 * 1024) --epb;
+    while (epb > 1 && (size_t)epb * slot * sizeof(double) > 32 * 1024) epb >>= 1;
     return epb;
 }
 

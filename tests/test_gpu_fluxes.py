@@ -104,6 +104,25 @@ def air5_noisy(vf, sf):
     return c
 
 
+def air5_zero_species():
+    """The curved periodic air field with NO, N and O exactly zero on the
+    elements whose first node lies at x < 0.5 (the entropy-conservative flux's
+    log means then meet zero densities on one or both sides), EC volume
+    flux and EC faces."""
+    from oracle.thermo import Mixture
+    mix = Mixture(W.Species())
+    c = air5_periodic(W.VF_RANOCHA, W.SF_RANOCHA)
+    u = c.u0.copy()
+    T = c.extra["T"]
+    cut = c.mesh.x[0][:, 0] < 0.5
+    rs = u[:5].copy()
+    rs[2:, cut] = 0.0
+    rho = rs.sum(0)
+    v = u[5:8] / u[:5].sum(0)
+    c.u0 = np.concatenate([rs, rho * v, (mix.rho_e(rs, T) + 0.5 * rho * (v * v).sum(0))[None]])
+    return c
+
+
 def air5_periodic(vf, sf=W.SF_RUSANOV):
     """Frozen 5-species air on the curved periodic 2^3 mesh (N = 4): smooth
     composition, density, temperature and velocity fields."""
@@ -154,6 +173,7 @@ CASES = [
     ("curved_air5_ec", lambda: air5_periodic(W.VF_RANOCHA)),
     ("curved_air5_ec_ec_faces", lambda: air5_noisy(W.VF_RANOCHA, W.SF_RANOCHA)),
     ("curved_air5_shock_ec", lambda: shock_hll(W.SF_RUSANOV, W.VF_RANOCHA)),
+    ("curved_air5_ec_zero_species", lambda: air5_zero_species()),
     ("tgv_morinishi", lambda: tgv_euler(W.VF_MORINISHI, W.SF_RUSANOV)),
     ("curved_morinishi", lambda: W.curved_periodic_case(n=2, N=3, volume_flux=W.VF_MORINISHI)),
     ("curved_N4_morinishi", lambda: W.curved_periodic_case(n=2, N=4, volume_flux=W.VF_MORINISHI)),
