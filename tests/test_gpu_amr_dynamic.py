@@ -237,3 +237,41 @@ def test_octree_and_adaptation_errors(dgx):
         dgx.dgx_amr_apply(s.ctx, u, torch.empty_like(u))
     assert ei.value.code == -6                    # DGX_E_STATE
     s.close()
+
+
+def test_finest_level(dgx):
+    """An octree refined toward one corner down to the finest level (12,
+    base 1, 540 leaves after 2:1 balancing): accepted, its right-hand side
+    matches the oracle, and a plan that would split a level-12 leaf is
+    rejected."""
+    leaves = [(0, 0, 0, 0)]
+    for _ in range(12):
+        tgt = {c: (c[0] + 1 if c[1:] == (0, 0, 0) else c[0]) for c in leaves}
+        new, _ = amr.adapt(1, leaves, tgt)
+        leaves = sorted(new)
+    c = W.case_amr(base=4, radii=(0.4,), centre=(0.5, 0.5, 0.5))
+    s = dgx.Solver(c)
+    order = [tuple(r) for r in s.set_octree(1, np.asarray(leaves, np.int32))]
+    assert order == amr.morton_order(1, leaves) and max(o[0] for o in order) == 12
+    x, faces, mortars, level = amr.mesh(1, N, order)
+    cfg = W.base_cfg(3, N, W.EQ_EULER)
+    mesh = W.Mesh(3, N, x, faces, np.zeros((0, 3), np.int32), mortars, np.zeros(0, np.int32),
+                  np.zeros((0, 5)), level=level)
+    u0 = W.blob_state(x, centre=(0.02, 0.03, 0.01), width=0.05)
+    op = Operator(cfg, mesh)
+    got = to_host(s.rhs(to_dev(u0)))
+    s.check()
+    e = parity_err(got, op.rhs(u0), flux_scale(op, u0))
+    print("finest-level octree (%d elements, %d mortars): rhs parity %.3e" % (len(order), len(mortars), e))
+    assert e < 1e-11
+    # a controller beyond the finest level is rejected; at the finest level a
+    # plan that keeps the level-12 leaves is accepted
+    ind = np.where(np.array([o[0] for o in order]) == 12, 1.0, 0.0)
+    with pytest.raises(dgx.DgxError) as ei:
+        dgx.dgx_amr_plan(s.ctx, ind, dict(base_level=0, med_level=13, max_level=13, med_threshold=0.5,
+                                          max_threshold=0.5))
+    assert ei.value.code == -1                    # DGX_E_INVAL
+    n = dgx.dgx_amr_plan(s.ctx, ind, dict(base_level=0, med_level=12, max_level=12, med_threshold=0.5,
+                                          max_threshold=0.5))
+    assert n > 0
+    s.close()
