@@ -14,6 +14,7 @@
 
 #include "../../include/dgx.h"
 #include "host_geometry.h"
+#include "host_parallel.h"
 #include "host_octree.h"
 #include "k_amr.h"
 #include "k_aux.h"
@@ -688,32 +689,48 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         if (nbr[i] == INT_MIN) return set_err(ctx, DGX_E_INVAL, "element face without neighbour or boundary");
     for (int b = 0; b < m->nbc; ++b)
         if (m->bc_kind[b] < 0 || m->bc_kind[b] > 4) return set_err(ctx, DGX_E_INVAL, "bad boundary kind");
-    // geometry
-    std::vector<double> Ja((size_t)dim * dim * E * nn), Jv((size_t)E * nn);
-    std::vector<double> jae(dim * dim * nn), je(nn);
-    std::vector<const double *> xe(dim);
-    bool affine = true;
-    for (int e = 0; e < E; ++e) {
-        for (int c = 0; c < dim; ++c) xe[c] = m->x + ((size_t)c * E + e) * nn;
-        element_metrics(ctx->basis, dim, xe.data(), jae.data(), je.data());
-        double mx = 0.0, dev = 0.0;
-        for (int k = 0; k < dim * dim; ++k)
+    // geometry: per-element metric terms at the first node and the affine
+    // test first; the nodal arrays only when a curved variant runs
+    const int GA = dim * dim + 1;
+    std::vector<double> g((size_t)E * GA);
+    std::vector<int> bad_J(16, INT_MAX);
+    std::vector<unsigned char> curved_el(E, 0);
+    host_parallel(E, [&](int e0, int e1, int t) {
+        MetricScratch ws;
+        std::vector<double> jae(dim * dim * nn), je(nn);
+        const double *xe[3];
+        for (int e = e0; e < e1; ++e) {
+            for (int c = 0; c < dim; ++c) xe[c] = m->x + ((size_t)c * E + e) * nn;
+            element_metrics(ctx->basis, dim, xe, jae.data(), je.data(), ws);
+            double mx = 0.0, dev = 0.0;
+            for (int k = 0; k < dim * dim; ++k)
+                for (int n = 0; n < nn; ++n) {
+                    mx = std::max(mx, std::fabs(jae[k * nn + n]));
+                    dev = std::max(dev, std::fabs(jae[k * nn + n] - jae[k * nn]));
+                }
+            bool pos = true;
             for (int n = 0; n < nn; ++n) {
-                mx = std::max(mx, std::fabs(jae[k * nn + n]));
-                dev = std::max(dev, std::fabs(jae[k * nn + n] - jae[k * nn]));
-                Ja[((size_t)k * E + e) * nn + n] = jae[k * nn + n];
+                pos = pos && je[n] > 0.0;
+                dev = std::max(dev, std::fabs(je[n] - je[0]) * mx / std::fabs(je[0]));
             }
-        for (int n = 0; n < nn; ++n) {
-            if (!(je[n] > 0.0)) return set_err(ctx, DGX_E_INVAL, "non-positive Jacobian in element " + std::to_string(e));
-            dev = std::max(dev, std::fabs(je[n] - je[0]) * mx / std::fabs(je[0]));
-            Jv[(size_t)e * nn + n] = je[n];
+            if (!pos) {
+                bad_J[t] = std::min(bad_J[t], e);
+                continue;
+            }
+            // affine up to the rounding of the coordinates: an element of size h
+            // at distance ~1 from the origin carries relative coordinate noise
+            // ~1e-16/h (4e-13 at the finest octree level), which the metric
+            // terms amplify; genuine curvature is many orders larger
+            curved_el[e] = dev > 1e-10 * mx;
+            for (int k = 0; k < dim * dim; ++k) g[(size_t)e * GA + k] = jae[k * nn];
+            g[(size_t)e * GA + dim * dim] = je[0];
         }
-        // affine up to the rounding of the coordinates: an element of size h
-        // at distance ~1 from the origin carries relative coordinate noise
-        // ~1e-16/h (4e-13 at the finest octree level), which the metric
-        // terms amplify; genuine curvature is many orders larger
-        if (dev > 1e-10 * mx) affine = false;
+    });
+    {
+        const int b = *std::min_element(bad_J.begin(), bad_J.end());
+        if (b != INT_MAX) return set_err(ctx, DGX_E_INVAL, "non-positive Jacobian in element " + std::to_string(b));
     }
+    bool affine = std::find(curved_el.begin(), curved_el.end(), (unsigned char)1) == curved_el.end();
     if (m->nmortar && !affine) return set_err(ctx, DGX_E_INVAL, "mortars need affine elements");
     // pick the kernel variant for this geometry
     const RhsEntry *sel = nullptr;
@@ -770,17 +787,23 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
         ctx->wq_nfree[k] = (int)std::count(waits.begin(), waits.end(), (unsigned char)0);
     }
     if (affine) {
-        const int GA = dim * dim + 1;
-        std::vector<double> g((size_t)E * GA);
-        for (int e = 0; e < E; ++e) {
-            for (int k = 0; k < dim * dim; ++k) g[(size_t)e * GA + k] = Ja[((size_t)k * E + e) * nn];
-            g[(size_t)e * GA + dim * dim] = Jv[(size_t)e * nn];
-        }
         if ((rc = dalloc(ctx, ctx->geo, g.size()))) return rc;
         HIPCHK(hipMemcpy(ctx->geo.p, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice));
         ctx->Jn.release();
         ctx->nsub.release();
     } else {
+        std::vector<double> Ja((size_t)dim * dim * E * nn), Jv((size_t)E * nn);
+        host_parallel(E, [&](int e0, int e1, int) {
+            MetricScratch ws;
+            std::vector<double> jae(dim * dim * nn);
+            const double *xe[3];
+            for (int e = e0; e < e1; ++e) {
+                for (int c = 0; c < dim; ++c) xe[c] = m->x + ((size_t)c * E + e) * nn;
+                element_metrics(ctx->basis, dim, xe, jae.data(), Jv.data() + (size_t)e * nn, ws);
+                for (int k = 0; k < dim * dim; ++k)
+                    std::memcpy(&Ja[((size_t)k * E + e) * nn], &jae[(size_t)k * nn], nn * sizeof(double));
+            }
+        });
         if ((rc = dalloc(ctx, ctx->geo, Ja.size()))) return rc;
         HIPCHK(hipMemcpy(ctx->geo.p, Ja.data(), Ja.size() * sizeof(double), hipMemcpyHostToDevice));
         if ((rc = dalloc(ctx, ctx->Jn, Jv.size()))) return rc;
@@ -1525,6 +1548,7 @@ namespace {
 int oct_upload(dgx_ctx *ctx, int base, const std::vector<OctLeaf> &order) {
     OctTree t;
     t.base = base;
+    t.leaves.reserve(order.size() * 2);
     for (auto &c : order) t.leaves.insert(oct_key(c));
     std::vector<int32_t> faces, morts;
     oct_tables(t, order, faces, morts);

@@ -112,16 +112,22 @@ inline void ref_derivative(const HostBasis &B, int dim, int d, const double *f, 
     }
 }
 
+// Working storage of element_metrics (one per host thread).
+struct MetricScratch {
+    std::vector<double> xl, dx, V, t1, t2;
+};
+
 // Metric terms Ja[i][c] (i: reference direction, c: Cartesian component) and
 // J at the nodes of one element.  x: [dim][nn] of that element.
 inline void element_metrics(const HostBasis &B, int dim, const double *const *xe, double *Ja /*[dim*dim][nn]*/,
-                            double *J /*[nn]*/) {
+                            double *J /*[nn]*/, MetricScratch &ws) {
     const int n1 = B.N1;
     const int nn = dim == 2 ? n1 * n1 : n1 * n1 * n1;
-    std::vector<double> xl(dim * nn);
+    std::vector<double> &xl = ws.xl, &dx = ws.dx;
+    xl.resize(dim * nn);
     for (int c = 0; c < dim; ++c)
         for (int n = 0; n < nn; ++n) xl[c * nn + n] = xe[c][n] - xe[c][0];
-    std::vector<double> dx(dim * dim * nn);  // dx[(c*dim+d)*nn+n] = d x_c / d X_d
+    dx.resize(dim * dim * nn);  // dx[(c*dim+d)*nn+n] = d x_c / d X_d
     for (int c = 0; c < dim; ++c)
         for (int d = 0; d < dim; ++d) ref_derivative(B, dim, d, &xl[c * nn], &dx[(c * dim + d) * nn]);
     auto DX = [&](int c, int d, int n) { return dx[(c * dim + d) * nn + n]; };
@@ -135,7 +141,10 @@ inline void element_metrics(const HostBasis &B, int dim, const double *const *xe
         }
         return;
     }
-    std::vector<double> V(3 * nn), t1(nn), t2(nn);
+    std::vector<double> &V = ws.V, &t1 = ws.t1, &t2 = ws.t2;
+    V.resize(3 * nn);
+    t1.resize(nn);
+    t2.resize(nn);
     for (int comp = 0; comp < 3; ++comp) {
         const int m = (comp + 1) % 3, l = (comp + 2) % 3;
         // V_d = x_l * d x_m / d X_d

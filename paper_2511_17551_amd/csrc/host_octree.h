@@ -18,6 +18,8 @@
 #include <unordered_set>
 #include <vector>
 
+#include "host_parallel.h"
+
 namespace dgx {
 
 struct OctLeaf {
@@ -144,6 +146,7 @@ inline std::string oct_check(int base, const std::vector<OctLeaf> &v, OctTree &t
     if (base < 1 || base > kOctMaxBase) return "octree base out of range";
     t.base = base;
     t.leaves.clear();
+    t.leaves.reserve(v.size() * 2);
     int lmax = 0;
     for (auto &c : v) {
         if (c.L < 0 || c.L > kOctMaxLevel) return "octree level out of range";
@@ -159,8 +162,11 @@ inline std::string oct_check(int base, const std::vector<OctLeaf> &v, OctTree &t
         vol += (unsigned __int128)1 << (3 * (lmax - c.L));
     }
     if (vol != ((unsigned __int128)base * base * base) << (3 * lmax)) return "octree leaves do not fill the cube";
-    for (auto &c : v)
-        if (t.finest_neighbour(c) > c.L + 1) return "octree is not 2:1 balanced";
+    std::vector<unsigned char> unbalanced(16, 0);
+    host_parallel((int)v.size(), [&](int b, int e, int th) {
+        for (int i = b; i < e && !unbalanced[th]; ++i) unbalanced[th] = t.finest_neighbour(v[i]) > v[i].L + 1;
+    });
+    if (std::count(unbalanced.begin(), unbalanced.end(), (unsigned char)1)) return "octree is not 2:1 balanced";
     return "";
 }
 
@@ -170,32 +176,41 @@ inline void oct_tables(const OctTree &t, const std::vector<OctLeaf> &order, std:
     std::unordered_map<uint64_t, int> eid;
     eid.reserve(order.size() * 2);
     for (size_t e = 0; e < order.size(); ++e) eid[oct_key(order[e])] = (int)e;
+    // rows per thread over contiguous element ranges, joined in element order
+    std::vector<std::vector<int32_t>> fpart(16), mpart(16);
+    host_parallel((int)order.size(), [&](int e0, int e1, int th) {
+        std::vector<int32_t> &fo = fpart[th], &mo = mpart[th];
+        for (int e = e0; e < e1; ++e) {
+            const OctLeaf &c = order[e];
+            for (int d = 0; d < 3; ++d)
+                for (int sgn = 1; sgn >= -1; sgn -= 2) {
+                    int ii[3] = {c.i, c.j, c.k};
+                    ii[d] += sgn;
+                    OctLeaf nb;
+                    if (t.leaf_at(c.L, ii[0], ii[1], ii[2], nb)) {
+                        if (nb.L == c.L && sgn == 1) {
+                            fo.push_back((int32_t)e);
+                            fo.push_back(2 * d + 1);
+                            fo.push_back(eid.at(oct_key(nb)));
+                            fo.push_back(2 * d);
+                        }
+                        continue;  // coarser neighbour: the large side records the mortar
+                    }
+                    OctLeaf fc[4];
+                    t.face_cells(c, d, sgn, fc);
+                    const int fl = 2 * d + (sgn == 1 ? 1 : 0);
+                    mo.push_back((int32_t)e);
+                    mo.push_back(fl);
+                    for (int s = 0; s < 4; ++s) mo.push_back(eid.at(oct_key(fc[s])));
+                    mo.push_back(fl ^ 1);
+                }
+        }
+    });
     faces.clear();
     morts.clear();
-    for (size_t e = 0; e < order.size(); ++e) {
-        const OctLeaf &c = order[e];
-        for (int d = 0; d < 3; ++d)
-            for (int sgn = 1; sgn >= -1; sgn -= 2) {
-                int ii[3] = {c.i, c.j, c.k};
-                ii[d] += sgn;
-                OctLeaf nb;
-                if (t.leaf_at(c.L, ii[0], ii[1], ii[2], nb)) {
-                    if (nb.L == c.L && sgn == 1) {
-                        faces.push_back((int32_t)e);
-                        faces.push_back(2 * d + 1);
-                        faces.push_back(eid.at(oct_key(nb)));
-                        faces.push_back(2 * d);
-                    }
-                    continue;  // coarser neighbour: the large side records the mortar
-                }
-                OctLeaf fc[4];
-                t.face_cells(c, d, sgn, fc);
-                const int fl = 2 * d + (sgn == 1 ? 1 : 0);
-                morts.push_back((int32_t)e);
-                morts.push_back(fl);
-                for (int s = 0; s < 4; ++s) morts.push_back(eid.at(oct_key(fc[s])));
-                morts.push_back(fl ^ 1);
-            }
+    for (int th = 0; th < 16; ++th) {
+        faces.insert(faces.end(), fpart[th].begin(), fpart[th].end());
+        morts.insert(morts.end(), mpart[th].begin(), mpart[th].end());
     }
 }
 
@@ -212,6 +227,8 @@ inline std::string oct_adapt(int base, const std::vector<OctLeaf> &old_order, co
     OctTree t;
     t.base = base;
     std::unordered_map<uint64_t, int> oid;
+    t.leaves.reserve(old_order.size() * 4);
+    oid.reserve(old_order.size() * 2);
     for (size_t e = 0; e < old_order.size(); ++e) {
         t.leaves.insert(oct_key(old_order[e]));
         oid[oct_key(old_order[e])] = (int)e;
@@ -228,16 +245,26 @@ inline std::string oct_adapt(int base, const std::vector<OctLeaf> &old_order, co
         const OctLeaf c{(int)(key >> 60), (int)((key >> 40) & 0xFFFFF), (int)((key >> 20) & 0xFFFFF), (int)(key & 0xFFFFF)};
         t.split(c);
     }
-    // 2:1 balance (its closure is unique, the scan order does not matter)
-    for (bool changed = true; changed;) {
-        changed = false;
-        for (const OctLeaf &c : t.list()) {
-            if (!t.has(c) || t.finest_neighbour(c) <= c.L + 1) continue;
+    // 2:1 balance.  A leaf that faces one two levels finer must be split in
+    // every balanced refinement of the current tree, so each sweep finds all
+    // such leaves (in parallel, the tree read-only) and splits them together;
+    // the sweeps end at the unique smallest balanced refinement.
+    for (;;) {
+        const std::vector<OctLeaf> cur = t.list();
+        std::vector<unsigned char> need(cur.size(), 0);
+        host_parallel((int)cur.size(), [&](int b, int e, int) {
+            for (int i = b; i < e; ++i) need[i] = t.finest_neighbour(cur[i]) > cur[i].L + 1;
+        });
+        bool any = false;
+        for (size_t i = 0; i < cur.size(); ++i) {
+            if (!need[i]) continue;
+            const OctLeaf &c = cur[i];
             if (c.L + 1 > kOctMaxLevel) return "2:1 balance beyond the finest octree level";
             t.split(c);
             if (oid.count(oct_key(c))) split.insert(oct_key(c));
-            changed = true;
+            any = true;
         }
+        if (!any) break;
     }
     // merges of unsplit families whose targets all lie below their level
     std::map<OctLeaf, std::vector<int>> fam;
