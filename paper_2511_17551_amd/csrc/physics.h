@@ -58,33 +58,76 @@ __device__ __forceinline__ double wave_sqrt(double x) {
     return fma(d, h, g);
 }
 
-// Logarithmic mean (y - x)/ln(y/x) from the values and their logs.  For
-// z = ((y-x)/(y+x))^2 < 1e-4 the mean is (x+y)/P(z) with the 4-term series
-// P = 2 + 2z/3 + 2z^2/5 + 2z^3/7; here 1/P is itself expanded,
-// 2/P = 1 - z/3 - 4z^2/45 - 44z^3/945 + O(z^4) (remainder < 1e-17 relative),
-// which saves a reciprocal.
+// Logarithmic mean (y - x)/ln(y/x) and its reciprocal.  With f = (y-x)/(y+x)
+// and z = f^2, ln(y/x) = 2 atanh f, so the mean is (x+y)/(2 A(z)) with
+// A(z) = atanh(sqrt z)/sqrt z = sum_n z^n/(2n+1).  Three branches by z:
+//   * z < 1e-4: A to four terms, and for the mean 1/A expanded,
+//     1 - z/3 - 4z^2/45 - 44z^3/945 (remainder < 1e-17 relative), which
+//     saves a reciprocal;
+//   * z < 0.02 (ratios y/x up to 1.33): A, and 1/A, to ten terms; the
+//     coefficients of 1/A come from the exact inversion of the series of A
+//     (truncation below 1e-18 relative on this range);
+//   * beyond: the logarithm.
+__device__ __forceinline__ double inv_atanh_ratio10(double z) {
+    // 1/A(z), degree 9
+    double r = -74185965772.0 / 7795859096025.0;
+    r = fma(r, z, -5472607916.0 / 488462349375.0);
+    r = fma(r, z, -25865068.0 / 1915538625.0);
+    r = fma(r, z, -10719068.0 / 638512875.0);
+    r = fma(r, z, -10196.0 / 467775.0);
+    r = fma(r, z, -428.0 / 14175.0);
+    r = fma(r, z, -44.0 / 945.0);
+    r = fma(r, z, -4.0 / 45.0);
+    r = fma(r, z, -1.0 / 3.0);
+    return fma(r, z, 1.0);
+}
+
+__device__ __forceinline__ double atanh_ratio10_x2(double z) {
+    // 2 A(z), degree 9
+    double r = 2.0 / 19.0;
+    r = fma(r, z, 2.0 / 17.0);
+    r = fma(r, z, 2.0 / 15.0);
+    r = fma(r, z, 2.0 / 13.0);
+    r = fma(r, z, 2.0 / 11.0);
+    r = fma(r, z, 2.0 / 9.0);
+    r = fma(r, z, 2.0 / 7.0);
+    r = fma(r, z, 2.0 / 5.0);
+    r = fma(r, z, 2.0 / 3.0);
+    return fma(r, z, 2.0);
+}
+
 __device__ __forceinline__ double ln_mean(double x, double y) {
     const double s = x + y;
     const double d = y - x;
-    if (d * d < 1e-4 * (s * s)) {
+    const double d2 = d * d, s2 = s * s;
+    if (d2 < 1e-4 * s2) {
         const double q = d * rcp(s);
         const double z = q * q;
         const double h = 0.5 * s;
         return fma(-h * z, 1.0 / 3.0 + z * (4.0 / 45.0 + z * (44.0 / 945.0)), h);
     }
+    if (d2 < 0.02 * s2) {
+        const double q = d * rcp(s);
+        return 0.5 * s * inv_atanh_ratio10(q * q);
+    }
     return d * rcp(log(y * rcp(x)));
 }
 
-// Reciprocal of the logarithmic mean, ln(y/x)/(y - x) (same branches).
 __device__ __forceinline__ double inv_ln_mean(double x, double y) {
     const double s = x + y;
     const double d = y - x;
-    if (d * d < 1e-4 * (s * s)) {
+    const double d2 = d * d, s2 = s * s;
+    if (d2 < 1e-4 * s2) {
         const double rs = rcp(s);
         const double q = d * rs;
         const double z = q * q;
         const double P = 2.0 + z * (2.0 / 3.0 + z * (2.0 / 5.0 + z * (2.0 / 7.0)));
         return P * rs;
+    }
+    if (d2 < 0.02 * s2) {
+        const double rs = rcp(s);
+        const double q = d * rs;
+        return atanh_ratio10_x2(q * q) * rs;
     }
     return log(y * rcp(x)) * rcp(d);
 }
