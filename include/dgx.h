@@ -433,7 +433,8 @@ int dgx_mixture_energy(const dgx_ctx *ctx, const double *rs, const double *T, in
  * right-hand side in the fused form of the second SSPRK3 stage
  * (out = 3/4 u0 + 1/4 (u + dt du), u0 a library copy of u in its own
  * buffer, out into library scratch; u is not modified), bracketing every
- * kernel with HIP events on `stream`.  ms_out[k] receives
+ * kernel with HIP events on `stream`, after one untimed evaluation.
+ * ms_out[k] receives
  * the average duration of kernel k in launch order, names_out (may be NULL)
  * a comma-separated list of the kernel names (buffer of names_len bytes);
  * *nk the number of kernels (<= 8).  Synchronises. */

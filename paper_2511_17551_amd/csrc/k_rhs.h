@@ -610,6 +610,16 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
             // pair of its own element whose slot is its node index (the
             // spread would give every thread one item as well)
             constexpr bool OWN = PDC == NN;
+            // odd N1 with (N1-1)/2 such chunks (N = 4): circulant pairs, chunk
+            // ch taking offset j = ch + 1.  The thread of the node at position
+            // a on line l evaluates the pair {a, (a + j) mod N1}, adds its own
+            // share at once and leaves the flux in its node's slot; its other
+            // pair of this offset, {(a - j) mod N1, a}, is read from the slot
+            // of that node.  Every pair is evaluated once, every node takes
+            // all its N1 - 1 pairs, and the lanes of a wave read slots of
+            // consecutive nodes (few LDS bank conflicts).
+            constexpr bool CIRC = OWN && (N1 % 2 == 1) && 2 * NCH == N1 - 1;
+            const int jc = ch + 1;
             Spread sp{tid, cursor};
             if constexpr (!OWN) {
                 sp = spread_phase(tid, NT, P.epb * PDC, cursor);
@@ -621,18 +631,27 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                 if (OWN ? valid : (tid < NT && it < nloc * PDC)) {
                     const int ei = OWN ? el : it / PDC;
                     const int jb = OWN ? node : it - ei * PDC;  // slot in this chunk's buffer
-                    const int p = ch * PDC + jb;       // pair index within the direction
-                    if (NCH > 1 && p >= PD) continue;
-                    const int l = p / NPL;
-                    const int k = p - l * NPL;
-                    const int a = (int)((PairTab<N1>::A >> (4 * k)) & 15u);
-                    const int b = (int)((PairTab<N1>::B >> (4 * k)) & 15u);
+                    // the pair's nodes na, nb (CIRC: the own node and its
+                    // partner at positions ca, cb; the volume fluxes are
+                    // symmetric in their two states)
+                    int na, nb, ca = 0, cb = 0;
+                    if constexpr (CIRC) {
+                        ca = node_pos<N1>(node, d);
+                        cb = ca + jc >= N1 ? ca + jc - N1 : ca + jc;
+                        na = node;
+                        nb = line_node<N1, DIM>(d, cb, node_line<N1, DIM>(node, d));
+                    } else {
+                        const int p = ch * PDC + jb;  // pair index within the direction
+                        if (NCH > 1 && p >= PD) continue;
+                        const int l = p / NPL;
+                        const int k = p - l * NPL;
+                        na = line_node<N1, DIM>(d, (int)((PairTab<N1>::A >> (4 * k)) & 15u), l);
+                        nb = line_node<N1, DIM>(d, (int)((PairTab<N1>::B >> (4 * k)) & 15u), l);
+                    }
                     const double *esu = smem + ei * S::SLOT;
                     const double *esq = esu + S::SU;
                     const double *eg = esu + OFF_G;
                     double *ebuf = smem + ei * S::SLOT + off_b;
-                    const int na = line_node<N1, DIM>(d, a, l);
-                    const int nb = line_node<N1, DIM>(d, b, l);
                     double nbar[DIM];
 #pragma unroll
                     for (int c = 0; c < DIM; ++c)
@@ -663,6 +682,11 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                     }
 #pragma unroll
                     for (int v = 0; v < NV; ++v) ebuf[jb * NVP + v] = F[v];
+                    if constexpr (CIRC) {
+                        const double coef = sDc[ca * N1 + cb];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) dg[v] = fma(coef, F[v], dg[v]);
+                    }
                 }
             }
             if (d == DIM - 1 && ch == NCH - 1) {
@@ -686,7 +710,15 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                     for (int c = 0; c < DIM; ++c) sJa[c * NN + node] = jnext[c];
                 }
             }
-            if (valid) {
+            if (CIRC && valid) {
+                const int a = node_pos<N1>(node, d);
+                const int l = node_line<N1, DIM>(node, d);
+                const int a2 = a - jc < 0 ? a - jc + N1 : a - jc;
+                const int src = line_node<N1, DIM>(d, a2, l);
+                const double coef = sDc[a * N1 + a2];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) dg[v] = fma(coef, buf[src * NVP + v], dg[v]);
+            } else if (valid) {
                 const int a = node_pos<N1>(node, d);
                 const int l = node_line<N1, DIM>(node, d);
                 const int sa4 = 4 * a;
