@@ -594,6 +594,18 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
 #pragma unroll
     for (int v = 0; v < NV; ++v) dg[v] = 0.0;
     const double gm1_inv = 1.0 / (gamma - 1.0);
+    // circulant pairs (below): the own node's state and current metric row
+    // stay in registers for the whole volume term
+    constexpr bool CIRC_K = PDC == NN && (N1 % 2 == 1) && 2 * NCH == N1 - 1 && !S::EC;
+    St<DIM, MIX> own_st;
+    double own_row[DIM];
+    if constexpr (CIRC_K) {
+        if (valid) lds_state<DIM, MIX>(su, sq, NN, node, gamma, own_st);
+        if constexpr (CURV) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) own_row[c] = valid ? sJa[c * NN + node] : 0.0;
+        }
+    }
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         // curved elements: the next direction's metric row, loaded now and
@@ -654,8 +666,10 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                     double *ebuf = smem + ei * S::SLOT + off_b;
                     double nbar[DIM];
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c)
-                        nbar[c] = CURV ? 0.5 * (eg[c * NN + na] + eg[c * NN + nb]) : eg[d * DIM + c];
+                    for (int c = 0; c < DIM; ++c) {
+                        if constexpr (CURV && CIRC_K) nbar[c] = 0.5 * (own_row[c] + eg[c * NN + nb]);
+                        else nbar[c] = CURV ? 0.5 * (eg[c * NN + na] + eg[c * NN + nb]) : eg[d * DIM + c];
+                    }
                     double F[NV];
                     if constexpr (S::EC) {
                         double vA[DIM], vB[DIM];
@@ -668,7 +682,8 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                                            esq[(1 + DIM) * NN + nb], esq[QB * NN + nb], nbar, gm1_inv, F);
                     } else {
                         St<DIM, MIX> A, B;
-                        lds_state<DIM, MIX>(esu, esq, NN, na, gamma, A);
+                        if constexpr (CIRC_K) A = own_st;
+                        else lds_state<DIM, MIX>(esu, esq, NN, na, gamma, A);
                         lds_state<DIM, MIX>(esu, esq, NN, nb, gamma, B);
                         if constexpr (VF == 0) {
                             ec_mixture_state<DIM>(A, B, nbar, P.M, F);
@@ -708,6 +723,10 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                 if (ch == NCH - 1 && d + 1 < DIM && valid) {
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) sJa[c * NN + node] = jnext[c];
+                    if constexpr (CIRC_K) {
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) own_row[c] = jnext[c];
+                    }
                 }
             }
             if (CIRC && valid) {
