@@ -631,14 +631,66 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
             // all its N1 - 1 pairs, and the lanes of a wave read slots of
             // consecutive nodes (few LDS bank conflicts).
             constexpr bool CIRC = OWN && (N1 % 2 == 1) && 2 * NCH == N1 - 1;
+            // four nodes per line (N = 3) in one chunk: the pair at offset 1,
+            // {a, (a + 1) mod 4}, as above; the pair at offset 2 is evaluated
+            // by both of its nodes (with its lower node first, so that both
+            // take the same flux) and needs no exchange
+            constexpr bool CIRC4 = N1 == 4 && NCH == 1;
             const int jc = ch + 1;
+            if constexpr (CIRC4) {
+                if (valid) {
+                    const int a = node_pos<N1>(node, d);
+                    const int l = node_line<N1, DIM>(node, d);
+#pragma unroll
+                    for (int j = 1; j <= 2; ++j) {
+                        const int b = (a + j) & 3;
+                        const int nb = line_node<N1, DIM>(d, b, l);
+                        const int nlo = a < b ? node : nb, nhi = a < b ? nb : node;
+                        double nbar[DIM];
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c)
+                            nbar[c] = CURV ? 0.5 * (sJa[c * NN + nlo] + sJa[c * NN + nhi]) : sJa[d * DIM + c];
+                        double F[NV];
+                        if constexpr (S::EC) {
+                            double vA[DIM], vB[DIM];
+#pragma unroll
+                            for (int c = 0; c < DIM; ++c) {
+                                vA[c] = sq[(1 + c) * NN + nlo];
+                                vB[c] = sq[(1 + c) * NN + nhi];
+                            }
+                            ranocha_prims<DIM>(sq[nlo], vA, sq[(1 + DIM) * NN + nlo], sq[QB * NN + nlo], sq[nhi], vB,
+                                               sq[(1 + DIM) * NN + nhi], sq[QB * NN + nhi], nbar, gm1_inv, F);
+                        } else {
+                            St<DIM, MIX> A, B;
+                            lds_state<DIM, MIX>(su, sq, NN, nlo, gamma, A);
+                            lds_state<DIM, MIX>(su, sq, NN, nhi, gamma, B);
+                            if constexpr (VF == 0) {
+                                ec_mixture_state<DIM>(A, B, nbar, P.M, F);
+                            } else if constexpr (VF == 1) {
+                                ducros_state<DIM, MIX>(A, B, nbar, F);
+                            } else if constexpr (VF == 4) {
+                                central_state<DIM, MIX>(A, B, nbar, F);
+                            } else {
+                                split_form_state<DIM, MIX, VF == 5 ? 2 : VF - 2>(A, B, nbar, gm1_inv, F);
+                            }
+                        }
+                        if (j == 1) {
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) buf[node * NVP + v] = F[v];
+                        }
+                        const double coef = sDc[a * N1 + b];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) dg[v] = fma(coef, F[v], dg[v]);
+                    }
+                }
+            }
             Spread sp{tid, cursor};
-            if constexpr (!OWN) {
+            if constexpr (!OWN && !CIRC4) {
                 sp = spread_phase(tid, NT, P.epb * PDC, cursor);
                 cursor = sp.cursor;
             }
 #pragma unroll
-            for (int r = 0; r < (PDC + NN - 1) / NN; ++r) {
+            for (int r = 0; r < (CIRC4 ? 0 : (PDC + NN - 1) / NN); ++r) {
                 const int it = r * NT + sp.t;
                 if (OWN ? valid : (tid < NT && it < nloc * PDC)) {
                     const int ei = OWN ? el : it / PDC;
@@ -729,7 +781,16 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                     }
                 }
             }
-            if (CIRC && valid) {
+            if (CIRC4 && valid) {
+                // the pair {(a + 3) mod 4, a}, left by that node
+                const int a = node_pos<N1>(node, d);
+                const int l = node_line<N1, DIM>(node, d);
+                const int a2 = (a + 3) & 3;
+                const int src = line_node<N1, DIM>(d, a2, l);
+                const double coef = sDc[a * N1 + a2];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) dg[v] = fma(coef, buf[src * NVP + v], dg[v]);
+            } else if (CIRC && valid) {
                 const int a = node_pos<N1>(node, d);
                 const int l = node_line<N1, DIM>(node, d);
                 const int a2 = a - jc < 0 ? a - jc + N1 : a - jc;
