@@ -595,8 +595,9 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
     for (int v = 0; v < NV; ++v) dg[v] = 0.0;
     const double gm1_inv = 1.0 / (gamma - 1.0);
     // circulant pairs (below): the own node's state and current metric row
-    // stay in registers for the whole volume term
-    constexpr bool CIRC_K = PDC == NN && (N1 % 2 == 1) && 2 * NCH == N1 - 1 && !S::EC;
+    // stay in registers for the whole volume term (not with the entropy-
+    // conservative mixture flux, whose registers would then cost a wave)
+    constexpr bool CIRC_K = PDC == NN && (N1 % 2 == 1) && 2 * NCH == N1 - 1 && !S::EC && !(MIX && VF == 0);
     St<DIM, MIX> own_st;
     double own_row[DIM];
     if constexpr (CIRC_K) {
