@@ -139,7 +139,11 @@ struct RhsShape {
     // chunks, which halves the flux buffer (LDS bounds their occupancy)
     static constexpr int NCH = CHF ? CHF : (PD * NV > 1200 ? 2 : 1);
     static constexpr int PDC = (PD + NCH - 1) / NCH;    // pairs per chunk
-    static constexpr int NSFC = (NSF + NCH - 1) / NCH;  // face nodes per chunk
+    // face work in one chunk where the pair phase takes one pair per thread
+    // and chunk (N = 4): the larger face buffer keeps the occupancy and
+    // saves the second chunk's two barriers
+    static constexpr int NCHF = (CHF == 0 && NCH == 2 && PDC == NN) ? 1 : NCH;
+    static constexpr int NSFC = (NSF + NCHF - 1) / NCHF;  // face nodes per chunk
     // the volume pair fluxes are stored pair-major (a pair's NV fluxes are
     // contiguous, so one base address serves all of them), with an odd row
     // stride so that rows written by consecutive lanes start on distinct LDS
@@ -203,14 +207,14 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
     using S = RhsShape<DIM, N, EQ, VF, CURV, CHF>;
     constexpr int N1 = S::N1, NN = S::NN, NF = S::NF, NV = S::NV, NQ = S::NQ, NW = S::NW;
     constexpr int NPL = S::NPL, PD = S::PD, NFV = S::NFV, NSF = S::NSF;
-    constexpr int NCH = S::NCH, PDC = S::PDC, NSFC = S::NSFC, NVP = S::NVP;
+    constexpr int NCH = S::NCH, NCHF = S::NCHF, PDC = S::PDC, NSFC = S::NSFC, NVP = S::NVP;
     constexpr bool MIX = S::MIX;
     constexpr int GA = DIM * DIM + 1;
     constexpr int QB = DIM + 3 + (MIX ? 1 : 0);  // EC slot in sq
     constexpr int OFF_G = S::SU + NQ * NN;        // element geometry within a slot
     constexpr int OFF_B = OFF_G + S::GEO + S::GEOA;
     constexpr int RFC = (NSFC + NN - 1) / NN;     // face rounds per chunk
-    constexpr int RF = NCH * RFC;                 // face rounds
+    constexpr int RF = NCHF * RFC;                // face rounds
     extern __shared__ double smem[];
     // 2 D (pair-flux coefficients) and the LGL weights: read with per-lane
     // indices, so they live in LDS rather than in the kernel arguments
@@ -250,10 +254,10 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
     // NCH chunks so that one chunk's fluxes fit the LDS buffer.  The face
     // phase's neighbour indices, and then the neighbour data of its first
     // round, are fetched first so that their latency overlaps the staging.
-    Spread spf[NCH];
+    Spread spf[NCHF];
     int cursor = 0;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
+    for (int c = 0; c < NCHF; ++c) {
         spf[c] = spread_phase(tid, NT, P.epb * NSFC, cursor);
         cursor = spf[c].cursor;
     }
@@ -390,7 +394,7 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
 
     // ---- interface / boundary Riemann fluxes: one work item per face node
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
+    for (int ch = 0; ch < NCHF; ++ch) {
 #pragma unroll
         for (int rr = 0; rr < RFC; ++rr) {
             const int g = ch * RFC + rr;
@@ -525,7 +529,7 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                 const int l = node_line<N1, DIM>(node, d);
                 if (a == N || a == 0) {
                     const int fi = (2 * d + (a == N ? 1 : 0)) * NF + l;
-                    if (NCH == 1 || (fi >= ch * NSFC && fi < (ch + 1) * NSFC)) {
+                    if (NCHF == 1 || (fi >= ch * NSFC && fi < (ch + 1) * NSFC)) {
                         const double sc = a == N ? 1.0 / sW[N] : -1.0 / sW[0];
 #pragma unroll
                         for (int v = 0; v < NV; ++v) acc[v] = fma(sc, buf[v * NSFC + fi - ch * NSFC], acc[v]);
