@@ -136,12 +136,17 @@ TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
 
 
 def kernel_source_hash():
-    """SHA-1 of the sources the right-hand-side kernel is compiled from."""
+    """SHA-1 of the code the right-hand-side kernel is compiled from: its
+    sources with // comments, trailing blanks and empty lines removed (a
+    comment edit does not make the recorded traffic stale)."""
     h = hashlib.sha1()
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_17551_amd", "csrc")
     for f in ("k_rhs.h", "physics.h", "dgx_internal.h"):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode("utf-8") + b"\n")
     return h.hexdigest()
 
 

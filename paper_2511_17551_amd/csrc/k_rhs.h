@@ -10,8 +10,13 @@
 //
 // The diagonal-free sum is the telescoped subcell flux difference of
 // Eq. DGvec with zero end values (the end values cancel against the strong-
-// form surface terms because 2 D_00 + 1/w_0 = 0).  Each symmetric pair
-// (a < b) of a line is evaluated once and feeds both nodes.
+// form surface terms because 2 D_00 + 1/w_0 = 0).  The two-point fluxes are
+// symmetric in their states, so a pair's flux feeds both of its nodes: the
+// thread of a node evaluates its pairs at fixed offsets along its line and
+// passes one of them to its neighbour through LDS (N = 4: offsets 1 and 2,
+// every pair evaluated once; N = 3: offset 1 exchanged, offset 2 evaluated
+// by both nodes with the lower one first); other tilings evaluate each pair
+// (a < b) once and both nodes gather it from a pair-indexed buffer.
 //
 // Work layout: thread <-> node, EPB elements per workgroup, the element's
 // primitives (and, for mixtures, the species densities; on curved meshes
@@ -118,7 +123,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // CHF: work-item chunks of the pair and face phases (the LDS tiling): 0 the
-// default rule below, else that many chunks
+// default rule below, else that many chunks for both
 template <int DIM, int N, int EQ, int VF, bool CURV, int CHF = 0>
 struct RhsShape {
     static constexpr int N1 = N + 1;
