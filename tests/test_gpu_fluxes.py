@@ -27,6 +27,8 @@ side, one SSPRK3 step).
 * Morinishi's form on the Taylor-Green state (Euler and Navier-Stokes), the
   curved periodic state at N = 3 and 4 and the 2D vortex.
 * One SSPRK3 step with Kennedy-Gruber on the curved mesh.
+* Discrete conservation of the volume and interface terms on periodic meshes
+  (N = 3 affine, N = 4 curved): the quadrature sum of J du vanishes.
 
 The Taylor-Green density is uniform, where the Kennedy-Gruber and Pirozzoli
 energy fluxes coincide; on the curved state they differ by 6e-2 in the
@@ -271,3 +273,29 @@ def test_perfect_gas_entropy_conservation_all_log_mean_branches(dgx):
     print("parity %.3e, entropy rate %.3e of %.3e" % (e, dens.sum(), np.abs(dens).sum()))
     assert e < RHS_TOL
     assert abs(dens.sum()) < 1e-12 * np.abs(dens).sum()
+
+
+@pytest.mark.parametrize("which", ["tgv_N3_ranocha", "curved_N4_ducros", "curved_N4_kennedy_gruber"])
+def test_periodic_rhs_conserves(dgx, which):
+    """On a periodic mesh the quadrature sum of J du vanishes for every
+    variable: each pair flux of the volume term (exchanged between the two
+    nodes of a pair, or evaluated by both with the same argument order) and
+    each interface flux enters with opposite signs.  N = 3 and N = 4 pair
+    schemes, affine and curved elements."""
+    if which == "tgv_N3_ranocha":
+        c = W.case_c2(n=4, eq=W.EQ_EULER)
+    elif which == "curved_N4_ducros":
+        c = W.curved_periodic_case(n=3, N=4, volume_flux=W.VF_DUCROS)
+    else:
+        c = W.curved_periodic_case(n=3, N=4, volume_flux=W.VF_KENNEDY_GRUBER)
+    op = Operator(c.cfg, c.mesh)
+    s = dgx.Solver(c)
+    du = to_host(s.rhs(to_dev(c.u0)))
+    s.check()
+    s.close()
+    w = op.b.w
+    wq = np.einsum("i,j,k->kji", w, w, w).reshape(-1)
+    tot = (du * op.J[None] * wq).sum(axis=(1, 2))
+    scale = np.abs(du * op.J[None] * wq).sum(axis=(1, 2))
+    print("%s: sum J du / sum |J du| = %s" % (which, np.abs(tot) / scale))
+    assert np.all(np.abs(tot) < 1e-12 * scale)
