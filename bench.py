@@ -332,7 +332,7 @@ def c3_bytes_per_launch(nelem, nn, nvar, dim, stage_base=True):
     return nelem * nn * per_node * 8 + nelem * (8 + 2 * dim * 4)
 
 
-def c3_leg(torch, W, dgx, reps=20, order=-1):
+def c3_leg(torch, W, dgx, reps=20, order=-1, epb=0):
     """The curvilinear 24^3 N = 4 frozen 5-species Mach-3 shock case:
     back-to-back right-hand sides on the shock state (each: T(e) Newton per
     node, modal indicator, fused RHS with subcell FV in the shocked elements),
@@ -346,7 +346,10 @@ def c3_leg(torch, W, dgx, reps=20, order=-1):
     s = dgx.Solver(c)
     u = torch.from_numpy(c.u0).to("cuda")
     du = torch.empty_like(u)
-    epb, tune = dgx.dgx_autotune(s.ctx, u, reps=5)
+    if epb > 0:
+        dgx.dgx_set_launch(s.ctx, epb)   # fixed launch shape (profiling runs)
+    else:
+        epb, tune = dgx.dgx_autotune(s.ctx, u, reps=5)
     if order >= 0:
         dgx.dgx_set_launch(s.ctx, epb, order)
     _, used_order = dgx.dgx_get_launch(s.ctx)
@@ -676,6 +679,8 @@ def main():
                          "mortar meshes and dynamic AMR")
     ap.add_argument("--epb", type=int, default=0,
                     help="elements per workgroup to use instead of autotuning (profiling runs)")
+    ap.add_argument("--c3-epb", type=int, default=0,
+                    help="elements per workgroup of the curved-shock leg instead of autotuning (profiling runs)")
     ap.add_argument("--order", type=int, default=-1, choices=(-1, 0, 1, 2, 4, 5, 6),
                     help="launch form of the headline and curved-shock legs instead of the autotuner's "
                          "(0 round-robin over the XCDs, 1 XCD-contiguous, 2 work-list queue; +4 the "
@@ -780,7 +785,7 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_leg(torch, W, dgx)
     if not args.no_c3:
-        out["c3"] = c3_leg(torch, W, dgx, order=args.order)
+        out["c3"] = c3_leg(torch, W, dgx, order=args.order, epb=args.c3_epb)
         out["c4"] = c4_leg(torch, W, dgx)
     if not args.no_fluxes:
         out["fluxes"] = flux_leg(torch, W, dgx)

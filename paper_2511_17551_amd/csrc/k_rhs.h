@@ -603,6 +603,31 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
 #pragma unroll
     for (int v = 0; v < NV; ++v) dg[v] = 0.0;
     const double gm1_inv = 1.0 / (gamma - 1.0);
+    // the configured two-point volume flux F#(A, B; nbar) from node states
+    // (for the perfect-gas entropy-conservative flux see ec_pair)
+    auto volume_flux = [&](const St<DIM, MIX> &A, const St<DIM, MIX> &B, const double *nbar, double *F) {
+        if constexpr (VF == 0) {
+            if constexpr (MIX) ec_mixture_state<DIM>(A, B, nbar, P.M, F);
+        } else if constexpr (VF == 1) {
+            ducros_state<DIM, MIX>(A, B, nbar, F);
+        } else if constexpr (VF == 4) {
+            central_state<DIM, MIX>(A, B, nbar, F);
+        } else {
+            split_form_state<DIM, MIX, VF == 5 ? 2 : VF - 2>(A, B, nbar, gm1_inv, F);
+        }
+    };
+    // the perfect-gas entropy-conservative flux from the staged (rho, v, p,
+    // beta) of nodes na and nb of the element whose primitives start at esq
+    auto ec_pair = [&](const double *esq, int na, int nb, const double *nbar, double *F) {
+        double vA[DIM], vB[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            vA[c] = esq[(1 + c) * NN + na];
+            vB[c] = esq[(1 + c) * NN + nb];
+        }
+        ranocha_prims<DIM>(esq[na], vA, esq[(1 + DIM) * NN + na], esq[QB * NN + na], esq[nb], vB,
+                           esq[(1 + DIM) * NN + nb], esq[QB * NN + nb], nbar, gm1_inv, F);
+    };
     // circulant pairs (below): the own node's state and current metric row
     // stay in registers for the whole volume term (not with the entropy-
     // conservative mixture flux, whose registers would then cost a wave)
@@ -662,27 +687,12 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                             nbar[c] = CURV ? 0.5 * (sJa[c * NN + nlo] + sJa[c * NN + nhi]) : sJa[d * DIM + c];
                         double F[NV];
                         if constexpr (S::EC) {
-                            double vA[DIM], vB[DIM];
-#pragma unroll
-                            for (int c = 0; c < DIM; ++c) {
-                                vA[c] = sq[(1 + c) * NN + nlo];
-                                vB[c] = sq[(1 + c) * NN + nhi];
-                            }
-                            ranocha_prims<DIM>(sq[nlo], vA, sq[(1 + DIM) * NN + nlo], sq[QB * NN + nlo], sq[nhi], vB,
-                                               sq[(1 + DIM) * NN + nhi], sq[QB * NN + nhi], nbar, gm1_inv, F);
+                            ec_pair(sq, nlo, nhi, nbar, F);
                         } else {
                             St<DIM, MIX> A, B;
                             lds_state<DIM, MIX>(su, sq, NN, nlo, gamma, A);
                             lds_state<DIM, MIX>(su, sq, NN, nhi, gamma, B);
-                            if constexpr (VF == 0) {
-                                ec_mixture_state<DIM>(A, B, nbar, P.M, F);
-                            } else if constexpr (VF == 1) {
-                                ducros_state<DIM, MIX>(A, B, nbar, F);
-                            } else if constexpr (VF == 4) {
-                                central_state<DIM, MIX>(A, B, nbar, F);
-                            } else {
-                                split_form_state<DIM, MIX, VF == 5 ? 2 : VF - 2>(A, B, nbar, gm1_inv, F);
-                            }
+                            volume_flux(A, B, nbar, F);
                         }
                         if (j == 1) {
 #pragma unroll
@@ -734,28 +744,13 @@ __device__ __forceinline__ void rhs_chunk(const RhsParams &P, int mode, int e0) 
                     }
                     double F[NV];
                     if constexpr (S::EC) {
-                        double vA[DIM], vB[DIM];
-#pragma unroll
-                        for (int c = 0; c < DIM; ++c) {
-                            vA[c] = esq[(1 + c) * NN + na];
-                            vB[c] = esq[(1 + c) * NN + nb];
-                        }
-                        ranocha_prims<DIM>(esq[na], vA, esq[(1 + DIM) * NN + na], esq[QB * NN + na], esq[nb], vB,
-                                           esq[(1 + DIM) * NN + nb], esq[QB * NN + nb], nbar, gm1_inv, F);
+                        ec_pair(esq, na, nb, nbar, F);
                     } else {
                         St<DIM, MIX> A, B;
                         if constexpr (CIRC_K) A = own_st;
                         else lds_state<DIM, MIX>(esu, esq, NN, na, gamma, A);
                         lds_state<DIM, MIX>(esu, esq, NN, nb, gamma, B);
-                        if constexpr (VF == 0) {
-                            ec_mixture_state<DIM>(A, B, nbar, P.M, F);
-                        } else if constexpr (VF == 1) {
-                            ducros_state<DIM, MIX>(A, B, nbar, F);
-                        } else if constexpr (VF == 4) {
-                            central_state<DIM, MIX>(A, B, nbar, F);
-                        } else {
-                            split_form_state<DIM, MIX, VF == 5 ? 2 : VF - 2>(A, B, nbar, gm1_inv, F);
-                        }
+                        volume_flux(A, B, nbar, F);
                     }
 #pragma unroll
                     for (int v = 0; v < NV; ++v) ebuf[jb * NVP + v] = F[v];
