@@ -448,27 +448,23 @@ __global__ void __launch_bounds__(256) k_mortar_grad(RhsParams P, int nmort) {
     for (int w = 0; w < NW; ++w) o[(s * NW + w) * NF + q] = 0.5 * (Ws[w] + Wi[w]);
 }
 
-// The per-node T(e) solve (Appendix, Thermodynamics) of a conserved state
-// read from u ([nvar][count], species first): Newton from t (T0 when t is
-// not a positive number); a failed warm start (warm != 0) is retried from
-// T0.  Returns the iteration count, < 0 on failure; rs, rho for the caller.
+// The per-node T(e) solve (Appendix, Thermodynamics) of the conserved state
+// uo of one node (species first): Newton from t (T0 when t is not a positive
+// number); a failed warm start (warm != 0) is retried from T0.  Returns the
+// iteration count, < 0 on failure; rs, rho for the caller.
 template <int DIM>
-__device__ __forceinline__ int node_temperature(const double *__restrict__ u, size_t count, size_t i, double &t,
-                                                double T0, double tol, int maxit, const MixC &M, int warm,
-                                                double *rs, double &rho) {
+__device__ __forceinline__ int node_temperature_state(const double *uo, double &t, double T0, double tol, int maxit,
+                                                      const MixC &M, int warm, double *rs, double &rho) {
     rho = 0.0;
 #pragma unroll
     for (int s = 0; s < kNS; ++s) {
-        rs[s] = u[s * count + i];
+        rs[s] = uo[s];
         rho += rs[s];
     }
     double m2 = 0.0;
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-        const double m = u[(kNS + c) * count + i];
-        m2 = fma(m, m, m2);
-    }
-    const double rhoe = u[(kNS + DIM) * count + i] - 0.5 * m2 / rho;
+    for (int c = 0; c < DIM; ++c) m2 = fma(uo[kNS + c], uo[kNS + c], m2);
+    const double rhoe = uo[kNS + DIM] - 0.5 * m2 / rho;
     if (!(t > 0.0) || !isfinite(t)) t = T0;
     int it = mix_newton(M, rs, rhoe, t, tol, maxit);
     if (warm && (it < 0 || !isfinite(t) || !(t > 0.0))) {
@@ -476,6 +472,17 @@ __device__ __forceinline__ int node_temperature(const double *__restrict__ u, si
         it = mix_newton(M, rs, rhoe, t, tol, maxit);
     }
     return (it < 0 || !isfinite(t) || !(t > 0.0)) ? -1 : it;
+}
+
+// The same for node i of u ([nvar][count]).
+template <int DIM>
+__device__ __forceinline__ int node_temperature(const double *__restrict__ u, size_t count, size_t i, double &t,
+                                                double T0, double tol, int maxit, const MixC &M, int warm,
+                                                double *rs, double &rho) {
+    double uo[kNS + DIM + 1];
+#pragma unroll
+    for (int v = 0; v < kNS + DIM + 1; ++v) uo[v] = u[v * count + i];
+    return node_temperature_state<DIM>(uo, t, T0, tol, maxit, M, warm, rs, rho);
 }
 
 // Per-node T(e) Newton (Appendix, Thermodynamics).  Tguess may be null
@@ -537,6 +544,9 @@ __global__ void __launch_bounds__(512) k_indicator(RhsParams P, int ind_var, dou
     const size_t stride = (size_t)P.nelem * NN;
     const size_t gi = (size_t)(valid ? e : 0) * NN + node;
     if (valid) {
+        double uo[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uo[v] = P.u[v * stride + gi];
         double Tn = 0.0;
         if constexpr (MIX) {
             Tn = P.T[gi];
@@ -544,15 +554,12 @@ __global__ void __launch_bounds__(512) k_indicator(RhsParams P, int ind_var, dou
                 // the right-hand side's T(e) solve, fused (the same steps as
                 // k_thermo with a warm start): T and the frozen sound speed
                 double rs[kNS], rho;
-                const int it = node_temperature<DIM>(P.u, stride, gi, Tn, T0, tol, maxit, P.M, 1, rs, rho);
+                const int it = node_temperature_state<DIM>(uo, Tn, T0, tol, maxit, P.M, 1, rs, rho);
                 Tw[gi] = Tn;
                 cw[gi] = mix_sound(P.M, rs, rho, Tn);
                 if (it < 0) atomicOr(P.flags, FLAG_NOCONV);
             }
         }
-        double uo[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) uo[v] = P.u[v * stride + gi];
         St<DIM, MIX> s;
         make_state<DIM, MIX>(uo, Tn, P.gamma, P.M, s);
         x[node] = ind_var == 1 ? s.p : s.rho * s.p;
