@@ -6,6 +6,7 @@
 #include <climits>
 #include <map>
 #include <mutex>
+#include <new>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -244,6 +245,19 @@ int set_err(dgx_ctx *ctx, int code, const std::string &msg) {
 int set_err_fixed(dgx_ctx *ctx, int code, const char *msg) {
     if (ctx) ctx->err_fixed = msg;
     return code;
+}
+
+// Runs f() and turns a C++ exception (a failed host allocation or thread
+// start) into an error code, so that none leaves the C ABI.
+template <typename F>
+int guarded(dgx_ctx *ctx, F &&f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return set_err_fixed(ctx, DGX_E_NOMEM, "host memory allocation failed");
+    } catch (...) {
+        return set_err_fixed(ctx, DGX_E_NOMEM, "host resources exhausted (memory or threads)");
+    }
 }
 
 template <typename T>
@@ -539,7 +553,7 @@ int check_ctx(dgx_ctx *ctx) {
 // ======================================================================= ABI
 extern "C" {
 
-int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
+static int create_body(const dgx_config *cfg, dgx_ctx **out) {
     if (!cfg || !out) return DGX_E_INVAL;
     *out = nullptr;
     if ((cfg->dim != 2 && cfg->dim != 3) || (cfg->N != 3 && cfg->N != 4)) return DGX_E_INVAL;
@@ -646,7 +660,11 @@ int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
     return DGX_OK;
 }
 
-int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
+int dgx_create(const dgx_config *cfg, dgx_ctx **out) {
+    return guarded(nullptr, [&] { return create_body(cfg, out); });
+}
+
+static int set_mesh_body(dgx_ctx *ctx, const dgx_mesh *m) {
     if (!ctx || !m || !m->x || m->nelem <= 0) return set_err(ctx, DGX_E_INVAL, "bad mesh");
     const int dim = ctx->cfg.dim, N = ctx->cfg.N, n1 = ctx->N1, nn = ctx->nn, E = m->nelem;
     const int nv = ctx->nvar;
@@ -918,6 +936,10 @@ int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
     ctx->oct_new.clear();
     ctx->oct_tab.clear();
     return DGX_OK;
+}
+
+int dgx_set_mesh(dgx_ctx *ctx, const dgx_mesh *m) {
+    return guarded(ctx, [&] { return set_mesh_body(ctx, m); });
 }
 
 int dgx_rhs(dgx_ctx *ctx, const double *u, double t, double *du, void *stream) {
@@ -1606,7 +1628,7 @@ int amr_ops_upload(dgx_ctx *ctx) {
 
 extern "C" {
 
-int dgx_set_octree(dgx_ctx *ctx, int base, int nleaf, const int32_t *leaves) {
+static int set_octree_body(dgx_ctx *ctx, int base, int nleaf, const int32_t *leaves) {
     if (!ctx || nleaf <= 0 || !leaves) return set_err(ctx, DGX_E_INVAL, "bad octree");
     if (ctx->cfg.dim != 3 || ctx->cfg.equation >= DGX_EQ_EULER_MIX)
         return set_err(ctx, DGX_E_INVAL, "octree meshes are built for the 3D perfect-gas equations");
@@ -1624,6 +1646,10 @@ int dgx_set_octree(dgx_ctx *ctx, int base, int nleaf, const int32_t *leaves) {
     ctx->oct_new.clear();
     ctx->oct_tab.clear();
     return DGX_OK;
+}
+
+int dgx_set_octree(dgx_ctx *ctx, int base, int nleaf, const int32_t *leaves) {
+    return guarded(ctx, [&] { return set_octree_body(ctx, base, nleaf, leaves); });
 }
 
 int dgx_get_octree(const dgx_ctx *ctx, int32_t *leaves_out, int nmax) {
@@ -1658,7 +1684,7 @@ int dgx_amr_indicator(dgx_ctx *ctx, const double *u, int kind, int variable, dou
     return DGX_OK;
 }
 
-int dgx_amr_plan(dgx_ctx *ctx, const double *ind, const dgx_amr_controller *c, int *nelem_new) {
+static int amr_plan_body(dgx_ctx *ctx, const double *ind, const dgx_amr_controller *c, int *nelem_new) {
     if (!ctx || !ind || !c || !nelem_new) return set_err(ctx, DGX_E_INVAL, "null argument");
     if (ctx->oct.empty()) return set_err(ctx, DGX_E_STATE, "no octree mesh");
     if (c->base_level < 0 || c->med_level < c->base_level || c->max_level < c->med_level ||
@@ -1682,7 +1708,11 @@ int dgx_amr_plan(dgx_ctx *ctx, const double *ind, const dgx_amr_controller *c, i
     return DGX_OK;
 }
 
-int dgx_amr_apply(dgx_ctx *ctx, const double *u_old, double *u_new, void *stream) {
+int dgx_amr_plan(dgx_ctx *ctx, const double *ind, const dgx_amr_controller *c, int *nelem_new) {
+    return guarded(ctx, [&] { return amr_plan_body(ctx, ind, c, nelem_new); });
+}
+
+static int amr_apply_body(dgx_ctx *ctx, const double *u_old, double *u_new, void *stream) {
     if (!ctx || !u_old || !u_new) return set_err(ctx, DGX_E_INVAL, "null argument");
     if (ctx->oct_new.empty()) return set_err(ctx, DGX_E_STATE, "no pending adaptation");
     if (u_old == u_new) return set_err(ctx, DGX_E_INVAL, "u_old and u_new must not alias");
@@ -1708,6 +1738,10 @@ int dgx_amr_apply(dgx_ctx *ctx, const double *u_old, double *u_new, void *stream
     if ((rc = oct_upload(ctx, ctx->oct_base, nv))) return rc;
     ctx->oct = std::move(nv);
     return DGX_OK;
+}
+
+int dgx_amr_apply(dgx_ctx *ctx, const double *u_old, double *u_new, void *stream) {
+    return guarded(ctx, [&] { return amr_apply_body(ctx, u_old, u_new, stream); });
 }
 
 const char *dgx_last_error(const dgx_ctx *ctx) {
