@@ -133,9 +133,11 @@ def test_far_from_equilibrium_states(dgx, thermo_fns, dt):
     budget or not depending on rounding (the GPU's Jacobian is analytic, the
     oracle's a central difference), so the two may take different substep
     sequences at such a node; both results are valid backward-Euler
-    integrations.  At most 2 of the 2048 nodes may differ that way: they
-    must keep mass, atoms and positivity exactly and agree to the substeps'
-    truncation error (1e-3 rho); every other node agrees to 1e-11 rho."""
+    integrations.  At most 2 of the 2048 nodes may differ that way, each one
+    whose integration needed substeps: they must keep mass, atoms and
+    positivity exactly and agree to 1e-4 rho, well inside the substeps'
+    truncation error (measured: one such node, at dt = 1e-7, 9 substeps,
+    5.5e-6 rho); every other node agrees to 1e-11 rho."""
     c = frozen_case(thermo_fns, 8, 16)
     nvar, nelem, nn = c.u0.shape
     rs, T = W.far_chem_states(nelem * nn, seed=11)
@@ -153,6 +155,8 @@ def test_far_from_equilibrium_states(dgx, thermo_fns, dt):
     rho = u0[:5].sum(0)
     err = (np.abs(got[:5] - ref[:5]) / rho[None]).max(0).reshape(-1)
     other = np.flatnonzero(err > 1e-11)
+    print("far dt %.0e: nodes above 1e-11 %s: oracle substeps %s, Newton iterations %s" % (
+        dt, other, nsub.reshape(-1)[other], np.asarray(it).reshape(-1)[other]))
     print("far dt %.0e: max |drho_s|/rho %.3e (%d nodes above 1e-11: %s), substeps gpu total %d max %d, "
           "oracle total %d max %d, multi %d" % (dt, np.delete(err, other).max(), other.size, err[other],
                                                 st["substeps_total"], st["substeps_max"], nsub.sum(), nsub.max(),
@@ -160,11 +164,12 @@ def test_far_from_equilibrium_states(dgx, thermo_fns, dt):
     assert st["nonconverged"] == 0
     assert (nsub > 1).sum() > 10
     assert other.size <= 2
+    assert np.all(nsub.reshape(-1)[other] > 1)
     assert abs(st["substeps_total"] - nsub.sum()) <= 32 * other.size
     if other.size == 0:
         assert st["substeps_max"] == nsub.max()
     assert np.delete(err, other).max() < 1e-11
-    assert np.all(err[other] < 1e-3)
+    assert np.all(err[other] < 1e-4)
     assert np.array_equal(got[5:], u0[5:])
     assert np.all(got[:5] >= 0.0)
     g, r0 = got[:5].reshape(5, -1), u0[:5].reshape(5, -1)
